@@ -1,0 +1,461 @@
+"""Pins of the oracle to facts fixed outside it.
+
+Each ``pin_*`` function takes a loaded oracle library (``oracle.load(path)``) and
+raises AssertionError when the oracle disagrees with something the paper or the
+mathematics fixes:
+
+  * hand-worked examples (tests/golden/*.txt, each with its derivation);
+  * FP64 shortest paths from SciPy's Dijkstra (pruning off: every reachable vertex;
+    pruning on: the goal and every vertex the promising-set argument covers);
+  * brute force over all simple paths on graphs of at most 9 vertices;
+  * exact integer hop distances on unit-cost lattices;
+  * the direct edge on complete obstacle-free graphs (triangle inequality);
+  * the left fold of FP32 additions along each root path (closed form of Evaluate);
+  * invariants: rooted acyclic tree, g(v) = g(parent) + c bitwise, pcost is a real
+    edge, Bellman's inequality over the final Improve domain, monotone g across
+    iterations, insertion-time local optimality, correctness from any initial
+    policy (Sec. V), error returns.
+
+The same functions run against copies of the oracle with planted mistakes
+(test_oracle_mutants.py) to show that each plausible slip is caught.
+"""
+from __future__ import annotations
+
+import glob
+import itertools
+import math
+import os
+from collections import deque
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.csgraph import dijkstra
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REL = 1e-5  # relative tolerance against FP64 shortest paths
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+
+def load_fixture(path):
+    fx = {"edges": [], "prune": 1, "h": None}
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *rest = line.split()
+            if key == "edge":
+                fx["edges"].append((int(rest[0]), int(rest[1]), float(rest[2])))
+            elif key in ("n", "root", "goal", "prune"):
+                fx[key] = int(rest[0])
+            elif key in ("h", "insert_g", "expect_g"):
+                fx[key] = np.array([float(x) for x in rest], np.float32)
+            elif key in ("insert_parent", "expect_parent"):
+                fx[key] = np.array([int(x) for x in rest], np.int32)
+            elif key == "expect_stats":
+                fx[key] = {k: int(v) for k, v in (kv.split("=") for kv in rest)}
+            else:
+                raise ValueError("unknown fixture key %r in %s" % (key, path))
+    return fx
+
+
+def fixtures():
+    return sorted(glob.glob(os.path.join(GOLDEN, "*.txt")))
+
+
+def build_graph(lib, batches):
+    G = O.Graph(lib)
+    for b in batches:
+        rc = G.insert_batch(b)
+        assert rc == 0, "insert rc=%d" % rc
+    return G
+
+
+def sparse_of(G):
+    ptr, nbr, cst = G.adjacency()
+    n = G.n
+    return sp.csr_matrix((cst.astype(np.float64), nbr, ptr), shape=(n, n))
+
+
+def fp64_dist(G, root):
+    # SciPy's Dijkstra keeps the smallest of parallel entries; explicit zeros
+    # are dropped by csr -> use a tiny positive stand-in is not needed because
+    # generator costs are > 0.
+    return dijkstra(sparse_of(G), directed=False, indices=root)
+
+
+def assert_close_fp64(g, d, mask, what):
+    g64 = g.astype(np.float64)
+    both = mask & np.isfinite(d)
+    rel = np.abs(g64[both] - d[both]) / np.maximum(np.abs(d[both]), 1e-30)
+    assert rel.size == 0 or rel.max() <= REL, "%s: max rel err %.3g" % (what, rel.max())
+
+
+def fold_root_path(parent, pcost, root):
+    """Closed form of Evaluate: g(v) is the left fold, in binary32, of the
+    parent-edge costs along the root path of v (+inf if the chain misses root)."""
+    n = len(parent)
+    out = np.full(n, np.inf, np.float32)
+    for v in range(n):
+        path = []
+        u = v
+        seen = 0
+        while u != root and u >= 0 and seen <= n:
+            path.append(u)
+            u = int(parent[u])
+            seen += 1
+        if u != root:
+            continue
+        acc = np.float32(0.0)
+        for w in reversed(path):
+            acc = np.float32(acc + pcost[w])
+        out[v] = acc
+    return out
+
+
+def check_invariants(G, root, goal, h, prune):
+    st = G.state()
+    g, parent, pcost = st.g, st.parent, st.pcost
+    n = G.n
+    ptr, nbr, cst = G.adjacency()
+    assert parent[root] == -1 and g[root] == 0.0
+    # rooted, acyclic, consistent: the closed form reproduces g bit for bit
+    fold = fold_root_path(parent, pcost, root)
+    assert np.array_equal(fold.view(np.uint32), g.view(np.uint32)), "g is not the root-path fold"
+    # each reachable vertex's parent edge exists with that exact cost
+    for v in np.nonzero(np.isfinite(g))[0]:
+        if v == root:
+            continue
+        p = parent[v]
+        row = slice(ptr[v], ptr[v + 1])
+        hits = (nbr[row] == p) & (cst[row].view(np.uint32) == np.float32(pcost[v]).view(np.uint32))
+        assert hits.any(), "pcost of %d is not the cost of an edge to its parent" % v
+    # Bellman at the fixed point over the final Improve domain
+    thr = g[goal] if prune else np.float32(np.inf)
+    hh = np.zeros(n, np.float32) if h is None else np.asarray(h, np.float32)
+    f = (g + hh).astype(np.float32)
+    P = f < thr
+    D = P.copy()
+    src = np.repeat(np.arange(n), np.diff(ptr))
+    D[nbr[P[src]]] = True
+    D[root] = False
+    cand = (g[nbr] + cst).astype(np.float32)  # binary32 adds, elementwise
+    bad = D[src] & (cand < g[src])
+    assert not bad.any(), "Bellman inequality violated at %d vertices" % int(bad.sum())
+
+
+# ----------------------------------------------------------------------------
+# pins (cheap first: the mutant test stops at the first failure)
+# ----------------------------------------------------------------------------
+
+def pin_golden(lib):
+    for path in fixtures():
+        fx = load_fixture(path)
+        G = build_graph(lib, [W.from_edges(fx["n"], fx["edges"])])
+        st = G.state()
+        name = os.path.basename(path)
+        assert np.array_equal(st.g, fx["insert_g"]), "%s: insertion g %s" % (name, st.g)
+        assert np.array_equal(st.parent, fx["insert_parent"]), "%s: insertion parent %s" % (name, st.parent)
+        rc, stats = G.replan(fx["root"], fx["goal"], fx["h"], bool(fx["prune"]))
+        assert rc == 0
+        st = G.state()
+        assert np.array_equal(st.g, fx["expect_g"]), "%s: g %s" % (name, st.g)
+        assert np.array_equal(st.parent, fx["expect_parent"]), "%s: parent %s" % (name, st.parent)
+        for k, v in fx["expect_stats"].items():
+            assert stats[k] == v, "%s: %s=%d, expected %d" % (name, k, stats[k], v)
+
+
+def pin_path_fold(lib):
+    rng = np.random.default_rng(7)
+    n = 200
+    costs = rng.uniform(0.01, 1.0, n - 1).astype(np.float32)
+    G = build_graph(lib, [W.path_graph(n, costs)])
+    # insertion already gives the fold; Replan keeps it
+    rc, stats = G.replan(0, n - 1, None, False)
+    assert rc == 0 and stats["iterations"] == 1
+    acc = np.float32(0.0)
+    want = [acc]
+    for c in costs:
+        acc = np.float32(acc + c)
+        want.append(acc)
+    want = np.array(want, np.float32)
+    assert np.array_equal(G.state().g.view(np.uint32), want.view(np.uint32))
+    # the same path with reversed labels: every vertex but 0 starts as an orphan
+    # except along the chain, and Replan must rebuild the fold from the root 0.
+    rev = n - 1 - np.arange(n)  # new label of old vertex i
+    edges = [(int(rev[i]), int(rev[i + 1]), float(costs[i])) for i in range(n - 1)]
+    G2 = build_graph(lib, [W.from_edges(n, edges)])
+    root = int(rev[0])
+    rc, _ = G2.replan(root, int(rev[n - 1]), None, False)
+    assert rc == 0
+    g2 = G2.state().g
+    assert np.array_equal(g2[rev].view(np.uint32), want.view(np.uint32))
+
+
+def pin_bruteforce_small(lib):
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        n = int(rng.integers(2, 10))
+        edges = []
+        for a in range(n):
+            for b in range(a + 1, n):
+                if rng.random() < 0.45:
+                    edges.append((a, b, float(np.float32(rng.uniform(0.1, 2.0)))))
+        adj = {v: [] for v in range(n)}
+        for a, b, c in edges:
+            adj[a].append((b, c))
+            adj[b].append((a, c))
+
+        def best_from(root):
+            best = [math.inf] * n
+            best[root] = 0.0
+
+            def dfs(u, acc, seen):
+                for w, c in adj[u]:
+                    if w in seen:
+                        continue
+                    t = acc + c
+                    if t < best[w]:
+                        best[w] = t
+                    dfs(w, t, seen | {w})
+            dfs(root, 0.0, {root})
+            return np.array(best)
+
+        dist = [best_from(v) for v in range(n)]
+        for root in range(n):
+            d = dist[root]
+            for goal in range(n):
+                if goal == root:
+                    continue
+                dg = dist[goal]
+                # admissible heuristic: half the true cost-to-go (0 where unreachable)
+                h_half = np.where(np.isfinite(dg), 0.5 * dg, 0.0).astype(np.float32)
+                for h in (None, h_half):
+                    for prune in (False, True):
+                        G2 = build_graph(lib, [W.from_edges(n, edges)])
+                        rc, _ = G2.replan(root, goal, h, prune)
+                        assert rc == 0
+                        g = G2.state().g
+                        if not prune:
+                            assert (np.isfinite(g) == np.isfinite(d)).all(), "reachable set differs"
+                            assert_close_fp64(g, d, np.ones(n, bool), "bruteforce n=%d" % n)
+                        elif np.isfinite(d[goal]):
+                            assert_close_fp64(g, d, np.arange(n) == goal, "bruteforce goal")
+                        else:
+                            assert not np.isfinite(g[goal])
+
+
+def pin_lattice(lib):
+    rng = np.random.default_rng(3)
+    side = 14
+    keep = rng.random((side, side)) > 0.15
+    keep[0, 0] = keep[side - 1, side - 1] = True
+    cells = [(i, j) for i in range(side) for j in range(side) if keep[i, j]]
+    perm = rng.permutation(len(cells))
+    # the root keeps label 0 so that insertion sees it first; the rest are shuffled
+    start = cells.index((0, 0))
+    order = [start] + [k for k in perm if k != start]
+    label = {cells[k]: i for i, k in enumerate(order)}
+    edges = []
+    for (i, j) in cells:
+        for (a, b) in ((i + 1, j), (i, j + 1)):
+            if (a, b) in label:
+                edges.append((label[(i, j)], label[(a, b)], 1.0))
+    n = len(cells)
+    G = build_graph(lib, [W.from_edges(n, edges)])
+    goal = label[(side - 1, side - 1)]
+    rc, _ = G.replan(0, goal, None, False)
+    assert rc == 0
+    # plain BFS hop distances
+    adj = [[] for _ in range(n)]
+    for a, b, _ in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+    hop = np.full(n, np.inf)
+    hop[0] = 0
+    q = deque([0])
+    while q:
+        u = q.popleft()
+        for w in adj[u]:
+            if hop[w] == np.inf:
+                hop[w] = hop[u] + 1
+                q.append(w)
+    assert np.array_equal(G.state().g, hop.astype(np.float32)), "lattice hop distances differ"
+
+
+def pin_complete_graph(lib):
+    rng = np.random.default_rng(5)
+    n = 48
+    pts = rng.random((n, 2))
+    edges = []
+    c = np.zeros((n, n), np.float32)
+    for a in range(n):
+        for b in range(a + 1, n):
+            c[a, b] = c[b, a] = np.float32(np.sqrt(((pts[a] - pts[b]) ** 2).sum()))
+            edges.append((a, b, float(c[a, b])))
+    G = build_graph(lib, [W.from_edges(n, edges)])
+    rc, _ = G.replan(0, 1, None, False)
+    assert rc == 0
+    st = G.state()
+    # a two-hop route can only beat the direct edge through FP32 rounding
+    for v in range(1, n):
+        two = min(np.float32(c[0, u] + c[u, v]) for u in range(1, n) if u != v)
+        if two > c[0, v]:
+            assert st.g[v] == c[0, v] and st.parent[v] == 0, "vertex %d" % v
+        else:
+            assert st.g[v] <= c[0, v]
+
+
+def pin_dijkstra(lib):
+    wl = W.plain_2d(samples=600, seed=0)
+    for root, goal in ((0, 1), (1, 0), (5, 17)):
+        G = build_graph(lib, wl.batches)
+        rc, _ = G.replan(root, goal, None, False)
+        assert rc == 0
+        d = fp64_dist(G, root)
+        g = G.state().g
+        assert (np.isfinite(g) == np.isfinite(d)).all(), "reachable set differs"
+        assert_close_fp64(g, d, np.ones(G.n, bool), "2D root %d" % root)
+    wl6 = W.batched_6d(batches=4, batch=300, seed=100)
+    G = O.Graph(lib)
+    for b in wl6.batches:
+        assert G.insert_batch(b) == 0
+        rc, _ = G.replan(0, 1, None, False)
+        assert rc == 0
+        d = fp64_dist(G, 0)
+        g = G.state().g
+        assert (np.isfinite(g) == np.isfinite(d)).all()
+        assert_close_fp64(g, d, np.ones(G.n, bool), "6D n=%d" % G.n)
+
+
+def pin_pruned_exactness(lib):
+    """With an admissible, consistent h and pruning on: g(goal) is optimal, and so
+    is g(v) for every v with d(v) + h(v) < d(goal) (margin 1e-4 for rounding)."""
+    for wl in (W.plain_2d(samples=800, seed=0), W.batched_6d(batches=3, batch=400, seed=100)):
+        G = O.Graph(lib)
+        for b in wl.batches:
+            assert G.insert_batch(b) == 0
+            h = wl.heuristic(G.n)
+            rc, _ = G.replan(0, 1, h, True)
+            assert rc == 0
+            d = fp64_dist(G, 0)
+            g = G.state().g
+            if np.isfinite(d[1]):
+                mask = (np.arange(G.n) == 1) | (d + h.astype(np.float64) < d[1] * (1 - 1e-4))
+                assert_close_fp64(g, d, mask, "%s pruned" % wl.name)
+            check_invariants(G, 0, 1, h, True)
+
+
+def pin_invariants(lib):
+    wl = W.plain_2d(samples=1000, seed=0)
+    for prune in (True, False):
+        G = build_graph(lib, wl.batches)
+        h = wl.heuristic()
+        rc, _ = G.replan(0, 1, h, prune)
+        assert rc == 0
+        check_invariants(G, 0, 1, h, prune)
+
+
+def pin_insertion_local(lib):
+    """Extend's local relaxation: each new vertex's (g, parent) is the smallest
+    (g(u) + c, u) over its lower-index neighbours, or an orphan if none is finite."""
+    wl = W.batched_6d(batches=3, batch=300, seed=100)
+    G = O.Graph(lib)
+    for b in wl.batches:
+        assert G.insert_batch(b) == 0
+        st = G.state()
+        for i in range(b.n_new):
+            v = b.n_old + i
+            if v == 0:
+                assert st.g[0] == 0 and st.parent[0] == -1
+                continue
+            cols = b.col[b.row_ptr[i]:b.row_ptr[i + 1]]
+            cs = b.cost[b.row_ptr[i]:b.row_ptr[i + 1]]
+            cands = sorted((float(np.float32(st.g[u] + c)), int(u)) for u, c in zip(cols, cs))
+            finite = [x for x in cands if math.isfinite(x[0])]
+            if not finite:
+                assert st.parent[v] == -1 and np.isinf(st.g[v])
+            else:
+                assert (float(st.g[v]), int(st.parent[v])) == finite[0], "vertex %d" % v
+        rc, _ = G.replan(0, 1, wl.heuristic(G.n), True)
+        assert rc == 0
+
+
+def pin_any_initial_policy(lib):
+    """Sec. V: Replan over the whole graph recovers the optimum from any initial
+    policy: one batch, many batches, and an all-orphan start agree with FP64."""
+    wl = W.plain_2d(samples=700, seed=0)
+    whole = build_graph(lib, wl.batches)
+    d = fp64_dist(whole, 0)
+    pts = wl.points
+    # the same graph split into 7 batches
+    edges = []
+    b = wl.batches[0]
+    for i in range(b.n_new):
+        for j in range(b.row_ptr[i], b.row_ptr[i + 1]):
+            edges.append((i, int(b.col[j]), float(b.cost[j])))
+    cuts = [0, 2, 100, 200, 300, 400, 500, len(pts)]
+    G = O.Graph(lib)
+    for a, z in zip(cuts[:-1], cuts[1:]):
+        assert G.insert_batch(W.from_edges(z, [e for e in edges if a <= max(e[0], e[1]) < z], n_old=a)) == 0
+    rc, _ = G.replan(0, 1, None, False)
+    assert rc == 0
+    assert (np.isfinite(G.state().g) == np.isfinite(d)).all()
+    assert_close_fp64(G.state().g, d, np.ones(G.n, bool), "7 batches")
+    # all orphans
+    G3 = build_graph(lib, wl.batches)
+    n = G3.n
+    assert G3.set_state(np.full(n, np.inf, np.float32), np.full(n, -1, np.int32), np.zeros(n, np.float32)) == 0
+    rc, _ = G3.replan(0, 1, None, False)
+    assert rc == 0
+    assert_close_fp64(G3.state().g, d, np.ones(n, bool), "all orphans")
+
+
+def pin_monotone(lib):
+    """g never increases from one policy-iteration step to the next, and the
+    iteration cap returns ENOTCONVERGED with a consistent state."""
+    wl = W.plain_2d(samples=600, seed=0)
+    base = build_graph(lib, wl.batches)
+    st0 = base.state()
+    h = wl.heuristic()
+    rc, full = base.replan(0, 1, h, True)
+    assert rc == 0
+    total = full["iterations"]
+    prev = None
+    for k in range(1, total + 1):
+        G = build_graph(lib, wl.batches)
+        assert G.set_state(st0.g, st0.parent, st0.pcost) == 0
+        rc, stats = G.replan(0, 1, h, True, max_iters=k)
+        if k < total:
+            assert rc == O.ENOTCONVERGED and stats["iterations"] == k, (k, rc, stats)
+        else:
+            assert rc == 0
+        g = G.state().g
+        fold = fold_root_path(G.state().parent, G.state().pcost, 0)
+        assert np.array_equal(fold.view(np.uint32), g.view(np.uint32))
+        if prev is not None:
+            assert (g <= prev).all(), "g increased at step %d" % k
+        prev = g
+
+
+def pin_errors(lib):
+    G = O.Graph(lib)
+    assert G.insert(np.array([0, 1], np.int64), np.array([0], np.int32), np.array([1.0], np.float32)) == O.EINVAL
+    assert G.n == 0
+    assert G.insert(np.array([0, 0, 1], np.int64), np.array([0], np.int32), np.array([np.nan], np.float32)) == O.EINVAL
+    assert G.insert(np.array([0, 0, 1], np.int64), np.array([0], np.int32), np.array([-1.0], np.float32)) == O.EINVAL
+    assert G.insert(np.array([0, 0, 1], np.int64), np.array([0], np.int32), np.array([1.0], np.float32)) == 0
+    assert G.replan(2, 0)[0] == O.EINVAL
+    assert G.replan(0, 1, np.array([0.0, np.nan], np.float32))[0] == O.EINVAL
+    assert G.replan(0, 1, np.array([0.0, -1.0], np.float32))[0] == O.EINVAL
+
+
+PINS = [pin_golden, pin_path_fold, pin_errors, pin_lattice, pin_complete_graph, pin_insertion_local,
+        pin_monotone, pin_invariants, pin_dijkstra, pin_pruned_exactness, pin_any_initial_policy,
+        pin_bruteforce_small]
