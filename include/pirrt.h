@@ -1,0 +1,172 @@
+/*
+ * pirrt.h -- C ABI of the MI355X (gfx950) implementation of PI-RRT#'s exploitation
+ * phase ("Replan": policy evaluation and policy improvement to a fixed point over the
+ * random geometric graph that exploration grows), after "GPU Parallelization of
+ * Policy Iteration RRT#" (arXiv 2003.04920).
+ *
+ * Problem statement (Sec. III): a graph G = (V, E) with a cached, symmetric edge cost
+ * c : E -> R+ (Sec. IV-A: the only edge property, computed once by Extend), a policy
+ * pi : V -> E giving each vertex a parent, the cost-to-come g under that policy, an
+ * admissible heuristic h, and the promising set B = { v : g(v) + h(v) < g(x_goal) }.
+ * Replan (Alg. 2) alternates Improve (each vertex of the domain takes the neighbour
+ * minimising g(n) + c(n, v)) and Evaluate (a breadth-first walk of the policy tree
+ * from x_init recomputing g) until no parent changes.
+ *
+ * Conventions shared by every entry point:
+ *   - Vertices are 0 .. n-1 in insertion order.  Vertex 0 is x_init for the
+ *     insertion-time policy (it gets g = 0); x_goal is any vertex (vertex 1 by the
+ *     usual construction of Alg. 1, which starts from V = {x_init, x_goal}).
+ *   - Costs and g are IEEE-754 binary32; every g is one binary32 addition
+ *     (round to nearest even) of the parent's g and the parent-edge cost, in
+ *     root-to-leaf order.  Unreachable vertices have g = +inf.
+ *   - Ties in any minimum go to the lowest neighbour index; Improve switches a
+ *     parent only on a strict decrease (Alg. 2's strict comparison).
+ *   - mem_kind says where caller buffers live: PIRRT_MEM_HOST (pageable or pinned
+ *     host memory) or PIRRT_MEM_DEVICE (device memory on the graph's device).
+ *     Inputs are copied before the call returns; the library never keeps caller
+ *     pointers.
+ *   - Every entry point returns PIRRT_OK (0) or a negative error code; no exception
+ *     crosses the ABI.  Arguments are validated before any state changes, so on
+ *     PIRRT_EINVAL the graph is unchanged.  After PIRRT_EDEVICE (a HIP runtime error)
+ *     the handle is poisoned: every later call except destroy returns PIRRT_EDEVICE.
+ *     pirrt_last_error gives a message for the last failure on a handle.
+ *   - A handle is not thread safe: use one handle per host thread (or serialise).
+ *     All device work of a handle is enqueued on the stream named in its config and
+ *     every entry point returns only after its results are complete.
+ */
+#ifndef PIRRT_H
+#define PIRRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PIRRT_OK = 0,
+  PIRRT_EINVAL = -1,        /* bad argument; state unchanged */
+  PIRRT_ENOMEM = -2,        /* device or host allocation failed; state unchanged */
+  PIRRT_EDEVICE = -3,       /* HIP runtime error; handle poisoned */
+  PIRRT_ENOTCONVERGED = -4  /* iteration cap reached; policy and g are consistent */
+};
+
+enum { PIRRT_MEM_HOST = 0, PIRRT_MEM_DEVICE = 1 };
+
+/* Replan flags. */
+enum {
+  PIRRT_NO_PRUNE = 1u << 0, /* threshold G = +inf instead of g(goal): every reachable
+                               vertex is promising */
+  PIRRT_TIMING = 1u << 1    /* time each phase with HIP events (fills the ms_* and
+                               per-kernel fields of pirrt_stats; adds event overhead) */
+};
+
+typedef struct pirrt_graph pirrt_graph;
+
+typedef struct {
+  int64_t vertex_capacity; /* initial reservation in vertices (0 = library default);
+                              storage grows on demand */
+  int64_t edge_capacity;   /* initial reservation in directed adjacency entries */
+  void* hip_stream;        /* hipStream_t for all device work; NULL = the null stream */
+  int32_t max_iters;       /* Replan iteration cap; 0 = 4n + 8 */
+  int32_t device;          /* HIP device ordinal; -1 = the device current at create */
+} pirrt_config;
+
+typedef struct {
+  int32_t iterations;     /* Improve passes, including the last one with no change */
+  int32_t eval_levels;    /* tree levels visited by the last Evaluate */
+  int64_t edges_examined; /* sum over iterations of the degrees of the Improve domain */
+  int64_t sum_P;          /* sum over iterations of |promising set| */
+  int64_t sum_D;          /* sum over iterations of |Improve domain| */
+  int64_t changed_total;  /* sum over iterations of parents switched */
+  /* wall time of the call and, with PIRRT_TIMING, of its phases (milliseconds) */
+  double ms_total;
+  double ms_evaluate;
+  double ms_mark;
+  double ms_improve;
+  int32_t improve_launches; /* launches of the Improve kernel timed in ms_improve */
+  int32_t mark_launches;
+  int32_t evaluate_calls;
+  int32_t reserved;
+} pirrt_stats;
+
+/* Fills *cfg with defaults (capacities 0, NULL stream, cap 0, device -1). */
+int pirrt_config_init(pirrt_config* cfg);
+
+/* Creates an empty graph (no vertices) on the configured device.  cfg may be NULL
+   (defaults).  *out receives the handle, owned by the caller until destroy. */
+int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg);
+
+/* Releases the handle and all its device memory.  NULL is allowed. */
+int pirrt_graph_destroy(pirrt_graph* g);
+
+/*
+ * Extend for a batch (Sec. III; Alg. 1 with S = 1, Alg. 3 with batch size S):
+ * appends n_new vertices with ids n_old .. n_old + n_new - 1 (n_old = current
+ * count).  Row i (entries row_ptr[i] .. row_ptr[i+1]-1 of col/cost) lists the
+ * neighbours j of vertex n_old + i with j < n_old + i, each undirected edge given
+ * once from its higher endpoint, with its cached cost c (Sec. IV-A).
+ *   row_ptr : int64[n_new + 1], row_ptr[0] == 0, non-decreasing.
+ *   col     : int32[row_ptr[n_new]], 0 <= col < own id.  Repeated entries are kept
+ *             as parallel edges.
+ *   cost    : float[row_ptr[n_new]], finite and >= 0.
+ * The library stores each edge in both endpoints' adjacency, then sets the
+ * insertion-time policy of each new vertex in ascending id order (Extend's local
+ * relaxation): (g, parent) = the smallest (g(u) + c, u) over its neighbours u below
+ * it, or an orphan (g = +inf, parent = -1) if none is finite; vertex 0 gets g = 0.
+ * Errors: EINVAL (n_new < 0, bad row_ptr/col/cost, ids beyond INT32_MAX), ENOMEM,
+ * EDEVICE.
+ */
+int pirrt_insert_batch(pirrt_graph* g, int32_t n_new, const int64_t* row_ptr, const int32_t* col,
+                       const float* cost, int mem_kind);
+
+/*
+ * Replan (Alg. 2) from the stored policy to its fixed point, with root = x_init and
+ * goal = x_goal.  Sets parent(root) = -1, runs Evaluate, then repeats
+ *   G = g(goal) (or +inf with PIRRT_NO_PRUNE);  P = { v : g(v) + h(v) < G };
+ *   D = P and every neighbour of a vertex of P, minus the root (Sec. IV-C);
+ *   Improve over D against the g of the last Evaluate (Jacobi, Sec. IV);
+ * re-evaluating after each Improve that switched a parent, until one switches none.
+ *   h          : float[n] admissible heuristic (>= 0, not NaN), or NULL for h = 0.
+ *   g_out      : float[n] or NULL; receives g.
+ *   parent_out : int32[n] or NULL; receives the parent of each vertex (-1 for the
+ *                root and for vertices never attached); the final tree is
+ *                { (parent(v), v) } (Alg. 1 output).
+ *   mem_kind   : location of h, g_out and parent_out.
+ *   stats      : optional.
+ * Errors: EINVAL (root/goal out of range, bad h), ENOTCONVERGED (cap reached; the
+ * state is a consistent policy with its g), EDEVICE.
+ */
+int pirrt_replan(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uint32_t flags,
+                 float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
+
+/* Copies the stored policy out: g, parent and parent-edge cost (each may be NULL). */
+int pirrt_get_policy(pirrt_graph* g, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind);
+
+/* Replaces the stored policy (for starting Replan from an arbitrary policy, Sec. V).
+   parent[v] must be -1 or a vertex id other than v; pcost must be finite and >= 0.
+   g is stored as given (Replan recomputes it from the tree). */
+int pirrt_set_policy(pirrt_graph* g, const float* g_in, const int32_t* parent_in, const float* pcost_in,
+                     int mem_kind);
+
+/* Keeps a device-side copy of the policy (g, parent, pcost) / restores it.  Restore
+   fails with EINVAL if no snapshot exists or the vertex count changed since. */
+int pirrt_snapshot_save(pirrt_graph* g);
+int pirrt_snapshot_restore(pirrt_graph* g);
+
+/* Copies the adjacency out as CSR: ptr int64[n+1], nbr int32[nnz], cost float[nnz]
+   (any may be NULL).  The order of entries inside a row is unspecified. */
+int pirrt_get_adjacency(pirrt_graph* g, int64_t* ptr, int32_t* nbr, float* cost, int mem_kind);
+
+int64_t pirrt_num_vertices(const pirrt_graph* g);
+int64_t pirrt_num_edges(const pirrt_graph* g); /* directed entries = 2 x undirected */
+
+const char* pirrt_last_error(const pirrt_graph* g);
+const char* pirrt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIRRT_H */

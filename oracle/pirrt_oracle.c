@@ -18,9 +18,10 @@
  *
  * Readings of the paper taken here (each documented with the design notes):
  *   - Extend's local relaxation (Sec. III) picks, for a new vertex v, the existing
- *     neighbour u < v minimising (g(u) + c(u,v), u) lexicographically; with no
- *     finite candidate v is an orphan (g = +inf, parent = -1).  Vertex 0 is x_init
- *     and gets g = 0.
+ *     neighbour u < v minimising (g(u) + c(u,v), u, c) lexicographically (the cost
+ *     only separates parallel edges); with no finite candidate v is an orphan
+ *     (g = +inf, parent = -1).  Vertex 0 is x_init and gets g = 0.  Costs must be
+ *     finite, >= 0 and not -0.0.
  *   - Evaluate (Alg. 2) is taken in full: every vertex whose parent chain reaches
  *     the root gets g(v) = g(parent) + c(parent, v) in breadth-first order from the
  *     root; every other vertex gets +inf.  The promising set is rebuilt after the
@@ -29,7 +30,7 @@
  *   - Improve (Alg. 2, Sec. IV-B) runs over the promising vertices and their
  *     neighbours (Sec. IV-C), excluding the root, as a Jacobi step: every candidate
  *     reads the g of the last Evaluate.  Among the neighbours it takes the
- *     lexicographic minimum of (g(n) + c(n,v), n) and switches only when that value
+ *     lexicographic minimum of (g(n) + c(n,v), n, c) and switches only when that value
  *     is strictly below g(v), as the strict comparison of Alg. 2 does.
  *   - The convergence test dJ < eps is taken with eps at its limit: stop when no
  *     parent changed (then dJ = 0); an iteration cap guards termination.
@@ -114,7 +115,7 @@ int orc_insert(orc_graph* G, int32_t n_new, const int64_t* row_ptr, const int32_
     for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
       float c = cost[j];
       if (col[j] < 0 || col[j] >= n0 + i) return ORC_EINVAL;
-      if (!(c >= 0.0f) || isinf(c)) return ORC_EINVAL;
+      if (!(c >= 0.0f) || isinf(c) || signbit(c)) return ORC_EINVAL;
     }
   }
   /* grow the per-vertex arrays */
@@ -170,7 +171,7 @@ int orc_insert(orc_graph* G, int32_t n_new, const int64_t* row_ptr, const int32_
     for (int64_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j) {
       int32_t u = col[j];
       float cand = G->g[u] + cost[j];
-      if (cand < best || (cand == best && best_u >= 0 && u < best_u)) {
+      if (cand < best || (cand == best && best_u >= 0 && (u < best_u || (u == best_u && cost[j] < best_c)))) {
         if (cand < INFINITY) {
           best = cand;
           best_u = u;
@@ -316,7 +317,7 @@ int orc_replan(orc_graph* G, int32_t root, int32_t goal, const float* h, int pru
       for (int32_t j = 0; j < G->deg[v]; ++j) {
         int32_t u = G->nbr[v][j];
         float cand = G->g[u] + G->cst[v][j];
-        if (cand < best || (cand == best && best_u >= 0 && u < best_u)) {
+        if (cand < best || (cand == best && best_u >= 0 && (u < best_u || (u == best_u && G->cst[v][j] < best_c)))) {
           best = cand;
           best_u = u;
           best_c = G->cst[v][j];

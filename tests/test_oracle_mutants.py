@@ -17,18 +17,18 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 MUTANTS = {
     "improve_non_strict": ("if (best_u >= 0 && best < G->g[v]) {", "if (best_u >= 0 && best <= G->g[v]) {"),
-    "improve_tie_highest": (
-        "float cand = G->g[u] + G->cst[v][j];\n        if (cand < best || (cand == best && best_u >= 0 && u < best_u)) {",
-        "float cand = G->g[u] + G->cst[v][j];\n        if (cand < best || (cand == best && best_u >= 0 && u > best_u)) {"),
+    "improve_tie_highest": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))",
+                            "(u > best_u || (u == best_u && G->cst[v][j] < best_c))"),
+    "improve_cost_tie_ignored": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))", "(u < best_u)"),
     "improve_max": (
         "float cand = G->g[u] + G->cst[v][j];\n        if (cand < best ||",
         "float cand = G->g[u] + G->cst[v][j];\n        if (cand > best ||"),
     "improve_drops_cost": ("float cand = G->g[u] + G->cst[v][j];", "float cand = G->g[u];"),
     "improve_keeps_old_pcost": ("newpc[v] = best_c;", "newpc[v] = G->pcost[v];"),
     "improve_gauss_seidel": ("newpar[v] = best_u;", "newpar[v] = best_u;\n        G->g[v] = best;"),
-    "insert_tie_highest": (
-        "float cand = G->g[u] + cost[j];\n      if (cand < best || (cand == best && best_u >= 0 && u < best_u)) {",
-        "float cand = G->g[u] + cost[j];\n      if (cand < best || (cand == best && best_u >= 0 && u > best_u)) {"),
+    "insert_tie_highest": ("(u < best_u || (u == best_u && cost[j] < best_c))",
+                           "(u > best_u || (u == best_u && cost[j] < best_c))"),
+    "insert_cost_tie_ignored": ("(u < best_u || (u == best_u && cost[j] < best_c))", "(u < best_u)"),
     "insert_orphan_zero": ("    G->g[v] = best;\n", "    G->g[v] = best_u >= 0 ? best : 0.0f;\n"),
     "evaluate_wrong_index": ("G->g[c] = G->g[v] + G->pcost[c];", "G->g[c] = G->g[v] + G->pcost[v];"),
     "evaluate_no_reset": ("for (int64_t v = 0; v < n; ++v) G->g[v] = INFINITY;", ""),

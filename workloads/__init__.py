@@ -291,7 +291,7 @@ def from_edges(n: int, edges, n_old: int = 0) -> Batch:
     row_ptr = np.zeros(n - n_old + 1, np.int64)
     col, cost = [], []
     for i, r in enumerate(rows):
-        r.sort()
+        r.sort(key=lambda t: t[0])  # stable: parallel edges keep their given order
         row_ptr[i + 1] = row_ptr[i] + len(r)
         col += [u for u, _ in r]
         cost += [c for _, c in r]
