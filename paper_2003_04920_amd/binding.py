@@ -1,0 +1,246 @@
+"""ctypes binding of libpirrt.so, the gfx950 Replan library declared in include/pirrt.h.
+
+The functions keep the C names (``pirrt_graph_create``, ``pirrt_insert_batch``,
+``pirrt_replan`` ...) and only marshal arguments: numpy arrays are passed as host
+buffers, torch tensors on a ROCm device as device buffers (their ``data_ptr``).
+Every step of the computation runs in the library's HIP kernels; when the library
+is not built, loading fails loudly instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpirrt.so")
+
+PIRRT_OK, PIRRT_EINVAL, PIRRT_ENOMEM, PIRRT_EDEVICE, PIRRT_ENOTCONVERGED = 0, -1, -2, -3, -4
+PIRRT_MEM_HOST, PIRRT_MEM_DEVICE = 0, 1
+PIRRT_NO_PRUNE, PIRRT_TIMING = 1, 2
+
+EXPORTS = [
+    "pirrt_config_init", "pirrt_graph_create", "pirrt_graph_destroy", "pirrt_insert_batch", "pirrt_replan",
+    "pirrt_get_policy", "pirrt_set_policy", "pirrt_snapshot_save", "pirrt_snapshot_restore",
+    "pirrt_get_adjacency", "pirrt_num_vertices", "pirrt_num_edges", "pirrt_last_error", "pirrt_strerror",
+]
+
+
+class pirrt_config(ctypes.Structure):
+    _fields_ = [("vertex_capacity", ctypes.c_int64), ("edge_capacity", ctypes.c_int64),
+                ("hip_stream", ctypes.c_void_p), ("max_iters", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class pirrt_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("eval_levels", ctypes.c_int32),
+                ("edges_examined", ctypes.c_int64), ("sum_P", ctypes.c_int64), ("sum_D", ctypes.c_int64),
+                ("changed_total", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_evaluate", ctypes.c_double), ("ms_mark", ctypes.c_double), ("ms_improve", ctypes.c_double),
+                ("improve_launches", ctypes.c_int32), ("mark_launches", ctypes.c_int32),
+                ("evaluate_calls", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class PirrtError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Loads libpirrt.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("libpirrt.so is not built (%s); run __graft_entry__.build()" % p)
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    cint = ctypes.c_int
+    sig = {
+        "pirrt_config_init": (cint, [ctypes.POINTER(pirrt_config)]),
+        "pirrt_graph_create": (cint, [ctypes.POINTER(vp), ctypes.POINTER(pirrt_config)]),
+        "pirrt_graph_destroy": (cint, [vp]),
+        "pirrt_insert_batch": (cint, [vp, i32, vp, vp, vp, cint]),
+        "pirrt_replan": (cint, [vp, i32, i32, vp, u32, vp, vp, cint, ctypes.POINTER(pirrt_stats)]),
+        "pirrt_get_policy": (cint, [vp, vp, vp, vp, cint]),
+        "pirrt_set_policy": (cint, [vp, vp, vp, vp, cint]),
+        "pirrt_snapshot_save": (cint, [vp]),
+        "pirrt_snapshot_restore": (cint, [vp]),
+        "pirrt_get_adjacency": (cint, [vp, vp, vp, vp, cint]),
+        "pirrt_num_vertices": (i64, [vp]),
+        "pirrt_num_edges": (i64, [vp]),
+        "pirrt_last_error": (ctypes.c_char_p, [vp]),
+        "pirrt_strerror": (ctypes.c_char_p, [cint]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load().pirrt_strerror(code).decode()
+    except Exception:  # library missing: still format the error
+        return "error"
+
+
+def _is_device(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def _mem_kind(*arrays) -> int:
+    kinds = {_is_device(a) for a in arrays if a is not None}
+    if len(kinds) > 1:
+        raise ValueError("mix of host and device buffers in one call")
+    return PIRRT_MEM_DEVICE if kinds == {True} else PIRRT_MEM_HOST
+
+
+def _check_dtype(x, np_dtype, torch_name):
+    if x is None:
+        return x
+    if hasattr(x, "data_ptr"):
+        if str(x.dtype) != "torch." + torch_name or not x.is_contiguous():
+            raise TypeError("expected a contiguous torch.%s tensor" % torch_name)
+        return x
+    return np.ascontiguousarray(x, dtype=np_dtype)
+
+
+class Graph:
+    """One pirrt_graph handle.  `stream` is a hipStream_t as an int (for example
+    ``torch.cuda.current_stream().cuda_stream``) or None for the null stream."""
+
+    def __init__(self, stream: Optional[int] = None, device: int = -1, max_iters: int = 0,
+                 vertex_capacity: int = 0, edge_capacity: int = 0, lib: Optional[ctypes.CDLL] = None):
+        self._lib = lib or load()
+        cfg = pirrt_config()
+        self._lib.pirrt_config_init(ctypes.byref(cfg))
+        cfg.vertex_capacity = vertex_capacity
+        cfg.edge_capacity = edge_capacity
+        cfg.hip_stream = stream or None
+        cfg.max_iters = max_iters
+        cfg.device = device
+        h = ctypes.c_void_p()
+        rc = self._lib.pirrt_graph_create(ctypes.byref(h), ctypes.byref(cfg))
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.pirrt_graph_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, rc: int, allow=()):
+        if rc != PIRRT_OK and rc not in allow:
+            raise PirrtError(rc, self._lib.pirrt_last_error(self._h).decode())
+        return rc
+
+    @property
+    def n(self) -> int:
+        return int(self._lib.pirrt_num_vertices(self._h))
+
+    @property
+    def nnz(self) -> int:
+        return int(self._lib.pirrt_num_edges(self._h))
+
+    def insert_batch(self, row_ptr, col, cost) -> int:
+        row_ptr = _check_dtype(row_ptr, np.int64, "int64")
+        col = _check_dtype(col, np.int32, "int32")
+        cost = _check_dtype(cost, np.float32, "float32")
+        kind = _mem_kind(row_ptr, col, cost)
+        n_new = int(row_ptr.shape[0]) - 1
+        rc = self._lib.pirrt_insert_batch(self._h, n_new, _ptr(row_ptr), _ptr(col) if len(col) else None,
+                                          _ptr(cost) if len(cost) else None, kind)
+        return self._check(rc)
+
+    def insert_rows(self, batch) -> int:
+        """Inserts a workload batch (row_ptr / col / cost arrays)."""
+        return self.insert_batch(batch.row_ptr, batch.col, batch.cost)
+
+    def replan(self, root: int, goal: int, h=None, prune: bool = True, timing: bool = False,
+               g_out=None, parent_out=None, allow_not_converged: bool = False):
+        """Runs Replan.  Outputs are numpy arrays unless device buffers are given
+        (torch tensors on the GPU) or h is a device tensor."""
+        h = _check_dtype(h, np.float32, "float32")
+        n = self.n
+        if g_out is None and parent_out is None and _is_device(h):
+            import torch
+            g_out = torch.empty(n, dtype=torch.float32, device=h.device)
+            parent_out = torch.empty(n, dtype=torch.int32, device=h.device)
+        if g_out is None and parent_out is None:
+            g_out = np.empty(n, np.float32)
+            parent_out = np.empty(n, np.int32)
+        kind = _mem_kind(h, g_out, parent_out)
+        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0)
+        st = pirrt_stats()
+        rc = self._lib.pirrt_replan(self._h, int(root), int(goal), _ptr(h), flags, _ptr(g_out), _ptr(parent_out),
+                                    kind, ctypes.byref(st))
+        self._check(rc, allow=(PIRRT_ENOTCONVERGED,) if allow_not_converged else ())
+        d = st.as_dict()
+        d["rc"] = rc
+        return g_out, parent_out, d
+
+    def get_policy(self, device=None):
+        n = self.n
+        if device is not None:
+            import torch
+            g = torch.empty(n, dtype=torch.float32, device=device)
+            p = torch.empty(n, dtype=torch.int32, device=device)
+            c = torch.empty(n, dtype=torch.float32, device=device)
+        else:
+            g, p, c = np.empty(n, np.float32), np.empty(n, np.int32), np.empty(n, np.float32)
+        self._check(self._lib.pirrt_get_policy(self._h, _ptr(g), _ptr(p), _ptr(c), _mem_kind(g, p, c)))
+        return g, p, c
+
+    def set_policy(self, g, parent, pcost) -> int:
+        g = _check_dtype(g, np.float32, "float32")
+        parent = _check_dtype(parent, np.int32, "int32")
+        pcost = _check_dtype(pcost, np.float32, "float32")
+        return self._check(self._lib.pirrt_set_policy(self._h, _ptr(g), _ptr(parent), _ptr(pcost),
+                                                      _mem_kind(g, parent, pcost)))
+
+    def snapshot_save(self) -> int:
+        return self._check(self._lib.pirrt_snapshot_save(self._h))
+
+    def snapshot_restore(self) -> int:
+        return self._check(self._lib.pirrt_snapshot_restore(self._h))
+
+    def adjacency(self):
+        ptr = np.empty(self.n + 1, np.int64)
+        nbr = np.empty(max(self.nnz, 1), np.int32)
+        cst = np.empty(max(self.nnz, 1), np.float32)
+        self._check(self._lib.pirrt_get_adjacency(self._h, _ptr(ptr), _ptr(nbr), _ptr(cst), PIRRT_MEM_HOST))
+        return ptr, nbr[: self.nnz], cst[: self.nnz]
+
+
+def pirrt_strerror(code: int) -> str:
+    return _strerror(code)

@@ -1,0 +1,202 @@
+// Evaluate (Alg. 2; Sec. IV-C): breadth-first walk of the policy tree from the root,
+// computing g(c) = g(p) + c(p, c) for each child c of a vertex p of the current
+// level.  Every g is one binary32 addition in root-to-leaf order, so the values are
+// the left fold of the parent-edge costs along each root path, exactly as a serial
+// FIFO traversal produces them (the order inside a level does not matter: each
+// vertex is written once, from its parent's final value).  Vertices the walk does
+// not reach get +inf.
+//
+// Data layout: the tree is given by parent[] / pcost[]; a child CSR
+// (child_ptr[n+1], child[n]) is rebuilt from it on every Evaluate with a count,
+// an exclusive scan and a scatter.  The scatter pops the counts back to zero, so
+// the count array never needs clearing.
+//
+// The walk is level synchronous.  Tree levels near the root and near the leaves
+// are small, the ones in between large (tens of thousands of vertices for a
+// million-vertex tree), so three kernels share it:
+//   head  : one 1024-thread workgroup walks the top levels while the frontier fits
+//           (workgroup barriers between levels);
+//   level : one launch per large level, a wide grid striding over the frontier;
+//   tail  : one workgroup walks whatever remains, of any size.
+// Frontier sizes live in lvl[k] on the device; a launch that finds its level empty
+// does nothing, so the host only chooses how many level launches to enqueue (from
+// the previous Evaluate's profile) and never waits on a frontier size.
+#include "internal.h"
+
+namespace pirrt {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWgThreads = 1024;  // head / tail workgroup
+
+inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+// Counter reads after atomics of the same kernel bypass the per-CU L1.
+__device__ __forceinline__ int32_t load_counter(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root, int32_t* __restrict__ parent,
+                                                       float* __restrict__ pcost, float* __restrict__ g,
+                                                       int32_t* __restrict__ child_cnt) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (v == root) {
+    parent[v] = -1;
+    pcost[v] = 0.0f;
+    g[v] = 0.0f;
+    return;
+  }
+  g[v] = pos_inf();
+  int32_t p = parent[v];
+  if (p >= 0) atomicAdd(&child_cnt[p], 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_eval_fill(int32_t n, int32_t root, const int32_t* __restrict__ parent,
+                                                       const int32_t* __restrict__ child_ptr,
+                                                       int32_t* __restrict__ child_cnt, int32_t* __restrict__ child) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || v == root) return;
+  int32_t p = parent[v];
+  if (p >= 0) {
+    int32_t k = atomicSub(&child_cnt[p], 1) - 1;
+    child[child_ptr[p] + k] = (int32_t)v;
+  }
+}
+
+// Expands one frontier vertex per active lane: writes its children's g and appends
+// them to the next frontier (one atomic per wave).  Every lane of the wave calls it.
+// kSameKernel: g[u] was written earlier in this same launch (head / tail
+// workgroup), so it is read past the L1.
+template <bool kSameKernel>
+__device__ __forceinline__ void expand(int32_t u, const int32_t* __restrict__ child_ptr,
+                                       const int32_t* __restrict__ child, const float* __restrict__ pcost,
+                                       float* __restrict__ g, int32_t* __restrict__ next, int32_t* __restrict__ ncount) {
+  int32_t a = 0, b = 0;
+  if (u >= 0) {
+    a = child_ptr[u];
+    b = child_ptr[u + 1];
+  }
+  int slot = wave_reserve(ncount, b - a);
+  if (b > a) {
+    const float gu = kSameKernel ? __hip_atomic_load(&g[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : g[u];
+    for (int32_t k = a; k < b; ++k) {
+      int32_t c = child[k];
+      g[c] = add_rn(gu, pcost[c]);
+      next[slot + (k - a)] = c;
+    }
+  }
+}
+
+struct Bfs {
+  const int32_t* child_ptr;
+  const int32_t* child;
+  const float* pcost;
+  float* g;
+  int32_t* fr0;
+  int32_t* fr1;
+  int32_t* lvl;  // lvl[k] = size of level k
+  EvalInfo* info;
+};
+
+__global__ void __launch_bounds__(kWgThreads) k_bfs_head(int32_t root, int32_t limit, Bfs B) {
+  if (threadIdx.x == 0) {
+    B.fr0[0] = root;
+    B.lvl[0] = 1;
+    B.lvl[1] = 0;
+    B.lvl[2] = 0;
+    B.info->levels = 0;
+    B.info->big_end = 0;
+  }
+  __syncthreads();
+  int k = 0;
+  for (;;) {
+    const int32_t size = load_counter(&B.lvl[k]);
+    if (size == 0 || size > limit) break;
+    const int32_t* in = (k & 1) ? B.fr1 : B.fr0;
+    int32_t* out = (k & 1) ? B.fr0 : B.fr1;
+    for (int32_t base = 0; base < size; base += kWgThreads) {
+      int32_t t = base + (int32_t)threadIdx.x;
+      expand<true>(t < size ? load_counter(&in[t]) : -1, B.child_ptr, B.child, B.pcost, B.g, out, &B.lvl[k + 1]);
+    }
+    if (threadIdx.x == 0) B.lvl[k + 2] = 0;
+    __syncthreads();
+    ++k;
+  }
+  if (threadIdx.x == 0) {
+    B.info->head_end = k;
+    B.info->levels = k;
+  }
+}
+
+// Level head_end + j.  lvl[k+1] was cleared by the launch of level k-1; this
+// launch clears lvl[k+2] for the next one, also when its own level is empty.
+__global__ void __launch_bounds__(kThreads) k_bfs_level(int32_t j, int32_t tail_limit, Bfs B) {
+  const int32_t k = B.info->head_end + j;
+  const int32_t size = B.lvl[k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    B.lvl[k + 2] = 0;
+    if (size > 0) atomicMax(&B.info->levels, k + 1);
+    if (size > tail_limit) atomicMax(&B.info->big_end, k + 1);
+  }
+  if (size == 0) return;
+  const int32_t* in = (k & 1) ? B.fr1 : B.fr0;
+  int32_t* out = (k & 1) ? B.fr0 : B.fr1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < size; base += stride) {
+    int64_t t = base + threadIdx.x;
+    expand<false>(t < size ? in[t] : -1, B.child_ptr, B.child, B.pcost, B.g, out, &B.lvl[k + 1]);
+  }
+}
+
+__global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tail_limit, Bfs B,
+                                                        IterCounters* __restrict__ ctr) {
+  int k = B.info->head_end + j0;
+  int levels = 0, big_end = 0;
+  for (;;) {
+    const int32_t size = load_counter(&B.lvl[k]);
+    if (size == 0) break;
+    levels = k + 1;
+    if (size > tail_limit) big_end = k + 1;
+    const int32_t* in = (k & 1) ? B.fr1 : B.fr0;
+    int32_t* out = (k & 1) ? B.fr0 : B.fr1;
+    for (int32_t base = 0; base < size; base += kWgThreads) {
+      int32_t t = base + (int32_t)threadIdx.x;
+      expand<true>(t < size ? load_counter(&in[t]) : -1, B.child_ptr, B.child, B.pcost, B.g, out, &B.lvl[k + 1]);
+    }
+    if (threadIdx.x == 0) B.lvl[k + 2] = 0;
+    __syncthreads();
+    ++k;
+  }
+  if (threadIdx.x == 0) {
+    if (levels > B.info->levels) B.info->levels = levels;
+    if (big_end > B.info->big_end) B.info->big_end = big_end;
+    // fresh counters for the promising-set / Improve pass that follows
+    ctr->changed = 0;
+    ctr->nP = 0;
+    ctr->nD = 0;
+    ctr->edges = 0ull;
+  }
+}
+
+}  // namespace
+
+void launch_evaluate(const EvalArgs& a, hipStream_t s) {
+  const int32_t n = a.n;
+  hipLaunchKernelGGL(k_eval_prep, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.parent, a.pcost, a.g,
+                     a.child_cnt);
+  scan_i32_to_i32(a.child_cnt, n, a.child_ptr, a.scan_scratch, s);
+  hipLaunchKernelGGL(k_eval_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.parent, a.child_ptr,
+                     a.child_cnt, a.child);
+  Bfs B{a.child_ptr, a.child, a.pcost, a.g, a.fr0, a.fr1, a.lvl, a.info};
+  hipLaunchKernelGGL(k_bfs_head, dim3(1), dim3(kWgThreads), 0, s, a.root, (int32_t)kWgThreads, B);
+  for (int32_t j = 0; j < a.mid_launches; ++j)
+    hipLaunchKernelGGL(k_bfs_level, dim3(a.level_blocks), dim3(kThreads), 0, s, j, (int32_t)kWgThreads, B);
+  hipLaunchKernelGGL(k_bfs_tail, dim3(1), dim3(kWgThreads), 0, s, a.mid_launches, (int32_t)kWgThreads, B, a.ctr);
+}
+
+}  // namespace pirrt

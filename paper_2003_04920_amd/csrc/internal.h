@@ -1,0 +1,70 @@
+// Internal interfaces between the host runtime (capi.hip) and the kernel files.
+#pragma once
+
+#include "common.h"
+
+namespace pirrt {
+
+// ---- scan.hip ----
+size_t scan_scratch_bytes(int64_t n);
+void scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, void* scratch, hipStream_t s);
+void scan_i32_to_i32(const int32_t* in, int64_t n, int32_t* out, void* scratch, hipStream_t s);
+
+// ---- store.hip ----
+void launch_validate_rows(int32_t n_new, int64_t n_old, const int64_t* rp, const int32_t* col, const float* cost,
+                          int64_t nnz, int* err, hipStream_t s);
+void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
+                    const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
+                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
+                    hipStream_t s);
+void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
+                    int32_t* frontier, int32_t* fcount, hipStream_t s);
+void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
+                         const int32_t* bcol, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
+                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
+                         hipStream_t s);
+
+// ---- evaluate.hip ----
+struct EvalArgs {
+  int32_t n;
+  int32_t root;
+  int32_t* parent;
+  float* pcost;
+  float* g;
+  int32_t* child_cnt;   // n, all zero on entry and on exit
+  int32_t* child_ptr;   // n + 1
+  int32_t* child;       // n
+  int32_t* fr0;         // n
+  int32_t* fr1;         // n
+  int32_t* lvl;         // level sizes, n + kMaxMidLaunches + 4
+  EvalInfo* info;
+  IterCounters* ctr;    // cleared at the end of the walk
+  void* scan_scratch;
+  int32_t mid_launches; // wide level launches between head and tail
+  int32_t level_blocks; // grid of each wide level launch
+};
+constexpr int32_t kMaxMidLaunches = 1024;
+void launch_evaluate(const EvalArgs& a, hipStream_t s);
+
+// ---- improve.hip ----
+struct StepArgs {
+  int32_t n;
+  int32_t root;
+  int32_t goal;
+  int32_t prune;
+  const float* g;
+  const float* h;  // nullable
+  const int64_t* rp;
+  const int32_t* col;
+  const float* cst;
+  uint32_t* stamp;
+  uint32_t epoch;
+  int32_t* parent;
+  float* pcost;
+  IterCounters* ctr;
+};
+constexpr int kRowVariants = 4;
+void launch_mark(const StepArgs& a, int variant, hipStream_t s);
+void launch_improve(const StepArgs& a, int variant, hipStream_t s);
+
+}  // namespace pirrt

@@ -1,0 +1,238 @@
+// Graph store: appending a batch of vertices to the symmetric CSR adjacency, and
+// Extend's insertion-time policy for the new vertices (Sec. III local relaxation;
+// Sec. IV-A cached edge costs).
+//
+// The adjacency is one CSR over all vertices: int64 row offsets and, per entry, an
+// int32 neighbour id and a binary32 cost in two parallel arrays.  A batch arrives as forward rows (each new vertex
+// lists its lower-index neighbours).  Appending rebuilds the CSR into a spare
+// buffer in one streaming pass: every row keeps its old entries, a new vertex's
+// row starts with its forward entries, and each forward edge (v, u) is mirrored
+// into u's row.  Entry order inside a row is not fixed (mirrors are placed with
+// atomics); nothing downstream depends on it because every minimum is taken on
+// (value, neighbour, cost).
+#include "internal.h"
+
+namespace pirrt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+// Error bits raised by validation.
+enum { kErrRowPtr = 1, kErrCol = 2, kErrCost = 4 };
+
+__global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64_t n_old,
+                                                           const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           const float* __restrict__ cost, int64_t nnz,
+                                                           int* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_new) return;
+  int64_t a = rp[i], b = rp[i + 1];
+  int bad = 0;
+  if (i == 0 && a != 0) bad |= kErrRowPtr;
+  if (a < 0 || b < a || b > nnz) {
+    atomicOr(err, bad | kErrRowPtr);
+    return;
+  }
+  const int64_t self = n_old + i;
+  for (int64_t j = a; j < b; ++j) {
+    int32_t c = col[j];
+    uint32_t w = __float_as_uint(cost[j]);
+    if (c < 0 || (int64_t)c >= self) bad |= kErrCol;
+    // finite, >= 0 and sign bit clear (rejects NaN, inf, negatives and -0.0)
+    if ((w >> 31) != 0 || (w & 0x7f800000u) == 0x7f800000u) bad |= kErrCost;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// add[v] += forward length of new vertex v; add[u] += 1 per mirrored entry.
+__global__ void __launch_bounds__(kThreads) k_count_new(int32_t n_new, int64_t n_old,
+                                                       const int64_t* __restrict__ brp,
+                                                       const int32_t* __restrict__ bcol,
+                                                       int32_t* __restrict__ add) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_new) return;
+  int64_t a = brp[i], b = brp[i + 1];
+  if (b > a) atomicAdd(&add[n_old + i], (int)(b - a));
+  for (int64_t j = a; j < b; ++j) atomicAdd(&add[bcol[j]], 1);
+}
+
+// deg[v] = old degree + added entries; add[v] becomes the fill cursor of v's row
+// (old degree + forward length, mirrors go after it).
+__global__ void __launch_bounds__(kThreads) k_degrees(int64_t n1, int64_t n_old,
+                                                     const int64_t* __restrict__ rp_old,
+                                                     const int64_t* __restrict__ brp,
+                                                     int32_t* __restrict__ add, int32_t* __restrict__ deg) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n1) return;
+  int32_t old = v < n_old ? (int32_t)(rp_old[v + 1] - rp_old[v]) : 0;
+  int32_t fwd = v >= n_old ? (int32_t)(brp[v - n_old + 1] - brp[v - n_old]) : 0;
+  deg[v] = old + add[v];
+  add[v] = old + fwd;
+}
+
+// Copies every old row to its new offset: one wave per row, lanes striding.
+__global__ void __launch_bounds__(kThreads) k_copy_rows(int64_t n_old, const int64_t* __restrict__ rp_old,
+                                                       const int32_t* __restrict__ col_old,
+                                                       const float* __restrict__ cst_old,
+                                                       const int64_t* __restrict__ rp_new,
+                                                       int32_t* __restrict__ col_new, float* __restrict__ cst_new) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (v >= n_old) return;
+  int64_t a = rp_old[v], b = rp_old[v + 1], dst = rp_new[v];
+  for (int64_t j = a + lane; j < b; j += kWave) {
+    col_new[dst + (j - a)] = col_old[j];
+    cst_new[dst + (j - a)] = cst_old[j];
+  }
+}
+
+// Forward entries of each new row, and their mirrors into the lower endpoint.
+__global__ void __launch_bounds__(kThreads) k_scatter_new(int32_t n_new, int64_t n_old,
+                                                         const int64_t* __restrict__ brp,
+                                                         const int32_t* __restrict__ bcol,
+                                                         const float* __restrict__ bcost,
+                                                         const int64_t* __restrict__ rp_new,
+                                                         int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ col_new,
+                                                         float* __restrict__ cst_new) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_new) return;
+  const int32_t v = (int32_t)(n_old + i);
+  int64_t a = brp[i], b = brp[i + 1], dst = rp_new[v];
+  for (int64_t j = a; j < b; ++j) {
+    int32_t u = bcol[j];
+    float c = bcost[j];
+    col_new[dst + (j - a)] = u;
+    cst_new[dst + (j - a)] = c;
+    int64_t pos = rp_new[u] + atomicAdd(&cursor[u], 1);
+    col_new[pos] = v;
+    cst_new[pos] = c;
+  }
+}
+
+// pending[i] = number of same-batch lower neighbours of new vertex n_old + i; the
+// ones with none start the first dependency level.
+__global__ void __launch_bounds__(kThreads) k_pending(int32_t n_new, int64_t n_old,
+                                                     const int64_t* __restrict__ brp,
+                                                     const int32_t* __restrict__ bcol,
+                                                     int32_t* __restrict__ pending,
+                                                     int32_t* __restrict__ frontier, int32_t* __restrict__ fcount) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int ready = 0;
+  if (i < n_new) {
+    int cnt = 0;
+    for (int64_t j = brp[i]; j < brp[i + 1]; ++j) cnt += (bcol[j] >= n_old);
+    pending[i] = cnt;
+    ready = cnt == 0;
+  }
+  int slot = wave_reserve(fcount, ready);
+  if (ready) frontier[slot] = (int32_t)(n_old + i);
+}
+
+// One dependency level of the insertion-time policy: every vertex of the frontier
+// has all its lower neighbours final, so its local relaxation is final too.
+__global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const int32_t* __restrict__ frontier,
+                                                          int64_t n_old, const int64_t* __restrict__ brp,
+                                                          const int32_t* __restrict__ bcol,
+                                                          const float* __restrict__ bcost,
+                                                          const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col, float* __restrict__ g,
+                                                          int32_t* __restrict__ parent, float* __restrict__ pcost,
+                                                          int32_t* __restrict__ pending,
+                                                          int32_t* __restrict__ next, int32_t* __restrict__ ncount) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t v = t < fsize ? frontier[t] : -1;
+  if (v >= 0) {
+    int64_t i = v - n_old;
+    int64_t a = brp[i], b = brp[i + 1];
+    if (v == 0) {
+      g[0] = 0.0f;
+      parent[0] = -1;
+      pcost[0] = 0.0f;
+    } else {
+      Cand best;
+      best.key = ~0ull;
+      best.cbits = ~0u;
+      for (int64_t j = a; j < b; ++j) {
+        int32_t u = bcol[j];
+        float c = bcost[j];
+        float val = add_rn(g[u], c);
+        cand_min(best, ((unsigned long long)__float_as_uint(val) << 32) | (uint32_t)u, __float_as_uint(c));
+      }
+      uint32_t vb = (uint32_t)(best.key >> 32);
+      if (best.key != ~0ull && vb < 0x7f800000u) {
+        g[v] = __uint_as_float(vb);
+        parent[v] = (int32_t)(uint32_t)best.key;
+        pcost[v] = __uint_as_float(best.cbits);
+      } else {
+        g[v] = pos_inf();
+        parent[v] = -1;
+        pcost[v] = 0.0f;
+      }
+    }
+  }
+  // release the same-batch higher neighbours (the mirror part of v's row)
+  int64_t ma = 0, mb = 0;
+  if (v >= 0) {
+    int64_t i = v - n_old;
+    ma = rp[v] + (brp[i + 1] - brp[i]);
+    mb = rp[v + 1];
+  }
+  for (int64_t j = ma; j < mb; ++j) {
+    int32_t w = col[j];
+    int32_t left = atomicSub(&pending[w - n_old], 1) - 1;
+    if (left == 0) {
+      int32_t slot = atomicAdd(ncount, 1);
+      next[slot] = w;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_validate_rows(int32_t n_new, int64_t n_old, const int64_t* rp, const int32_t* col,
+                          const float* cost, int64_t nnz, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_rows, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, rp, col,
+                     cost, nnz, err);
+}
+
+void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
+                    const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
+                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
+                    hipStream_t s) {
+  const int64_t n1 = n_old + n_new;
+  hipMemsetAsync(add, 0, sizeof(int32_t) * (size_t)n1, s);
+  if (n_new > 0)
+    hipLaunchKernelGGL(k_count_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add);
+  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n1)), dim3(kThreads), 0, s, n1, n_old, rp_old, brp, add, deg);
+  scan_i32_to_i64(deg, n1, rp_new, scan_scratch, s);
+  if (n_old > 0)
+    hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(n_old * kWave)), dim3(kThreads), 0, s, n_old, rp_old,
+                       col_old, cst_old, rp_new, col_new, cst_new);
+  if (n_new > 0)
+    hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol,
+                       bcost, rp_new, add, col_new, cst_new);
+}
+
+void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
+                    int32_t* frontier, int32_t* fcount, hipStream_t s) {
+  hipLaunchKernelGGL(k_pending, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, pending,
+                     frontier, fcount);
+}
+
+void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
+                         const int32_t* bcol, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
+                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, n_old, brp,
+                     bcol, bcost, rp, col, g, parent, pcost, pending, next, ncount);
+}
+
+}  // namespace pirrt

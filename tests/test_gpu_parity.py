@@ -1,0 +1,271 @@
+"""GPU Replan (libpirrt.so through its C ABI) against the oracle, element by element.
+
+g must match bit for bit (compared as uint32), parents exactly, and the
+per-Replan statistics (iterations, |P| and |D| sums, edges examined, parents
+switched) exactly: the GPU path follows the same algorithm step by step.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle_pins import fixtures, load_fixture
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_04920_amd as P
+    P.load()
+    return P
+
+
+def gpu_graph(P, **kw):
+    import torch
+    return P.Graph(stream=torch.cuda.current_stream().cuda_stream, **kw)
+
+
+def assert_same_policy(tag, g_gpu, p_gpu, g_orc, p_orc):
+    g_gpu = np.asarray(g_gpu)
+    p_gpu = np.asarray(p_gpu)
+    bad_g = np.nonzero(g_gpu.view(np.uint32) != g_orc.view(np.uint32))[0]
+    bad_p = np.nonzero(p_gpu != p_orc)[0]
+    assert bad_g.size == 0, "%s: %d g mismatches, first %s: gpu %r oracle %r" % (
+        tag, bad_g.size, bad_g[:5], g_gpu[bad_g[:5]], g_orc[bad_g[:5]])
+    assert bad_p.size == 0, "%s: %d parent mismatches, first %s: gpu %r oracle %r" % (
+        tag, bad_p.size, bad_p[:5], p_gpu[bad_p[:5]], p_orc[bad_p[:5]])
+
+
+def assert_same_stats(tag, sg, so):
+    for k in STAT_KEYS:
+        assert sg[k] == so[k], "%s: %s gpu %d oracle %d" % (tag, k, sg[k], so[k])
+
+
+def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True):
+    """Inserts `batches` into both and, after each batch i in `plan`, replans
+    (root, goal) = plan[i] on both and compares everything."""
+    G = gpu_graph(P)
+    R = O.Graph()
+    for i, b in enumerate(batches):
+        G.insert_rows(b)
+        assert R.insert_batch(b) == 0
+        if check_insert:
+            g, p, c = G.get_policy()
+            st = R.state()
+            assert_same_policy("insert %d" % i, g, p, st.g, st.parent)
+            assert np.array_equal(c.view(np.uint32), st.pcost.view(np.uint32))
+        if i in plan:
+            root, goal = plan[i]
+            h = None if h_of is None else h_of(G.n)
+            gg, pp, sg = G.replan(root, goal, h, prune)
+            rc, so = R.replan(root, goal, h, prune)
+            assert rc == 0 and sg["rc"] == 0
+            st = R.state()
+            assert_same_policy("replan %d" % i, gg, pp, st.g, st.parent)
+            assert_same_stats("replan %d" % i, sg, so)
+    return G, R
+
+
+def test_golden_fixtures(P):
+    for path in fixtures():
+        fx = load_fixture(path)
+        G = gpu_graph(P)
+        G.insert_rows(W.from_edges(fx["n"], fx["edges"]))
+        g, p, _ = G.get_policy()
+        assert np.array_equal(g, fx["insert_g"]) and np.array_equal(p, fx["insert_parent"]), path
+        gg, pp, st = G.replan(fx["root"], fx["goal"], fx["h"], bool(fx["prune"]))
+        assert np.array_equal(gg, fx["expect_g"]), (path, gg)
+        assert np.array_equal(pp, fx["expect_parent"]), (path, pp)
+        for k, v in fx["expect_stats"].items():
+            assert st[k] == v, (path, k, st[k], v)
+
+
+@pytest.mark.parametrize("prune", [True, False])
+def test_plain_2d(P, prune):
+    wl = W.plain_2d()
+    run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, prune)
+
+
+def test_plain_2d_goal_rooted(P):
+    wl = W.plain_2d()
+    G, R = run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, True)
+    # second Replan on the same graph, rooted at the goal, pruning off
+    gg, pp, sg = G.replan(1, 0, None, False)
+    rc, so = R.replan(1, 0, None, False)
+    assert rc == 0
+    st = R.state()
+    assert_same_policy("goal-rooted", gg, pp, st.g, st.parent)
+    assert_same_stats("goal-rooted", sg, so)
+
+
+def test_batched_6d_small(P):
+    wl = W.batched_6d(batches=12, batch=500, seed=100)
+    run_both(P, wl.batches, {i: (0, 1) for i in range(12)}, wl.heuristic, True)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 8])
+def test_dimensions(P, d):
+    obs = W.make_obstacles(d, 20, "mixed", 40 + d)
+    wl = W.grow("dim%d" % d, d, obs, 50 + d, [3000])
+    run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, True)
+
+
+def test_all_orphans_start(P):
+    wl = W.plain_2d(samples=1500, seed=3)
+    G = gpu_graph(P)
+    R = O.Graph()
+    G.insert_rows(wl.batches[0])
+    R.insert_batch(wl.batches[0])
+    n = G.n
+    z = (np.full(n, np.inf, np.float32), np.full(n, -1, np.int32), np.zeros(n, np.float32))
+    G.set_policy(*z)
+    R.set_state(*z)
+    gg, pp, sg = G.replan(0, 1, wl.heuristic(), True)
+    rc, so = R.replan(0, 1, wl.heuristic(), True)
+    st = R.state()
+    assert_same_policy("orphans", gg, pp, st.g, st.parent)
+    assert_same_stats("orphans", sg, so)
+
+
+def test_iteration_cap(P):
+    wl = W.plain_2d(samples=800, seed=4)
+    G = gpu_graph(P, max_iters=2)
+    R = O.Graph()
+    G.insert_rows(wl.batches[0])
+    R.insert_batch(wl.batches[0])
+    gg, pp, sg = G.replan(0, 1, wl.heuristic(), True, allow_not_converged=True)
+    rc, so = R.replan(0, 1, wl.heuristic(), True, max_iters=2)
+    assert sg["rc"] == P.PIRRT_ENOTCONVERGED and rc == O.ENOTCONVERGED
+    st = R.state()
+    assert_same_policy("cap", gg, pp, st.g, st.parent)
+    assert_same_stats("cap", sg, so)
+
+
+def test_degenerate_graphs(P):
+    # a lone vertex; root == goal
+    G = gpu_graph(P)
+    G.insert_batch(np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    g, p, st = G.replan(0, 0)
+    assert g[0] == 0 and p[0] == -1 and st["iterations"] == 1
+    # empty batch is a no-op
+    G.insert_batch(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    assert G.n == 1
+    # isolated vertices, a detached component and zero-cost edges
+    edges = [(0, 2, 0.0), (2, 3, 1.0), (4, 5, 1.0), (5, 6, 0.5), (3, 1, 2.0)]
+    b = W.from_edges(8, edges)
+    G2 = gpu_graph(P)
+    R = O.Graph()
+    G2.insert_rows(b)
+    R.insert_batch(b)
+    for prune in (True, False):
+        gg, pp, sg = G2.replan(0, 1, None, prune)
+        rc, so = R.replan(0, 1, None, prune)
+        st = R.state()
+        assert_same_policy("degenerate", gg, pp, st.g, st.parent)
+        assert_same_stats("degenerate", sg, so)
+    assert np.isinf(gg[4:]).all() and gg[7] == np.inf
+
+
+def test_rows_longer_than_a_wave(P):
+    # a hub with 300 neighbours and a ring: rows far longer than 64 entries
+    rng = np.random.default_rng(9)
+    n = 400
+    edges = [(0, v, float(np.float32(rng.uniform(0.5, 2.0)))) for v in range(2, 302)]
+    edges += [(v, v + 1, float(np.float32(rng.uniform(0.1, 0.3)))) for v in range(1, n - 1)]
+    edges += [(1, n - 1, 0.25)]
+    b = W.from_edges(n, edges)
+    run_both(P, [b], {0: (0, 1)}, None, False)
+    run_both(P, [b], {0: (5, 1)}, None, True)
+
+
+def test_device_buffers(P):
+    import torch
+    wl = W.plain_2d(samples=1200, seed=6)
+    b = wl.batches[0]
+    dev = torch.device("cuda:0")
+    G = gpu_graph(P)
+    G.insert_batch(torch.from_numpy(b.row_ptr).to(dev), torch.from_numpy(b.col).to(dev),
+                   torch.from_numpy(b.cost).to(dev))
+    h = torch.from_numpy(wl.heuristic()).to(dev)
+    gg, pp, sg = G.replan(0, 1, h, True)
+    assert gg.is_cuda and pp.is_cuda
+    R = O.Graph()
+    R.insert_batch(b)
+    rc, so = R.replan(0, 1, wl.heuristic(), True)
+    st = R.state()
+    assert_same_policy("device", gg.cpu().numpy(), pp.cpu().numpy(), st.g, st.parent)
+    assert_same_stats("device", sg, so)
+
+
+def test_invalid_arguments_leave_state(P):
+    wl = W.plain_2d(samples=300, seed=7)
+    G = gpu_graph(P)
+    G.insert_rows(wl.batches[0])
+    n0, e0 = G.n, G.nnz
+    before = G.get_policy()
+    bad = [
+        (np.array([0, 1], np.int64), np.array([n0], np.int32), np.array([1.0], np.float32)),   # col == own id
+        (np.array([0, 1], np.int64), np.array([-1], np.int32), np.array([1.0], np.float32)),   # negative col
+        (np.array([0, 1], np.int64), np.array([0], np.int32), np.array([np.nan], np.float32)),  # NaN cost
+        (np.array([0, 1], np.int64), np.array([0], np.int32), np.array([-0.0], np.float32)),   # -0.0 cost
+        (np.array([0, 1], np.int64), np.array([0], np.int32), np.array([np.inf], np.float32)),  # inf cost
+        (np.array([1, 1], np.int64), np.array([0], np.int32), np.array([1.0], np.float32)),    # row_ptr[0] != 0
+    ]
+    for rp, c, w in bad:
+        with pytest.raises(P.PirrtError) as e:
+            G.insert_batch(rp, c, w)
+        assert e.value.code == P.PIRRT_EINVAL
+    assert G.n == n0 and G.nnz == e0
+    after = G.get_policy()
+    for x, y in zip(before, after):
+        assert np.array_equal(np.asarray(x).view(np.uint32), np.asarray(y).view(np.uint32))
+    for root, goal in ((-1, 1), (0, n0), (n0, 0)):
+        with pytest.raises(P.PirrtError) as e:
+            G.replan(root, goal)
+        assert e.value.code == P.PIRRT_EINVAL
+    h = wl.heuristic()
+    h[3] = np.nan
+    with pytest.raises(P.PirrtError):
+        G.replan(0, 1, h)
+    h[3] = -1.0
+    with pytest.raises(P.PirrtError):
+        G.replan(0, 1, h)
+
+
+def test_snapshot_restore_repeatable(P):
+    wl = W.batched_6d(batches=2, batch=2000, seed=100)
+    G = gpu_graph(P)
+    for b in wl.batches:
+        G.insert_rows(b)
+    G.snapshot_save()
+    outs = []
+    for _ in range(3):
+        G.snapshot_restore()
+        g, p, st = G.replan(0, 1, wl.heuristic(), True)
+        outs.append((g.copy(), p.copy(), st))
+    for g, p, st in outs[1:]:
+        assert np.array_equal(g.view(np.uint32), outs[0][0].view(np.uint32))
+        assert np.array_equal(p, outs[0][1])
+        assert_same_stats("repeat", st, outs[0][2])
+
+
+def test_adjacency_is_symmetric_union(P):
+    wl = W.batched_6d(batches=3, batch=700, seed=101)
+    G = gpu_graph(P)
+    R = O.Graph()
+    for b in wl.batches:
+        G.insert_rows(b)
+        R.insert_batch(b)
+    pg, ng, cg = G.adjacency()
+    po, no, co = R.adjacency()
+    assert np.array_equal(pg, po)
+    for v in range(G.n):
+        a = sorted(zip(ng[pg[v]:pg[v + 1]].tolist(), cg[pg[v]:pg[v + 1]].view(np.uint32).tolist()))
+        b = sorted(zip(no[po[v]:po[v + 1]].tolist(), co[po[v]:po[v + 1]].view(np.uint32).tolist()))
+        assert a == b, v
