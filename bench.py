@@ -1,0 +1,198 @@
+"""Benchmark: PI-RRT# Replan on the 6D 1,000,000-vertex random geometric graph.
+
+One step = one full Replan (Alg. 2: Evaluate, then promising set, Improve domain,
+Improve and Evaluate to the fixed point) of the 1M-vertex graph from its
+insertion-time policy, on one MI355X.  Each step first restores that policy from
+the device-side snapshot (a 12 MB device copy, inside the timed region).  The
+graph, the heuristic and the outputs stay in device memory throughout.
+
+Prints one JSON line.  `value` is Replan GTEPS = edges examined by Improve / wall
+time of the timed steps.  `roofline` is the Improve kernel against HBM bandwidth,
+timed with HIP events on the library's stream; `cpu_baseline` is the serial
+oracle on this host's cores for one Replan of the same graph.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def improve_bytes(edges: int, sum_d: int, n: int, launches: int) -> int:
+    """Algorithmic HBM bytes of the Improve launches: 8 B per examined edge (int32
+    neighbour + binary32 cost, streamed), 24 B per domain vertex (two row offsets,
+    its g, its domain stamp and the parent/pcost update) and, once per launch, the
+    4 B domain stamp and 4 B g of every vertex (the chunk scan and the g array
+    the gathers read)."""
+    return 8 * edges + 24 * sum_d + 8 * n * launches
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=1_000_000)
+    ap.add_argument("--extra", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the Replan library runs on a single device and "
+              "this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.time()
+    wl = W.plain_6d(samples=args.samples, extra=0 if args.no_extra else args.extra, seed=200)
+    log("workload %s: n=%d, batches=%d, directed edges=%d (%.1fs)" %
+        (wl.name, wl.n, len(wl.batches), 2 * wl.nnz, time.time() - t0))
+    b0 = wl.batches[0]
+    G = P.Graph(stream=stream.cuda_stream, device=0)
+    t0 = time.time()
+    G.insert_rows(b0)
+    torch.cuda.synchronize()
+    insert_s = time.time() - t0
+    n = G.n
+    log("inserted %d vertices, %d directed entries in %.3fs" % (n, G.nnz, insert_s))
+    G.snapshot_save()
+    h = torch.from_numpy(wl.heuristic(n)).to(dev)
+    g_out = torch.empty(n, dtype=torch.float32, device=dev)
+    p_out = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def step(timing=False):
+        G.snapshot_restore()
+        _, _, st = G.replan(0, 1, h, True, timing=timing, g_out=g_out, parent_out=p_out)
+        return st
+
+    for i in range(args.warmup):
+        st = step()
+        log("warmup %d: %.3f ms, iterations %d, edges %d" % (i, st["ms_total"], st["iterations"],
+                                                             st["edges_examined"]))
+    # phase breakdown (HIP events around every launch; separate from the timed steps)
+    tst = step(timing=True)
+    log("timing pass: %s" % json.dumps({k: tst[k] for k in ("ms_total", "ms_evaluate", "ms_mark", "ms_improve",
+                                                              "improve_launches", "evaluate_calls")}))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / max(1, args.steps)
+    edges = sum(s["edges_examined"] for s in stats)
+    gteps = edges / elapsed / 1e9
+    st = stats[-1]
+    for s in stats:
+        assert s["edges_examined"] == st["edges_examined"] and s["iterations"] == st["iterations"]
+    log("timed: %d steps, %.3f ms/step, %.1f GTEPS" % (args.steps, ms_per_step, gteps))
+
+    nbytes = improve_bytes(tst["edges_examined"], tst["sum_D"], n, tst["improve_launches"])
+    achieved = nbytes / (tst["ms_improve"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_improve", "launches": tst["improve_launches"],
+                "avg_launch_us": round(1e3 * tst["ms_improve"] / max(1, tst["improve_launches"]), 2),
+                "bytes_per_launch": int(nbytes / max(1, tst["improve_launches"]))}
+
+    extra = None
+    if not args.no_extra and len(wl.batches) > 1:
+        # a further 10,000-vertex batch on the converged 1M-vertex policy
+        G.snapshot_restore()
+        G.replan(0, 1, h, True, g_out=g_out, parent_out=p_out)
+        b1 = wl.batches[1]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.insert_rows(b1)
+        torch.cuda.synchronize()
+        t_ins = time.perf_counter() - t0
+        h2 = torch.from_numpy(wl.heuristic(G.n)).to(dev)
+        g2 = torch.empty(G.n, dtype=torch.float32, device=dev)
+        p2 = torch.empty(G.n, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, s2 = G.replan(0, 1, h2, True, g_out=g2, parent_out=p2)
+        torch.cuda.synchronize()
+        t_rep = time.perf_counter() - t0
+        extra = {"batch": b1.n_new, "insert_ms": round(1e3 * t_ins, 3), "replan_ms": round(1e3 * t_rep, 3),
+                 "iterations": s2["iterations"], "edges_examined": s2["edges_examined"],
+                 "gteps": round(s2["edges_examined"] / t_rep / 1e9, 2)}
+        log("+%d batch: %s" % (b1.n_new, json.dumps(extra)))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        R = oracle.Graph()
+        assert R.insert_batch(b0) == 0
+        hh = wl.heuristic(n)
+        t0 = time.perf_counter()
+        rc, so = R.replan(0, 1, hh, True)
+        t_cpu = time.perf_counter() - t0
+        assert rc == 0 and so["edges_examined"] == st["edges_examined"], (so, st)
+        cpu = {"value": round(so["edges_examined"] / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "one full Replan of the same 1M-vertex graph from its insertion-time policy "
+                         "(serial C oracle, one thread, %.2f s)" % t_cpu}
+        log("cpu baseline: %s" % json.dumps(cpu))
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+    out = {
+        "metric": "Replan GTEPS + ms/replan (6D 1M-vertex RRG), HBM % peak; plain vs learned",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "6D unit-cube RRG, 40 sphere obstacles, %d vertices, r=(ln n/n)^(1/6), "
+                               "%d directed FP32-cost edges; one full Replan from the insertion-time "
+                               "policy, pruning on, h = Euclidean distance to goal" % (n, 2 * b0.nnz),
+                   "vertices": n, "directed_edges": 2 * b0.nnz, "iterations": st["iterations"],
+                   "edges_examined_per_replan": st["edges_examined"], "sum_D": st["sum_D"],
+                   "parallelism": "single GPU"},
+        "phases_ms": {k: round(tst[k], 4) for k in ("ms_evaluate", "ms_mark", "ms_improve")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra_batch": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "pirrt.h"
@@ -83,14 +84,29 @@ struct pirrt_graph {
   // promising / domain marks
   uint32_t* stamp = nullptr;
   uint32_t epoch = 0;
-  // insertion scratch
+  // Evaluate stamps {epoch, g bits}
+  unsigned long long* word = nullptr;
+  uint32_t eval_epoch = 0;
+  bool eval_levels = false;  // level-synchronous Evaluate instead of the walk
+  // storage order: ext_of[slot] = caller id, slot_of[id] = slot (host mirror hslot)
+  int32_t* ext_of = nullptr;
+  int32_t* slot_of = nullptr;
+  std::vector<int32_t> hslot;
+  int64_t reorder_n = 0;       // vertex count at the last renumbering
+  double reorder_growth = 1.25;  // renumber when n grows by this factor (0 = never)
+  // insertion / renumbering / translation scratch
   int32_t* add = nullptr;
   int32_t* deg = nullptr;
   int32_t* pending = nullptr;
   float* hbuf = nullptr;
+  float* g2 = nullptr;
+  int32_t* parent2 = nullptr;
+  float* pcost2 = nullptr;
+  int32_t* ext2 = nullptr;
   // batch staging
   int64_t* brp = nullptr;
   int32_t* bcol = nullptr;
+  int32_t* bslot = nullptr;
   float* bcost = nullptr;
   int64_t brows_cap = 0, bnnz_cap = 0;
   void* scan_scratch = nullptr;
@@ -171,6 +187,22 @@ int ensure_scan(pirrt_graph* G, int64_t n) {
   return PIRRT_OK;
 }
 
+void free_vertex_arrays(pirrt_graph* G) {
+  dfree(G->rp); dfree(G->rp2); dfree(G->g); dfree(G->parent); dfree(G->pcost); dfree(G->child_cnt);
+  dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
+  dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf); dfree(G->ext_of); dfree(G->slot_of);
+  dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word);
+}
+
+void forget_vertex_arrays(pirrt_graph* T) {
+  T->rp = T->rp2 = nullptr;
+  T->g = T->pcost = T->hbuf = T->g2 = T->pcost2 = nullptr;
+  T->parent = T->child_cnt = T->child_ptr = T->child = T->fr0 = T->fr1 = T->lvl = nullptr;
+  T->add = T->deg = T->pending = T->ext_of = T->slot_of = T->parent2 = T->ext2 = nullptr;
+  T->stamp = nullptr;
+  T->word = nullptr;
+}
+
 // Grows every per-vertex array to hold `need` vertices, keeping g / parent / pcost
 // and the row offsets.  On failure nothing changes.
 int ensure_vcap(pirrt_graph* G, int64_t need) {
@@ -183,34 +215,38 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(&T.pcost, cap) && dalloc(&T.child_cnt, cap) && dalloc(&T.child_ptr, cap + 1) &&
             dalloc(&T.child, cap) && dalloc(&T.fr0, cap) && dalloc(&T.fr1, cap) &&
             dalloc(&T.lvl, cap + kMaxMidLaunches + 8) && dalloc(&T.stamp, cap) && dalloc(&T.add, cap) &&
-            dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap);
+            dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap) && dalloc(&T.ext_of, cap) &&
+            dalloc(&T.slot_of, cap) && dalloc(&T.g2, cap) && dalloc(&T.parent2, cap) && dalloc(&T.pcost2, cap) &&
+            dalloc(&T.ext2, cap) && dalloc(&T.word, cap);
   if (!ok) {
-    dfree(T.rp); dfree(T.rp2); dfree(T.g); dfree(T.parent); dfree(T.pcost); dfree(T.child_cnt);
-    dfree(T.child_ptr); dfree(T.child); dfree(T.fr0); dfree(T.fr1); dfree(T.lvl); dfree(T.stamp);
-    dfree(T.add); dfree(T.deg); dfree(T.pending); dfree(T.hbuf);
+    free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
   }
   hipStream_t s = G->stream;
   HIP_OR_FAIL(G, hipMemsetAsync(T.child_cnt, 0, sizeof(int32_t) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.stamp, 0, sizeof(uint32_t) * (size_t)cap, s));
+  HIP_OR_FAIL(G, hipMemsetAsync(T.word, 0, sizeof(unsigned long long) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.rp, 0, sizeof(int64_t) * (size_t)(cap + 1), s));
   if (G->n > 0) {
     HIP_OR_FAIL(G, hipMemcpyAsync(T.rp, G->rp, sizeof(int64_t) * (size_t)(G->n + 1), hipMemcpyDeviceToDevice, s));
     HIP_OR_FAIL(G, hipMemcpyAsync(T.g, G->g, sizeof(float) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
     HIP_OR_FAIL(G, hipMemcpyAsync(T.parent, G->parent, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
     HIP_OR_FAIL(G, hipMemcpyAsync(T.pcost, G->pcost, sizeof(float) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.ext_of, G->ext_of, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.slot_of, G->slot_of, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
   }
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
-  dfree(G->rp); dfree(G->rp2); dfree(G->g); dfree(G->parent); dfree(G->pcost); dfree(G->child_cnt);
-  dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
-  dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf);
+  free_vertex_arrays(G);
   G->rp = T.rp; G->rp2 = T.rp2; G->g = T.g; G->parent = T.parent; G->pcost = T.pcost;
   G->child_cnt = T.child_cnt; G->child_ptr = T.child_ptr; G->child = T.child; G->fr0 = T.fr0; G->fr1 = T.fr1;
   G->lvl = T.lvl; G->stamp = T.stamp; G->add = T.add; G->deg = T.deg; G->pending = T.pending; G->hbuf = T.hbuf;
-  T.rp = T.rp2 = nullptr; T.g = T.pcost = T.hbuf = nullptr; T.parent = T.child_cnt = T.child_ptr = T.child = nullptr;
-  T.fr0 = T.fr1 = T.lvl = T.add = T.deg = T.pending = nullptr; T.stamp = nullptr;
+  G->ext_of = T.ext_of; G->slot_of = T.slot_of; G->g2 = T.g2; G->parent2 = T.parent2; G->pcost2 = T.pcost2;
+  G->ext2 = T.ext2;
+  G->word = T.word;
+  forget_vertex_arrays(&T);
   G->vcap = cap;
   G->epoch = 0;
+  G->eval_epoch = 0;
   return ensure_scan(G, cap + 1);
 }
 
@@ -246,28 +282,32 @@ int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
   }
   if (nnz > G->bnnz_cap) {
     int32_t* c = nullptr;
+    int32_t* t = nullptr;
     float* w = nullptr;
     int64_t cap = nnz > 4096 ? nnz : 4096;
-    if (!dalloc(&c, cap) || !dalloc(&w, cap)) {
+    if (!dalloc(&c, cap) || !dalloc(&t, cap) || !dalloc(&w, cap)) {
       dfree(c);
+      dfree(t);
       dfree(w);
       return fail(G, PIRRT_ENOMEM, "device allocation for batch staging failed");
     }
     dfree(G->bcol);
+    dfree(G->bslot);
     dfree(G->bcost);
     G->bcol = c;
+    G->bslot = t;
     G->bcost = w;
-    G->bnnz_cap = nnz;
+    G->bnnz_cap = cap;
   }
   return PIRRT_OK;
 }
 
 void release_all(pirrt_graph* G) {
-  dfree(G->rp); dfree(G->col); dfree(G->cst); dfree(G->rp2); dfree(G->col2); dfree(G->cst2);
-  dfree(G->g); dfree(G->parent); dfree(G->pcost); dfree(G->sg); dfree(G->sparent); dfree(G->spcost);
-  dfree(G->child_cnt); dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl);
-  dfree(G->stamp); dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf);
-  dfree(G->brp); dfree(G->bcol); dfree(G->bcost); dfree(G->ctr); dfree(G->info); dfree(G->dflag); dfree(G->dcount);
+  free_vertex_arrays(G);
+  dfree(G->col); dfree(G->cst); dfree(G->col2); dfree(G->cst2);
+  dfree(G->sg); dfree(G->sparent); dfree(G->spcost);
+  dfree(G->brp); dfree(G->bcol); dfree(G->bslot); dfree(G->bcost);
+  dfree(G->ctr); dfree(G->info); dfree(G->dflag); dfree(G->dcount);
   if (G->scan_scratch) (void)hipFree(G->scan_scratch);
   G->scan_scratch = nullptr;
   if (G->host) (void)hipHostFree(G->host);
@@ -294,6 +334,92 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     return 0.0;
   }
   return (double)ms;
+}
+
+// Copies the policy out in caller order (device outputs are written directly;
+// host outputs go through device staging).
+int policy_out(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {
+  const int32_t n = (int32_t)G->n;
+  hipStream_t s = G->stream;
+  if (n == 0) return PIRRT_OK;
+  const bool dev = mem_kind == PIRRT_MEM_DEVICE;
+  float* gd = g_out ? (dev ? g_out : G->g2) : nullptr;
+  int32_t* pd = parent_out ? (dev ? parent_out : G->parent2) : nullptr;
+  float* cd = pcost_out ? (dev ? pcost_out : G->pcost2) : nullptr;
+  launch_policy_to_ext(n, G->slot_of, G->ext_of, G->g, G->parent, G->pcost, gd, pd, cd, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  if (!dev) {
+    if (g_out) HIP_OR_FAIL(G, hipMemcpyAsync(g_out, G->g2, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
+    if (parent_out)
+      HIP_OR_FAIL(G, hipMemcpyAsync(parent_out, G->parent2, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    if (pcost_out)
+      HIP_OR_FAIL(G, hipMemcpyAsync(pcost_out, G->pcost2, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
+  }
+  return PIRRT_OK;
+}
+
+// Renumbers the storage slots in breadth-first order of the graph from x_init
+// (vertex 0); vertices it cannot reach follow in their current order.
+int renumber(pirrt_graph* G) {
+  const int32_t n = (int32_t)G->n;
+  hipStream_t s = G->stream;
+  int rc;
+  if ((rc = ensure_spare(G, G->nnz))) return rc;
+  int32_t* visited = G->pending;
+  int32_t* order = G->fr0;
+  HIP_OR_FAIL(G, hipMemsetAsync(visited, 0, sizeof(int32_t) * (size_t)n, s));
+  launch_bfs_init(G->hslot[0], order, visited, &G->dcount[0], s);
+  int32_t lo = 0, hi = 1;
+  while (hi > lo) {
+    launch_graph_bfs_level(lo, hi, order, G->rp, G->col, visited, &G->dcount[0], s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[0], &G->dcount[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    lo = hi;
+    hi = G->host->count[0];
+    if (hi > n) return fail_device(G, hipErrorUnknown, "renumbering visited too many vertices");
+  }
+  launch_append_unvisited(n, visited, order, &G->dcount[0], s);
+  HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[0], &G->dcount[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  if (G->host->count[0] != n) return fail_device(G, hipErrorUnknown, "renumbering lost vertices");
+  PermuteArgs a;
+  a.n = n;
+  a.order = order;
+  a.newslot = G->fr1;
+  a.deg = G->deg;
+  a.rp = G->rp;
+  a.col = G->col;
+  a.cst = G->cst;
+  a.rp_new = G->rp2;
+  a.col_new = G->col2;
+  a.cst_new = G->cst2;
+  a.g = G->g;
+  a.parent = G->parent;
+  a.pcost = G->pcost;
+  a.ext_of = G->ext_of;
+  a.g2 = G->g2;
+  a.parent2 = G->parent2;
+  a.pcost2 = G->pcost2;
+  a.ext2 = G->ext2;
+  a.slot_of = G->slot_of;
+  a.scan_scratch = G->scan_scratch;
+  launch_permute(a, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  std::swap(G->rp, G->rp2);
+  std::swap(G->col, G->col2);
+  std::swap(G->cst, G->cst2);
+  std::swap(G->ecap, G->ecap2);
+  std::swap(G->g, G->g2);
+  std::swap(G->parent, G->parent2);
+  std::swap(G->pcost, G->pcost2);
+  std::swap(G->ext_of, G->ext2);
+  G->hslot.resize((size_t)n);
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->hslot.data(), G->slot_of, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  G->reorder_n = n;
+  G->snap_n = -1;  // a snapshot in the old order is no longer valid
+  return PIRRT_OK;
 }
 
 }  // namespace
@@ -388,6 +514,10 @@ int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg) {
     delete G;
     return PIRRT_EDEVICE;
   }
+  const char* growth = getenv("PIRRT_REORDER_GROWTH");
+  if (growth) G->reorder_growth = atof(growth);
+  const char* ev = getenv("PIRRT_EVALUATE");
+  if (ev && strcmp(ev, "levels") == 0) G->eval_levels = true;
   const char* variant = getenv("PIRRT_ROW_VARIANT");
   if (variant) {
     int v = atoi(variant);
@@ -466,8 +596,11 @@ int pirrt_insert_batch(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, co
   const int64_t n_old = G->n, n1 = G->n + n_new;
   if ((rc = ensure_vcap(G, n1))) return rc;
   if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) return rc;
+  // new vertices take the slots after the existing ones; neighbours to slots
+  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
+  launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
   // adjacency rebuild into the spare arrays, then swap
-  launch_rebuild(n_new, n_old, G->brp, G->bcol, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
+  launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
                  G->deg, G->scan_scratch, s);
   HIP_OR_FAIL(G, hipGetLastError());
   std::swap(G->rp, G->rp2);
@@ -476,6 +609,8 @@ int pirrt_insert_batch(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, co
   std::swap(G->ecap, G->ecap2);
   G->n = n1;
   G->nnz += 2 * nnz_b;
+  G->hslot.resize((size_t)n1);
+  for (int64_t v = n_old; v < n1; ++v) G->hslot[(size_t)v] = (int32_t)v;
   // insertion-time policy, one dependency level at a time
   HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 2 * sizeof(int32_t), s));
   launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
@@ -490,11 +625,14 @@ int pirrt_insert_batch(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, co
     done += size;
     if (done > n_new) return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
     HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
-    launch_insert_level(size, cur ? G->fr1 : G->fr0, n_old, G->brp, G->bcol, G->bcost, G->rp, G->col, G->g,
-                        G->parent, G->pcost, G->pending, nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
+    launch_insert_level(size, cur ? G->fr1 : G->fr0, n_old, G->brp, G->bcol, G->bslot, G->bcost, G->rp, G->col,
+                        G->g, G->parent, G->pcost, G->pending, nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
     HIP_OR_FAIL(G, hipGetLastError());
   }
   if (done != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
+  if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
+    if ((rc = renumber(G))) return rc;
+  }
   return PIRRT_OK;
 }
 
@@ -508,13 +646,15 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
   const int32_t n = (int32_t)G->n;
   hipStream_t s = G->stream;
+  const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   const float* hdev = nullptr;
   if (h) {
+    const float* hsrc = h;
     if (mem_kind == PIRRT_MEM_HOST) {
       for (int32_t v = 0; v < n; ++v)
         if (!(h[v] >= 0.0f)) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
-      HIP_OR_FAIL(G, hipMemcpyAsync(G->hbuf, h, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
-      hdev = G->hbuf;
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->g2, h, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+      hsrc = G->g2;
     } else {
       HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
       hipLaunchKernelGGL(k_check_h, dim3(grid_for(n)), dim3(256), 0, s, n, h, G->dflag);
@@ -522,8 +662,10 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
       int32_t bad = 0;
       if ((rc = read_flag(G, &bad))) return rc;
       if (bad) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
-      hdev = h;
     }
+    launch_gather_by_slot(n, G->ext_of, hsrc, G->hbuf, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    hdev = G->hbuf;
   }
   const bool timing = (flags & PIRRT_TIMING) != 0;
   const int64_t cap = G->max_iters > 0 ? G->max_iters : 4 * (int64_t)n + 8;
@@ -532,7 +674,7 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
 
   EvalArgs ea;
   ea.n = n;
-  ea.root = root;
+  ea.root = rslot;
   ea.parent = G->parent;
   ea.pcost = G->pcost;
   ea.g = G->g;
@@ -550,8 +692,8 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
 
   StepArgs sa;
   sa.n = n;
-  sa.root = root;
-  sa.goal = goal;
+  sa.root = rslot;
+  sa.goal = gslot;
   sa.prune = (flags & PIRRT_NO_PRUNE) ? 0 : 1;
   sa.g = G->g;
   sa.h = hdev;
@@ -559,6 +701,7 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   sa.col = G->col;
   sa.cst = G->cst;
   sa.stamp = G->stamp;
+  sa.ext_of = G->ext_of;
   sa.parent = G->parent;
   sa.pcost = G->pcost;
   sa.ctr = G->ctr;
@@ -570,13 +713,24 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
     if (mid > n) mid = n;
     ea.mid_launches = mid;
     if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[0], s));
-    launch_evaluate(ea, s);
+    if (G->eval_levels) {
+      launch_evaluate(ea, s);
+    } else {
+      if (++G->eval_epoch == 0) {
+        HIP_OR_FAIL(G, hipMemsetAsync(G->word, 0, sizeof(unsigned long long) * (size_t)G->vcap, s));
+        G->eval_epoch = 1;
+      }
+      launch_eval_walk(n, rslot, G->eval_epoch, G->parent, G->pcost, G->g, G->word, G->ctr, s);
+    }
     HIP_OR_FAIL(G, hipGetLastError());
     if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
     st.evaluate_calls += 1;
     return PIRRT_OK;
   };
 
+  // the root has no parent (Alg. 2 walks the policy tree from x_init)
+  HIP_OR_FAIL(G, hipMemsetAsync(G->parent + rslot, 0xff, sizeof(int32_t), s));
+  HIP_OR_FAIL(G, hipMemsetAsync(G->pcost + rslot, 0, sizeof(float), s));
   if ((rc = evaluate())) return rc;
   bool pending_eval_time = timing;
   for (;;) {
@@ -622,9 +776,11 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
       break;
     }
   }
-  if (g_out) HIP_OR_FAIL(G, hipMemcpyAsync(g_out, G->g, sizeof(float) * (size_t)n, out_kind(mem_kind), s));
-  if (parent_out)
-    HIP_OR_FAIL(G, hipMemcpyAsync(parent_out, G->parent, sizeof(int32_t) * (size_t)n, out_kind(mem_kind), s));
+  if ((rc == PIRRT_OK || rc == PIRRT_ENOTCONVERGED) && (g_out || parent_out)) {
+    const int keep = rc;
+    if ((rc = policy_out(G, g_out, parent_out, nullptr, mem_kind))) return rc;
+    rc = keep;
+  }
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   if (timing && pending_eval_time) st.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
   st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -637,14 +793,8 @@ int pirrt_get_policy(pirrt_graph* G, float* g_out, int32_t* parent_out, float* p
   int rc = guard(G);
   if (rc) return rc;
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
-  const size_t n = (size_t)G->n;
-  hipStream_t s = G->stream;
-  if (n > 0) {
-    if (g_out) HIP_OR_FAIL(G, hipMemcpyAsync(g_out, G->g, sizeof(float) * n, out_kind(mem_kind), s));
-    if (parent_out) HIP_OR_FAIL(G, hipMemcpyAsync(parent_out, G->parent, sizeof(int32_t) * n, out_kind(mem_kind), s));
-    if (pcost_out) HIP_OR_FAIL(G, hipMemcpyAsync(pcost_out, G->pcost, sizeof(float) * n, out_kind(mem_kind), s));
-  }
-  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  if ((rc = policy_out(G, g_out, parent_out, pcost_out, mem_kind))) return rc;
+  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   return PIRRT_OK;
 }
 
@@ -672,9 +822,19 @@ int pirrt_set_policy(pirrt_graph* G, const float* g_in, const int32_t* parent_in
     if ((rc = read_flag(G, &bad))) return rc;
     if (bad) return fail(G, PIRRT_EINVAL, "bad parent or pcost");
   }
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->g, g_in, sizeof(float) * (size_t)n, in_kind(mem_kind), s));
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->parent, parent_in, sizeof(int32_t) * (size_t)n, in_kind(mem_kind), s));
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost, pcost_in, sizeof(float) * (size_t)n, in_kind(mem_kind), s));
+  const float* gs = g_in;
+  const int32_t* ps = parent_in;
+  const float* cs = pcost_in;
+  if (mem_kind == PIRRT_MEM_HOST) {
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->g2, g_in, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->parent2, parent_in, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost2, pcost_in, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+    gs = G->g2;
+    ps = G->parent2;
+    cs = G->pcost2;
+  }
+  launch_policy_from_ext(n, G->slot_of, gs, ps, cs, G->g, G->parent, G->pcost, s);
+  HIP_OR_FAIL(G, hipGetLastError());
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   return PIRRT_OK;
 }
@@ -732,12 +892,32 @@ int pirrt_get_adjacency(pirrt_graph* G, int64_t* ptr, int32_t* nbr, float* cost,
   if (rc) return rc;
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
   hipStream_t s = G->stream;
-  if (ptr) HIP_OR_FAIL(G, hipMemcpyAsync(ptr, G->rp, sizeof(int64_t) * (size_t)(G->n + 1), out_kind(mem_kind), s));
-  if (G->nnz > 0) {
-    if (nbr) HIP_OR_FAIL(G, hipMemcpyAsync(nbr, G->col, sizeof(int32_t) * (size_t)G->nnz, out_kind(mem_kind), s));
-    if (cost) HIP_OR_FAIL(G, hipMemcpyAsync(cost, G->cst, sizeof(float) * (size_t)G->nnz, out_kind(mem_kind), s));
+  const size_t n = (size_t)G->n, m = (size_t)G->nnz;
+  // translated on the host: rows in caller order, neighbours as caller ids
+  std::vector<int64_t> rp(n + 1), out_ptr(n + 1);
+  std::vector<int32_t> col(m), ext(n), out_col(m);
+  std::vector<float> cst(m), out_cst(m);
+  HIP_OR_FAIL(G, hipMemcpyAsync(rp.data(), G->rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  if (m) {
+    HIP_OR_FAIL(G, hipMemcpyAsync(col.data(), G->col, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(cst.data(), G->cst, sizeof(float) * m, hipMemcpyDeviceToHost, s));
   }
+  if (n) HIP_OR_FAIL(G, hipMemcpyAsync(ext.data(), G->ext_of, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  out_ptr[0] = 0;
+  for (size_t e = 0; e < n; ++e) {
+    const size_t sl = (size_t)G->hslot[e];
+    int64_t k = out_ptr[e];
+    for (int64_t j = rp[sl]; j < rp[sl + 1]; ++j, ++k) {
+      out_col[(size_t)k] = ext[(size_t)col[(size_t)j]];
+      out_cst[(size_t)k] = cst[(size_t)j];
+    }
+    out_ptr[e + 1] = k;
+  }
+  const hipMemcpyKind kind = mem_kind == PIRRT_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  if (ptr) HIP_OR_FAIL(G, hipMemcpy(ptr, out_ptr.data(), sizeof(int64_t) * (n + 1), kind));
+  if (m && nbr) HIP_OR_FAIL(G, hipMemcpy(nbr, out_col.data(), sizeof(int32_t) * m, kind));
+  if (m && cost) HIP_OR_FAIL(G, hipMemcpy(cost, out_cst.data(), sizeof(float) * m, kind));
   return PIRRT_OK;
 }
 

@@ -55,34 +55,34 @@ __device__ __forceinline__ int wave_reserve(int* counter, int count) {
   return base + off;
 }
 
-// Lexicographic (key, cost) minimum, key = (binary32 bits of the candidate << 32 |
-// neighbour id).  All candidates are >= +0, so the bit patterns order like the
-// values; +inf stays above every finite candidate.
-struct Cand {
-  unsigned long long key;
-  uint32_t cbits;
-};
-
-__device__ __forceinline__ void cand_min(Cand& a, unsigned long long k, uint32_t c) {
-  if (k < a.key || (k == a.key && c < a.cbits)) {
-    a.key = k;
-    a.cbits = c;
-  }
-}
-
-// Butterfly minimum over groups of `width` consecutive lanes (width a power of
-// two <= 64); every lane of the group ends with the group minimum.
+// Minimum over groups of `width` consecutive lanes (width a power of two <= 64);
+// every lane of the group ends with the group minimum.
 template <int width>
-__device__ __forceinline__ Cand group_min(Cand a) {
+__device__ __forceinline__ uint32_t group_min_u32(uint32_t x) {
 #pragma unroll
   for (int off = width / 2; off > 0; off >>= 1) {
-    uint32_t lo = (uint32_t)a.key, hi = (uint32_t)(a.key >> 32);
-    uint32_t olo = __shfl_xor(lo, off, kWave);
-    uint32_t ohi = __shfl_xor(hi, off, kWave);
-    uint32_t oc = __shfl_xor(a.cbits, off, kWave);
-    cand_min(a, ((unsigned long long)ohi << 32) | olo, oc);
+    uint32_t y = __shfl_xor(x, off, kWave);
+    x = y < x ? y : x;
   }
-  return a;
+  return x;
+}
+
+template <int width>
+__device__ __forceinline__ unsigned long long group_min_u64(unsigned long long x) {
+#pragma unroll
+  for (int off = width / 2; off > 0; off >>= 1) {
+    uint32_t lo = __shfl_xor((uint32_t)x, off, kWave);
+    uint32_t hi = __shfl_xor((uint32_t)(x >> 32), off, kWave);
+    unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// Bits [grp*width, grp*width + width) of a wave-wide ballot, as the low bits.
+template <int width>
+__device__ __forceinline__ unsigned long long group_bits(unsigned long long ballot, int grp) {
+  return width == 64 ? ballot : (ballot >> (grp * width)) & ((1ull << width) - 1ull);
 }
 
 }  // namespace pirrt

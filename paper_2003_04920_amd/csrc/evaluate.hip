@@ -11,6 +11,9 @@
 // an exclusive scan and a scatter.  The scatter pops the counts back to zero, so
 // the count array never needs clearing.
 //
+// Two evaluators compute the same values.  The default (k_eval_walk, below) needs
+// one launch.  The level-synchronous one is kept as an independent check:
+//
 // The walk is level synchronous.  Tree levels near the root and near the leaves
 // are small, the ones in between large (tens of thousands of vertices for a
 // million-vertex tree), so three kernels share it:
@@ -183,7 +186,98 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
   }
 }
 
+// ---------------------------------------------------------------------------
+// Walk evaluation: one launch, no level barriers.
+//
+// Each vertex v walks up its parent chain until it meets a vertex whose value of
+// this Evaluate is already known (a 64-bit word {epoch, g bits} stamped with the
+// current epoch), the root (g = 0), or a vertex without parent that is not the
+// root (the chain is detached: +inf).  It then folds the recorded path downward,
+// g(x) = g(parent x) + pcost(x) one binary32 addition at a time -- exactly the
+// additions, in exactly the order, of the breadth-first walk -- and stamps every
+// vertex it computed.  Threads that meet each other's stamps stop early; stamps
+// that are not yet visible only cost extra walking, never a wrong value, because
+// any word carrying the current epoch holds the final value of its vertex.
+//
+// The path is kept in a ring of kRing slots per thread in LDS; a longer path folds
+// its top kRing vertices, stamps them and walks again from v (which now stops
+// there).  A walk longer than n hops can only be a parent cycle away from the
+// root; its vertices are unreachable and get +inf.
+constexpr int kWalkThreads = 256;
+constexpr int kRing = 16;
+
+__device__ __forceinline__ unsigned long long load_word(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_word(unsigned long long* p, unsigned long long w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t n, int32_t root, uint32_t epoch,
+                                                           const int32_t* __restrict__ parent,
+                                                           const float* __restrict__ pcost, float* __restrict__ g,
+                                                           unsigned long long* __restrict__ word,
+                                                           IterCounters* __restrict__ ctr) {
+  __shared__ int32_t ring_v[kRing][kWalkThreads];
+  __shared__ float ring_c[kRing][kWalkThreads];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // fresh counters for the promising-set / Improve pass that follows
+    ctr->changed = 0;
+    ctr->nP = 0;
+    ctr->nD = 0;
+    ctr->edges = 0ull;
+  }
+  if (v >= n) return;
+  const unsigned long long tag = (unsigned long long)epoch << 32;
+  for (;;) {
+    int32_t u = (int32_t)v;
+    int64_t k = 0;
+    uint32_t top;  // g bits above the recorded path
+    for (;;) {
+      // the stamp, parent and parent-edge cost of u in one round trip
+      const unsigned long long w = load_word(&word[u]);
+      const int32_t p = parent[u];
+      const float c = pcost[u];
+      if ((w & 0xffffffff00000000ull) == tag) {
+        top = (uint32_t)w;
+        break;
+      }
+      if (u == root) {
+        top = 0u;
+        store_word(&word[u], tag);
+        g[u] = 0.0f;
+        break;
+      }
+      ring_v[k % kRing][threadIdx.x] = u;
+      ring_c[k % kRing][threadIdx.x] = c;
+      ++k;
+      if (p < 0 || k > n) {  // detached chain (or a cycle): unreachable
+        top = 0x7f800000u;
+        break;
+      }
+      u = p;
+    }
+    const int64_t stop = k > kRing ? k - kRing : 0;
+    float acc = __uint_as_float(top);
+    for (int64_t i = k - 1; i >= stop; --i) {
+      const int32_t x = ring_v[i % kRing][threadIdx.x];
+      acc = add_rn(acc, ring_c[i % kRing][threadIdx.x]);
+      store_word(&word[x], tag | __float_as_uint(acc));
+      g[x] = acc;
+    }
+    if (stop == 0) break;
+  }
+}
+
 }  // namespace
+
+void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
+                      unsigned long long* word, IterCounters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_eval_walk, dim3(blocks_for(n, kWalkThreads)), dim3(kWalkThreads), 0, s, n, root, epoch,
+                     parent, pcost, g, word, ctr);
+}
 
 void launch_evaluate(const EvalArgs& a, hipStream_t s) {
   const int32_t n = a.n;

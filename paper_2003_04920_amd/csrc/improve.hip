@@ -4,7 +4,8 @@
 //           pruning).  Every v of P and every neighbour of v is stamped with the
 //           iteration's epoch, which makes D = P u N(P) without a clearing pass.
 // improve : for every stamped v other than the root, the lexicographic minimum of
-//           (g(n) + c(n, v), n, c) over v's row; the parent switches only when
+//           (g(n) + c(n, v), n, c) over v's row, n being the caller's vertex id
+//           (storage slots may be renumbered); the parent switches only when
 //           that value is strictly below g(v).  g is only read (Jacobi step), so
 //           all rows are independent.
 //
@@ -53,14 +54,16 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, int32_t goal, int 
     const int idx = r + grp;
     if (idx < cnt) {
       const int32_t u = members[wid][idx];
-      const int64_t a = rp[u], b = rp[u + 1];
+      const int64_t a = rp[u], b = rp[u + 1];  // (mark: rows of P only)
       for (int64_t j = a + gl; j < b; j += GW * U) {
+        // every load is issued unconditionally (clamped to an entry of the row) so
+        // the U loads of a lane are in flight together
         int32_t w[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) w[q] = (j + q * GW < b) ? col[j + q * GW] : -1;
+        for (int q = 0; q < U; ++q) w[q] = col[j + q * GW < b ? j + q * GW : a];
 #pragma unroll
         for (int q = 0; q < U; ++q)
-          if (w[q] >= 0) stamp[w[q]] = epoch;
+          if (j + q * GW < b) stamp[w[q]] = epoch;
       }
     }
   }
@@ -71,8 +74,9 @@ template <int GW, int U>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, int32_t root, const float* __restrict__ g,
                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      const float* __restrict__ cst, const uint32_t* __restrict__ stamp,
-                                                     uint32_t epoch, int32_t* __restrict__ parent,
-                                                     float* __restrict__ pcost, IterCounters* __restrict__ ctr) {
+                                                     uint32_t epoch, const int32_t* __restrict__ ext_of,
+                                                     int32_t* __restrict__ parent, float* __restrict__ pcost,
+                                                     IterCounters* __restrict__ ctr) {
   __shared__ int32_t members[kWavesPerBlock][kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t v = ((int64_t)blockIdx.x * kWavesPerBlock + wid) * kWave + lane;
@@ -88,36 +92,61 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, int32_t root, c
   for (int r = 0; r < cnt; r += R) {
     const int idx = r + grp;
     const bool act = idx < cnt;
-    const int32_t x = act ? members[wid][idx] : 0;
-    const int64_t a = act ? rp[x] : 0, b = act ? rp[x + 1] : 0;
-    Cand best;
-    best.key = ~0ull;
-    best.cbits = ~0u;
+    const int32_t x = members[wid][act ? idx : 0];
+    const int64_t ra = rp[x], rb = rp[x + 1];
+    const int64_t a = act ? ra : 0, b = act ? rb : 0;
+    // lane-local minimum of (g(u) + c, caller id of u, c); bu = slot of u
+    uint32_t bv = 0xffffffffu, bc = 0xffffffffu;
+    int32_t bu = -1;
     for (int64_t j = a + gl; j < b; j += GW * U) {
+      // loads are unconditional (entries past the row end re-read entry a and are
+      // masked below): one wait for the U entries, one for their U gathers
       int32_t u[U];
       float c[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const bool ok = j + q * GW < b;
-        u[q] = ok ? col[j + q * GW] : -1;
-        c[q] = ok ? cst[j + q * GW] : 0.0f;
+        const int64_t jj = j + q * GW < b ? j + q * GW : a;
+        u[q] = col[jj];
+        c[q] = cst[jj];
       }
       float gu[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) gu[q] = u[q] >= 0 ? g[u[q]] : 0.0f;
+      for (int q = 0; q < U; ++q) gu[q] = g[u[q]];
 #pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (u[q] >= 0)
-          cand_min(best, ((unsigned long long)__float_as_uint(add_rn(gu[q], c[q])) << 32) | (uint32_t)u[q],
-                   __float_as_uint(c[q]));
+      for (int q = 0; q < U; ++q) {
+        if (j + q * GW >= b) continue;
+        const uint32_t vb = __float_as_uint(add_rn(gu[q], c[q])), cb = __float_as_uint(c[q]);
+        if (vb >= 0x7f800000u) continue;  // +inf never improves anything
+        if (vb < bv) {
+          bv = vb;
+          bu = u[q];
+          bc = cb;
+        } else if (vb == bv) {  // equal candidates within one lane: rare
+          const int32_t e1 = ext_of[u[q]], e0 = ext_of[bu];
+          if (e1 < e0 || (e1 == e0 && cb < bc)) {
+            bu = u[q];
+            bc = cb;
+          }
+        }
+      }
     }
-    best = group_min<GW>(best);
+    // group minimum: value first; the caller id is fetched only for real ties
+    const uint32_t mv = group_min_u32<GW>(bv);
+    const bool tied = bu >= 0 && bv == mv;
+    const unsigned long long tb = group_bits<GW>(__ballot(tied), grp);
+    const bool multi = __popcll(tb) > 1;
+    const uint32_t e = tied ? (multi ? (uint32_t)ext_of[bu] : 0u) : 0xffffffffu;
+    const unsigned long long k2 = ((unsigned long long)e << 32) | (tied ? bc : 0xffffffffu);
+    const unsigned long long m2 = group_min_u64<GW>(k2);
+    const unsigned long long wb = group_bits<GW>(__ballot(tied && k2 == m2), grp);
+    const int src = grp * GW + (wb ? __ffsll((long long)wb) - 1 : 0);
+    const int32_t wu = __shfl(bu, src, kWave);
+    const uint32_t wc = __shfl(bc, src, kWave);
     if (act && gl == 0) {
       edges += (unsigned long long)(b - a);
-      const float m = __uint_as_float((uint32_t)(best.key >> 32));
-      if (best.key != ~0ull && m < g[x]) {
-        parent[x] = (int32_t)(uint32_t)best.key;
-        pcost[x] = __uint_as_float(best.cbits);
+      if (wb != 0 && __uint_as_float(mv) < g[x]) {
+        parent[x] = wu;
+        pcost[x] = __uint_as_float(wc);
         ++changed;
       }
     }
@@ -150,7 +179,7 @@ void launch_improve_t(const StepArgs& a, hipStream_t s) {
   const int64_t chunks = ((int64_t)a.n + kWave - 1) / kWave;
   const unsigned blocks = (unsigned)((chunks + kWavesPerBlock - 1) / kWavesPerBlock);
   hipLaunchKernelGGL((k_improve<GW, U>), dim3(blocks > 0 ? blocks : 1), dim3(kThreads), 0, s, a.n, a.root, a.g,
-                     a.rp, a.col, a.cst, a.stamp, a.epoch, a.parent, a.pcost, a.ctr);
+                     a.rp, a.col, a.cst, a.stamp, a.epoch, a.ext_of, a.parent, a.pcost, a.ctr);
 }
 
 }  // namespace

@@ -19,10 +19,48 @@ void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
                     hipStream_t s);
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s);
+// bcol: neighbour ids as given (tie-break keys); bslot: the same in storage slots.
 void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
-                         const int32_t* bcol, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
-                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
-                         hipStream_t s);
+                         const int32_t* bcol, const int32_t* bslot, const float* bcost, const int64_t* rp,
+                         const int32_t* col, float* g, int32_t* parent, float* pcost, int32_t* pending,
+                         int32_t* next, int32_t* ncount, hipStream_t s);
+
+// ---- reorder.hip ----
+struct PermuteArgs {
+  int32_t n;
+  const int32_t* order;    // order[k] = old slot of new slot k
+  int32_t* newslot;        // out: new slot of each old slot
+  int32_t* deg;            // scratch, n
+  const int64_t* rp;
+  const int32_t* col;
+  const float* cst;
+  int64_t* rp_new;
+  int32_t* col_new;
+  float* cst_new;
+  const float* g;
+  const int32_t* parent;
+  const float* pcost;
+  const int32_t* ext_of;
+  float* g2;
+  int32_t* parent2;
+  float* pcost2;
+  int32_t* ext2;
+  int32_t* slot_of;        // updated in place
+  void* scan_scratch;
+};
+void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
+void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s);
+void launch_bfs_init(int32_t root, int32_t* order, int32_t* visited, int32_t* count, hipStream_t s);
+void launch_graph_bfs_level(int32_t lo, int32_t hi, int32_t* order, const int64_t* rp, const int32_t* col,
+                            int32_t* visited, int32_t* count, hipStream_t s);
+void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, int32_t* count, hipStream_t s);
+void launch_permute(const PermuteArgs& a, hipStream_t s);
+void launch_gather_by_slot(int32_t n, const int32_t* ext_of, const float* src_ext, float* dst_slot, hipStream_t s);
+void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const float* g,
+                          const int32_t* parent, const float* pcost, float* g_ext, int32_t* parent_ext,
+                          float* pcost_ext, hipStream_t s);
+void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const float* g_ext, const int32_t* parent_ext,
+                            const float* pcost_ext, float* g, int32_t* parent, float* pcost, hipStream_t s);
 
 // ---- evaluate.hip ----
 struct EvalArgs {
@@ -45,6 +83,9 @@ struct EvalArgs {
 };
 constexpr int32_t kMaxMidLaunches = 1024;
 void launch_evaluate(const EvalArgs& a, hipStream_t s);
+// word: n 64-bit {epoch, g bits} stamps; epochs of earlier calls must be smaller.
+void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
+                      unsigned long long* word, IterCounters* ctr, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
@@ -59,6 +100,7 @@ struct StepArgs {
   const float* cst;
   uint32_t* stamp;
   uint32_t epoch;
+  const int32_t* ext_of;  // caller id of each slot (tie-break key)
   int32_t* parent;
   float* pcost;
   IterCounters* ctr;

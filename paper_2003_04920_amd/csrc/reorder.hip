@@ -1,0 +1,222 @@
+// Vertex storage order.
+//
+// The library keeps every per-vertex array and the adjacency in an internal
+// order ("slots") and translates at the ABI: ext_of[slot] is the caller's vertex
+// id, slot_of[id] its slot.  Results never depend on the order: every minimum
+// breaks ties on the caller's ids, and Evaluate's sums do not depend on where a
+// vertex is stored.
+//
+// Why: Improve gathers g of every neighbour of every domain vertex.  With ids in
+// sampling order the neighbours of a vertex are scattered over the whole g array
+// and nearly every 4-byte gather costs a cache line from the MALL or HBM.  After a
+// breadth-first renumbering of the graph from x_init, neighbours sit a few BFS
+// levels apart, so the rows of consecutive slots gather from a window of g that
+// stays in the XCD's L2; the policy tree (close to a shortest-path tree) inherits
+// the same locality, which helps Evaluate and the promising-set marks too.
+//
+// New vertices are appended after the existing slots; the whole graph is
+// renumbered again when it has grown enough since the last renumbering.
+#include "internal.h"
+
+namespace pirrt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_identity_ids(int64_t lo, int64_t hi, int32_t* __restrict__ ext_of,
+                                                          int32_t* __restrict__ slot_of) {
+  int64_t s = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= hi) return;
+  ext_of[s] = (int32_t)s;
+  slot_of[s] = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_translate(int64_t m, const int32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ slot_of,
+                                                       int32_t* __restrict__ out) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) out[j] = slot_of[ids[j]];
+}
+
+__global__ void k_bfs_init(int32_t root, int32_t* __restrict__ order, int32_t* __restrict__ visited,
+                           int32_t* __restrict__ count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    order[0] = root;
+    visited[root] = 1;
+    *count = 1;
+  }
+}
+
+// One breadth-first level over the graph: order[lo, hi) is the frontier; newly
+// reached vertices are appended to order[] (the queue is the new storage order).
+__global__ void __launch_bounds__(kThreads) k_graph_bfs_level(int32_t lo, int32_t hi, int32_t* __restrict__ order,
+                                                             const int64_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ col,
+                                                             int32_t* __restrict__ visited,
+                                                             int32_t* __restrict__ count) {
+  int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hi) return;
+  const int32_t u = order[t];
+  for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
+    const int32_t w = col[j];
+    if (visited[w] == 0 && atomicExch(&visited[w], 1) == 0) order[atomicAdd(count, 1)] = w;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_append_unvisited(int32_t n, const int32_t* __restrict__ visited,
+                                                              int32_t* __restrict__ order, int32_t* __restrict__ count) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int take = (s < n && visited[s] == 0) ? 1 : 0;
+  const int slot = wave_reserve(count, take);
+  if (take) order[slot] = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_invert(int32_t n, const int32_t* __restrict__ order,
+                                                    int32_t* __restrict__ newslot, const int64_t* __restrict__ rp,
+                                                    int32_t* __restrict__ deg) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t o = order[k];
+  newslot[o] = (int32_t)k;
+  deg[k] = (int32_t)(rp[o + 1] - rp[o]);
+}
+
+// Row k of the new adjacency is old row order[k] with its neighbours renamed.
+__global__ void __launch_bounds__(kThreads) k_permute_rows(int32_t n, const int32_t* __restrict__ order,
+                                                          const int32_t* __restrict__ newslot,
+                                                          const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const float* __restrict__ cst,
+                                                          const int64_t* __restrict__ rp_new,
+                                                          int32_t* __restrict__ col_new, float* __restrict__ cst_new) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (k >= n) return;
+  const int32_t o = order[k];
+  const int64_t a = rp[o], b = rp[o + 1], dst = rp_new[k];
+  for (int64_t j = a + lane; j < b; j += kWave) {
+    col_new[dst + (j - a)] = newslot[col[j]];
+    cst_new[dst + (j - a)] = cst[j];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_permute_vertices(int32_t n, const int32_t* __restrict__ order,
+                                                              const int32_t* __restrict__ newslot,
+                                                              const float* __restrict__ g,
+                                                              const int32_t* __restrict__ parent,
+                                                              const float* __restrict__ pcost,
+                                                              const int32_t* __restrict__ ext_of,
+                                                              float* __restrict__ g2, int32_t* __restrict__ parent2,
+                                                              float* __restrict__ pcost2, int32_t* __restrict__ ext2,
+                                                              int32_t* __restrict__ slot_of) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t o = order[k];
+  g2[k] = g[o];
+  const int32_t p = parent[o];
+  parent2[k] = p >= 0 ? newslot[p] : -1;
+  pcost2[k] = pcost[o];
+  const int32_t e = ext_of[o];
+  ext2[k] = e;
+  slot_of[e] = (int32_t)k;
+}
+
+__global__ void __launch_bounds__(kThreads) k_gather_by_slot(int32_t n, const int32_t* __restrict__ ext_of,
+                                                            const float* __restrict__ src_ext,
+                                                            float* __restrict__ dst_slot) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) dst_slot[s] = src_ext[ext_of[s]];
+}
+
+__global__ void __launch_bounds__(kThreads) k_policy_to_ext(int32_t n, const int32_t* __restrict__ slot_of,
+                                                           const int32_t* __restrict__ ext_of,
+                                                           const float* __restrict__ g,
+                                                           const int32_t* __restrict__ parent,
+                                                           const float* __restrict__ pcost, float* __restrict__ g_ext,
+                                                           int32_t* __restrict__ parent_ext,
+                                                           float* __restrict__ pcost_ext) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t s = slot_of[e];
+  if (g_ext) g_ext[e] = g[s];
+  if (parent_ext) {
+    const int32_t p = parent[s];
+    parent_ext[e] = p >= 0 ? ext_of[p] : -1;
+  }
+  if (pcost_ext) pcost_ext[e] = pcost[s];
+}
+
+__global__ void __launch_bounds__(kThreads) k_policy_from_ext(int32_t n, const int32_t* __restrict__ slot_of,
+                                                             const float* __restrict__ g_ext,
+                                                             const int32_t* __restrict__ parent_ext,
+                                                             const float* __restrict__ pcost_ext,
+                                                             float* __restrict__ g, int32_t* __restrict__ parent,
+                                                             float* __restrict__ pcost) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t s = slot_of[e];
+  g[s] = g_ext[e];
+  const int32_t p = parent_ext[e];
+  parent[s] = p >= 0 ? slot_of[p] : -1;
+  pcost[s] = pcost_ext[e];
+}
+
+}  // namespace
+
+void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s) {
+  if (hi > lo)
+    hipLaunchKernelGGL(k_identity_ids, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, ext_of, slot_of);
+}
+
+void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_translate, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, ids, slot_of, out);
+}
+
+void launch_bfs_init(int32_t root, int32_t* order, int32_t* visited, int32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, root, order, visited, count);
+}
+
+void launch_graph_bfs_level(int32_t lo, int32_t hi, int32_t* order, const int64_t* rp, const int32_t* col,
+                            int32_t* visited, int32_t* count, hipStream_t s) {
+  if (hi > lo)
+    hipLaunchKernelGGL(k_graph_bfs_level, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, order, rp, col,
+                       visited, count);
+}
+
+void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, int32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_append_unvisited, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, visited, order, count);
+}
+
+void launch_permute(const PermuteArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_invert, dim3(blocks_for(a.n)), dim3(kThreads), 0, s, a.n, a.order, a.newslot, a.rp, a.deg);
+  scan_i32_to_i64(a.deg, a.n, a.rp_new, a.scan_scratch, s);
+  hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((int64_t)a.n * kWave)), dim3(kThreads), 0, s, a.n, a.order,
+                     a.newslot, a.rp, a.col, a.cst, a.rp_new, a.col_new, a.cst_new);
+  hipLaunchKernelGGL(k_permute_vertices, dim3(blocks_for(a.n)), dim3(kThreads), 0, s, a.n, a.order, a.newslot, a.g,
+                     a.parent, a.pcost, a.ext_of, a.g2, a.parent2, a.pcost2, a.ext2, a.slot_of);
+}
+
+void launch_gather_by_slot(int32_t n, const int32_t* ext_of, const float* src_ext, float* dst_slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_by_slot, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, ext_of, src_ext, dst_slot);
+}
+
+void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const float* g,
+                          const int32_t* parent, const float* pcost, float* g_ext, int32_t* parent_ext,
+                          float* pcost_ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_policy_to_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, ext_of, g, parent,
+                     pcost, g_ext, parent_ext, pcost_ext);
+}
+
+void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const float* g_ext, const int32_t* parent_ext,
+                            const float* pcost_ext, float* g, int32_t* parent, float* pcost, hipStream_t s) {
+  hipLaunchKernelGGL(k_policy_from_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, g_ext, parent_ext,
+                     pcost_ext, g, parent, pcost);
+}
+
+}  // namespace pirrt

@@ -2,9 +2,10 @@
 // Extend's insertion-time policy for the new vertices (Sec. III local relaxation;
 // Sec. IV-A cached edge costs).
 //
-// The adjacency is one CSR over all vertices: int64 row offsets and, per entry, an
-// int32 neighbour id and a binary32 cost in two parallel arrays.  A batch arrives as forward rows (each new vertex
-// lists its lower-index neighbours).  Appending rebuilds the CSR into a spare
+// The adjacency is one CSR over all vertex slots: int64 row offsets and, per entry,
+// an int32 neighbour slot and a binary32 cost in two parallel arrays.  A batch
+// arrives as forward rows (each new vertex lists its lower-index neighbours),
+// translated to slots before it gets here.  Appending rebuilds the CSR into a spare
 // buffer in one streaming pass: every row keeps its old entries, a new vertex's
 // row starts with its forward entries, and each forward edge (v, u) is mirrored
 // into u's row.  Entry order inside a row is not fixed (mirrors are placed with
@@ -137,10 +138,13 @@ __global__ void __launch_bounds__(kThreads) k_pending(int32_t n_new, int64_t n_o
 }
 
 // One dependency level of the insertion-time policy: every vertex of the frontier
-// has all its lower neighbours final, so its local relaxation is final too.
+// has all its lower neighbours final, so its local relaxation is final too.  The
+// minimum is over (g(u) + c, u, c) with u the caller's id (bcol); g is read at the
+// storage slot (bslot).  New vertices occupy slots equal to their ids.
 __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const int32_t* __restrict__ frontier,
                                                           int64_t n_old, const int64_t* __restrict__ brp,
                                                           const int32_t* __restrict__ bcol,
+                                                          const int32_t* __restrict__ bslot,
                                                           const float* __restrict__ bcost,
                                                           const int64_t* __restrict__ rp,
                                                           const int32_t* __restrict__ col, float* __restrict__ g,
@@ -148,50 +152,43 @@ __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const 
                                                           int32_t* __restrict__ pending,
                                                           int32_t* __restrict__ next, int32_t* __restrict__ ncount) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t v = t < fsize ? frontier[t] : -1;
-  if (v >= 0) {
-    int64_t i = v - n_old;
-    int64_t a = brp[i], b = brp[i + 1];
-    if (v == 0) {
-      g[0] = 0.0f;
-      parent[0] = -1;
-      pcost[0] = 0.0f;
+  if (t >= fsize) return;
+  const int32_t v = frontier[t];
+  const int64_t i = v - n_old;
+  const int64_t a = brp[i], b = brp[i + 1];
+  if (v == 0) {
+    g[0] = 0.0f;
+    parent[0] = -1;
+    pcost[0] = 0.0f;
+  } else {
+    uint32_t bv = 0xffffffffu, bc = 0xffffffffu;
+    int32_t be = 0x7fffffff;
+    int64_t bj = -1;
+    for (int64_t j = a; j < b; ++j) {
+      const int32_t u = bcol[j];
+      const float c = bcost[j];
+      const uint32_t vb = __float_as_uint(add_rn(g[bslot[j]], c)), cb = __float_as_uint(c);
+      if (vb < bv || (vb == bv && (u < be || (u == be && cb < bc)))) {
+        bv = vb;
+        be = u;
+        bc = cb;
+        bj = j;
+      }
+    }
+    if (bj >= 0 && bv < 0x7f800000u) {
+      g[v] = __uint_as_float(bv);
+      parent[v] = bslot[bj];
+      pcost[v] = __uint_as_float(bc);
     } else {
-      Cand best;
-      best.key = ~0ull;
-      best.cbits = ~0u;
-      for (int64_t j = a; j < b; ++j) {
-        int32_t u = bcol[j];
-        float c = bcost[j];
-        float val = add_rn(g[u], c);
-        cand_min(best, ((unsigned long long)__float_as_uint(val) << 32) | (uint32_t)u, __float_as_uint(c));
-      }
-      uint32_t vb = (uint32_t)(best.key >> 32);
-      if (best.key != ~0ull && vb < 0x7f800000u) {
-        g[v] = __uint_as_float(vb);
-        parent[v] = (int32_t)(uint32_t)best.key;
-        pcost[v] = __uint_as_float(best.cbits);
-      } else {
-        g[v] = pos_inf();
-        parent[v] = -1;
-        pcost[v] = 0.0f;
-      }
+      g[v] = pos_inf();
+      parent[v] = -1;
+      pcost[v] = 0.0f;
     }
   }
   // release the same-batch higher neighbours (the mirror part of v's row)
-  int64_t ma = 0, mb = 0;
-  if (v >= 0) {
-    int64_t i = v - n_old;
-    ma = rp[v] + (brp[i + 1] - brp[i]);
-    mb = rp[v + 1];
-  }
-  for (int64_t j = ma; j < mb; ++j) {
-    int32_t w = col[j];
-    int32_t left = atomicSub(&pending[w - n_old], 1) - 1;
-    if (left == 0) {
-      int32_t slot = atomicAdd(ncount, 1);
-      next[slot] = w;
-    }
+  for (int64_t j = rp[v] + (b - a); j < rp[v + 1]; ++j) {
+    const int32_t w = col[j];
+    if (atomicSub(&pending[w - n_old], 1) == 1) next[atomicAdd(ncount, 1)] = w;
   }
 }
 
@@ -228,11 +225,11 @@ void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
 }
 
 void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
-                         const int32_t* bcol, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
-                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
-                         hipStream_t s) {
+                         const int32_t* bcol, const int32_t* bslot, const float* bcost, const int64_t* rp,
+                         const int32_t* col, float* g, int32_t* parent, float* pcost, int32_t* pending,
+                         int32_t* next, int32_t* ncount, hipStream_t s) {
   hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, n_old, brp,
-                     bcol, bcost, rp, col, g, parent, pcost, pending, next, ncount);
+                     bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
 }
 
 }  // namespace pirrt

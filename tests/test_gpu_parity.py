@@ -269,3 +269,59 @@ def test_adjacency_is_symmetric_union(P):
         a = sorted(zip(ng[pg[v]:pg[v + 1]].tolist(), cg[pg[v]:pg[v + 1]].view(np.uint32).tolist()))
         b = sorted(zip(no[po[v]:po[v + 1]].tolist(), co[po[v]:po[v + 1]].view(np.uint32).tolist()))
         assert a == b, v
+
+
+def lattice_batch(side, keep_frac, seed, shuffle=True):
+    rng = np.random.default_rng(seed)
+    keep = rng.random((side, side)) < keep_frac
+    keep[0, 0] = keep[side - 1, side - 1] = True
+    cells = [(i, j) for i in range(side) for j in range(side) if keep[i, j]]
+    start, end = cells.index((0, 0)), cells.index((side - 1, side - 1))
+    rest = [k for k in range(len(cells)) if k not in (start, end)]
+    if shuffle:
+        rest = list(rng.permutation(rest))
+    order = [start, end] + rest
+    label = {cells[k]: i for i, k in enumerate(order)}
+    edges = []
+    for (i, j) in cells:
+        for (a, b) in ((i + 1, j), (i, j + 1), (i + 1, j + 1)):
+            if (a, b) in label:
+                edges.append((label[(i, j)], label[(a, b)], 1.0 if a == i or b == j else 1.5))
+    return W.from_edges(len(cells), edges)
+
+
+@pytest.mark.parametrize("prune", [True, False])
+def test_lattice_ties(P, prune):
+    """Unit-cost lattice with diagonals: equal candidates everywhere, so every
+    minimum is decided by the neighbour id (and storage renumbering must not leak)."""
+    b = lattice_batch(60, 0.85, 12)
+    run_both(P, [b], {0: (0, 1)}, None, prune)
+
+
+def test_renumbering_is_invisible(P, monkeypatch):
+    wl = W.batched_6d(batches=5, batch=800, seed=102)
+    outs = []
+    for growth in ("0", "1.0", "1.25"):
+        monkeypatch.setenv("PIRRT_REORDER_GROWTH", growth)
+        G = gpu_graph(P)
+        res = []
+        for b in wl.batches:
+            G.insert_rows(b)
+            g, p, st = G.replan(0, 1, wl.heuristic(G.n), True)
+            res.append((g.copy(), p.copy(), {k: st[k] for k in STAT_KEYS}))
+        outs.append(res)
+    for other in outs[1:]:
+        for (g0, p0, s0), (g1, p1, s1) in zip(outs[0], other):
+            assert np.array_equal(g0.view(np.uint32), g1.view(np.uint32))
+            assert np.array_equal(p0, p1)
+            assert s0 == s1
+
+
+def test_level_synchronous_evaluator_agrees(P, monkeypatch):
+    """The two GPU evaluators (walk with stamps, level-synchronous BFS) must give
+    the oracle's results bit for bit."""
+    monkeypatch.setenv("PIRRT_EVALUATE", "levels")
+    wl = W.batched_6d(batches=4, batch=1500, seed=103)
+    run_both(P, wl.batches, {i: (0, 1) for i in range(4)}, wl.heuristic, True)
+    b = lattice_batch(40, 0.9, 5)
+    run_both(P, [b], {0: (0, 1)}, None, False)
