@@ -1,6 +1,7 @@
 // Host runtime and C ABI (declared in include/pirrt.h): graph storage on the device,
 // batch insertion, and the Replan driver of Alg. 2.
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <chrono>
@@ -20,7 +21,8 @@ constexpr int64_t kMinEdgeCap = 4096;
 
 // Pinned host block read back once per Replan iteration.
 struct HostBlock {
-  IterCounters ctr;
+  IterCounters ctr[kCounterSlots];
+  unsigned long long hops;
   EvalInfo info;
   int32_t flag;
   int32_t count[2];
@@ -88,6 +90,8 @@ struct pirrt_graph {
   unsigned long long* word = nullptr;
   uint32_t eval_epoch = 0;
   bool eval_levels = false;  // level-synchronous Evaluate instead of the walk
+  int walk_parts = 1;        // walk launches over consecutive slot ranges
+  bool walk_coherent = true; // device-scope stamp accesses
   // storage order: ext_of[slot] = caller id, slot_of[id] = slot (host mirror hslot)
   int32_t* ext_of = nullptr;
   int32_t* slot_of = nullptr;
@@ -116,10 +120,13 @@ struct pirrt_graph {
   EvalInfo* info = nullptr;
   int32_t* dflag = nullptr;
   int32_t* dcount = nullptr;
+  unsigned long long* dhops = nullptr;
+  bool trace = false;  // per-iteration counters to stderr
   HostBlock* host = nullptr;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   // tuning
   int32_t mid_hint = 64;
+  int32_t max_blocks = 2048;  // persistent grids: CUs x 8 workgroups of 256 threads
   int row_variant = 0;
   bool poisoned = false;
   std::string err;
@@ -307,7 +314,7 @@ void release_all(pirrt_graph* G) {
   dfree(G->col); dfree(G->cst); dfree(G->col2); dfree(G->cst2);
   dfree(G->sg); dfree(G->sparent); dfree(G->spcost);
   dfree(G->brp); dfree(G->bcol); dfree(G->bslot); dfree(G->bcost);
-  dfree(G->ctr); dfree(G->info); dfree(G->dflag); dfree(G->dcount);
+  dfree(G->ctr); dfree(G->info); dfree(G->dflag); dfree(G->dcount); dfree(G->dhops);
   if (G->scan_scratch) (void)hipFree(G->scan_scratch);
   G->scan_scratch = nullptr;
   if (G->host) (void)hipHostFree(G->host);
@@ -463,6 +470,13 @@ int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg) {
   }
   G->device = dev;
   G->stream = (hipStream_t)c.hip_stream;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      G->max_blocks = cus * 8;
+    else
+      (void)hipGetLastError();
+  }
   G->max_iters = c.max_iters;
   if (hipSetDevice(dev) != hipSuccess) {
     (void)hipGetLastError();
@@ -470,7 +484,7 @@ int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg) {
     g_create_error = "hipSetDevice failed";
     return PIRRT_EDEVICE;
   }
-  bool ok = dalloc(&G->ctr, 1) && dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 2);
+  bool ok = dalloc(&G->ctr, kCounterSlots) && dalloc(&G->dhops, 1) && dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 2);
   if (ok && hipHostMalloc((void**)&G->host, sizeof(HostBlock), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     G->host = nullptr;
@@ -516,13 +530,21 @@ int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg) {
   }
   const char* growth = getenv("PIRRT_REORDER_GROWTH");
   if (growth) G->reorder_growth = atof(growth);
+  const char* tr = getenv("PIRRT_TRACE");
+  G->trace = tr && atoi(tr) > 0;
   const char* ev = getenv("PIRRT_EVALUATE");
   if (ev && strcmp(ev, "levels") == 0) G->eval_levels = true;
+  const char* wp = getenv("PIRRT_WALK_PARTS");
+  if (wp && atoi(wp) >= 1) G->walk_parts = atoi(wp);
+  const char* wc = getenv("PIRRT_WALK_COHERENT");
+  if (wc) G->walk_coherent = atoi(wc) != 0;
   const char* variant = getenv("PIRRT_ROW_VARIANT");
   if (variant) {
     int v = atoi(variant);
     if (v >= 0 && v < kRowVariants) G->row_variant = v;
   }
+  const char* blocks = getenv("PIRRT_MAX_BLOCKS");
+  if (blocks && atoi(blocks) >= 8) G->max_blocks = atoi(blocks);
   *out = G;
   return PIRRT_OK;
 }
@@ -705,6 +727,7 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   sa.parent = G->parent;
   sa.pcost = G->pcost;
   sa.ctr = G->ctr;
+  sa.max_blocks = G->max_blocks;
 
   auto evaluate = [&]() -> int {
     int32_t mid = G->mid_hint;
@@ -720,7 +743,9 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
         HIP_OR_FAIL(G, hipMemsetAsync(G->word, 0, sizeof(unsigned long long) * (size_t)G->vcap, s));
         G->eval_epoch = 1;
       }
-      launch_eval_walk(n, rslot, G->eval_epoch, G->parent, G->pcost, G->g, G->word, G->ctr, s);
+      if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
+      launch_eval_walk(n, rslot, G->eval_epoch, G->parent, G->pcost, G->g, G->word, G->ctr,
+                       G->trace ? G->dhops : nullptr, G->walk_parts, G->walk_coherent, s);
     }
     HIP_OR_FAIL(G, hipGetLastError());
     if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
@@ -746,8 +771,10 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
     launch_improve(sa, G->row_variant, s);
     HIP_OR_FAIL(G, hipGetLastError());
     if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[4], s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->ctr, G->ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->ctr, G->ctr, sizeof(IterCounters) * kCounterSlots, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->info, G->info, sizeof(EvalInfo), hipMemcpyDeviceToHost, s));
+    if (G->trace)
+      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->hops, G->dhops, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
     if (timing) {
       if (pending_eval_time) st.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
@@ -757,13 +784,22 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
       st.mark_launches += 1;
       st.improve_launches += 1;
     }
-    const IterCounters c = G->host->ctr;
+    IterCounters c{};
+    for (int k = 0; k < kCounterSlots; ++k) {
+      c.changed += G->host->ctr[k].changed;
+      c.nP += G->host->ctr[k].nP;
+      c.nD += G->host->ctr[k].nD;
+      c.edges += G->host->ctr[k].edges;
+    }
     const EvalInfo info = G->host->info;
     st.iterations += 1;
     st.edges_examined += (int64_t)c.edges;
     st.sum_P += c.nP;
     st.sum_D += c.nD;
     st.changed_total += c.changed;
+    if (G->trace)
+      fprintf(stderr, "pirrt iter %d: |P| %d |D| %d edges %llu changed %d walk hops %llu\n", st.iterations, c.nP,
+              c.nD, (unsigned long long)c.edges, c.changed, G->eval_levels ? 0ull : G->host->hops);
     st.eval_levels = info.levels;
     // wide level launches for the next walk: the large levels seen this time, plus slack
     int32_t need = info.big_end - info.head_end;

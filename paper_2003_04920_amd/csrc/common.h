@@ -8,7 +8,10 @@ namespace pirrt {
 
 constexpr int kWave = 64;  // CDNA wavefront width
 
-// Per-iteration counters written by the mark / improve kernels.
+// Per-iteration counters written by the mark / improve kernels.  Kernels add into
+// kCounterSlots copies (workgroup b uses copy b % kCounterSlots) so that the
+// atomics do not pile onto one address; the host sums the copies.
+constexpr int kCounterSlots = 256;
 struct IterCounters {
   int32_t changed;           // parents switched by Improve
   int32_t nP;                // |promising set|
@@ -53,6 +56,53 @@ __device__ __forceinline__ int wave_reserve(int* counter, int count) {
   if (lane == 0 && total > 0) base = atomicAdd(counter, total);
   base = __shfl(base, 0, kWave);
   return base + off;
+}
+
+// Cross-lane moves through DPP (a VALU operand modifier, no LDS round trip).
+// Controls: quad_perm(1,0,3,2) = 0xB1, quad_perm(2,3,0,1) = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140.  All lanes must be active.
+template <int ctrl>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, ctrl, 0xf, 0xf, false);
+}
+
+// Minimum over groups of `width` (2, 4, 8 or 16) consecutive lanes with DPP;
+// wider groups continue with lane shuffles.  Every lane ends with its group's
+// minimum.
+template <int width>
+__device__ __forceinline__ uint32_t dpp_group_min_u32(uint32_t x) {
+  uint32_t y;
+  if (width >= 2) { y = dpp_u32<0xB1>(x); x = y < x ? y : x; }
+  if (width >= 4) { y = dpp_u32<0x4E>(x); x = y < x ? y : x; }
+  if (width >= 8) { y = dpp_u32<0x141>(x); x = y < x ? y : x; }
+  if (width >= 16) { y = dpp_u32<0x140>(x); x = y < x ? y : x; }
+#pragma unroll
+  for (int off = 16; off < width; off <<= 1) {
+    y = __shfl_xor(x, off, kWave);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+template <int width>
+__device__ __forceinline__ unsigned long long dpp_group_min_u64(unsigned long long x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32), ylo, yhi;
+#define PIRRT_DPP_MIN64(ctrl)                                            \
+  ylo = dpp_u32<ctrl>(lo);                                               \
+  yhi = dpp_u32<ctrl>(hi);                                               \
+  if (yhi < hi || (yhi == hi && ylo < lo)) { hi = yhi; lo = ylo; }
+  if (width >= 2) { PIRRT_DPP_MIN64(0xB1) }
+  if (width >= 4) { PIRRT_DPP_MIN64(0x4E) }
+  if (width >= 8) { PIRRT_DPP_MIN64(0x141) }
+  if (width >= 16) { PIRRT_DPP_MIN64(0x140) }
+#undef PIRRT_DPP_MIN64
+#pragma unroll
+  for (int off = 16; off < width; off <<= 1) {
+    ylo = __shfl_xor(lo, off, kWave);
+    yhi = __shfl_xor(hi, off, kWave);
+    if (yhi < hi || (yhi == hi && ylo < lo)) { hi = yhi; lo = ylo; }
+  }
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Minimum over groups of `width` consecutive lanes (width a power of two <= 64);

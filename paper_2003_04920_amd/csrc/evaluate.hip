@@ -178,11 +178,14 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
   if (threadIdx.x == 0) {
     if (levels > B.info->levels) B.info->levels = levels;
     if (big_end > B.info->big_end) B.info->big_end = big_end;
+  }
+  if (threadIdx.x < kCounterSlots) {
     // fresh counters for the promising-set / Improve pass that follows
-    ctr->changed = 0;
-    ctr->nP = 0;
-    ctr->nD = 0;
-    ctr->edges = 0ull;
+    IterCounters& c = ctr[threadIdx.x];
+    c.changed = 0;
+    c.nP = 0;
+    c.nD = 0;
+    c.edges = 0ull;
   }
 }
 
@@ -206,38 +209,52 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
 constexpr int kWalkThreads = 256;
 constexpr int kRing = 16;
 
+// kCoherent: stamps are read and written at device scope (visible across XCDs
+// within the launch); otherwise they are plain accesses (visible within the XCD
+// and to later launches).
+template <bool kCoherent>
 __device__ __forceinline__ unsigned long long load_word(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (kCoherent) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+template <bool kCoherent>
 __device__ __forceinline__ void store_word(unsigned long long* p, unsigned long long w) {
-  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (kCoherent)
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t n, int32_t root, uint32_t epoch,
+template <bool kCountHops, bool kCoherent>
+__global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t hi, int32_t n, int32_t root,
+                                                           uint32_t epoch,
                                                            const int32_t* __restrict__ parent,
                                                            const float* __restrict__ pcost, float* __restrict__ g,
                                                            unsigned long long* __restrict__ word,
-                                                           IterCounters* __restrict__ ctr) {
+                                                           IterCounters* __restrict__ ctr,
+                                                           unsigned long long* __restrict__ hops) {
   __shared__ int32_t ring_v[kRing][kWalkThreads];
   __shared__ float ring_c[kRing][kWalkThreads];
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const int64_t v = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (lo == 0 && blockIdx.x == 0 && threadIdx.x < kCounterSlots) {
     // fresh counters for the promising-set / Improve pass that follows
-    ctr->changed = 0;
-    ctr->nP = 0;
-    ctr->nD = 0;
-    ctr->edges = 0ull;
+    IterCounters& c = ctr[threadIdx.x];
+    c.changed = 0;
+    c.nP = 0;
+    c.nD = 0;
+    c.edges = 0ull;
   }
-  if (v >= n) return;
+  if (v >= hi) return;
   const unsigned long long tag = (unsigned long long)epoch << 32;
+  unsigned long long walked = 0;
   for (;;) {
     int32_t u = (int32_t)v;
     int64_t k = 0;
     uint32_t top;  // g bits above the recorded path
     for (;;) {
       // the stamp, parent and parent-edge cost of u in one round trip
-      const unsigned long long w = load_word(&word[u]);
+      const unsigned long long w = load_word<kCoherent>(&word[u]);
       const int32_t p = parent[u];
       const float c = pcost[u];
       if ((w & 0xffffffff00000000ull) == tag) {
@@ -246,7 +263,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t n, int32_t r
       }
       if (u == root) {
         top = 0u;
-        store_word(&word[u], tag);
+        store_word<kCoherent>(&word[u], tag);
         g[u] = 0.0f;
         break;
       }
@@ -259,24 +276,41 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t n, int32_t r
       }
       u = p;
     }
+    walked += (unsigned long long)k;
     const int64_t stop = k > kRing ? k - kRing : 0;
     float acc = __uint_as_float(top);
     for (int64_t i = k - 1; i >= stop; --i) {
       const int32_t x = ring_v[i % kRing][threadIdx.x];
       acc = add_rn(acc, ring_c[i % kRing][threadIdx.x]);
-      store_word(&word[x], tag | __float_as_uint(acc));
+      store_word<kCoherent>(&word[x], tag | __float_as_uint(acc));
       g[x] = acc;
     }
     if (stop == 0) break;
   }
+  if (kCountHops) atomicAdd(hops, walked);
 }
 
 }  // namespace
 
 void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
-                      unsigned long long* word, IterCounters* ctr, hipStream_t s) {
-  hipLaunchKernelGGL(k_eval_walk, dim3(blocks_for(n, kWalkThreads)), dim3(kWalkThreads), 0, s, n, root, epoch,
-                     parent, pcost, g, word, ctr);
+                      unsigned long long* word, IterCounters* ctr, unsigned long long* hops, int parts,
+                      bool coherent, hipStream_t s) {
+  if (parts < 1) parts = 1;
+  const int64_t per = ((int64_t)n + parts - 1) / parts;
+  for (int k = 0; k < parts; ++k) {
+    const int32_t lo = (int32_t)(k * per < n ? k * per : n), hi = (int32_t)((k + 1) * per < n ? (k + 1) * per : n);
+    if (hi <= lo && k > 0) break;
+    const dim3 grid(blocks_for(hi - lo, kWalkThreads));
+#define PIRRT_WALK(H, C) \
+  hipLaunchKernelGGL((k_eval_walk<H, C>), grid, dim3(kWalkThreads), 0, s, lo, hi, n, root, epoch, parent, pcost, g, \
+                     word, ctr, hops)
+    if (hops) {
+      if (coherent) PIRRT_WALK(true, true); else PIRRT_WALK(true, false);
+    } else {
+      if (coherent) PIRRT_WALK(false, true); else PIRRT_WALK(false, false);
+    }
+#undef PIRRT_WALK
+  }
 }
 
 void launch_evaluate(const EvalArgs& a, hipStream_t s) {

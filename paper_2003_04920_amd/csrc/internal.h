@@ -76,7 +76,7 @@ struct EvalArgs {
   int32_t* fr1;         // n
   int32_t* lvl;         // level sizes, n + kMaxMidLaunches + 4
   EvalInfo* info;
-  IterCounters* ctr;    // cleared at the end of the walk
+  IterCounters* ctr;    // kCounterSlots copies, cleared at the end of the walk
   void* scan_scratch;
   int32_t mid_launches; // wide level launches between head and tail
   int32_t level_blocks; // grid of each wide level launch
@@ -84,8 +84,12 @@ struct EvalArgs {
 constexpr int32_t kMaxMidLaunches = 1024;
 void launch_evaluate(const EvalArgs& a, hipStream_t s);
 // word: n 64-bit {epoch, g bits} stamps; epochs of earlier calls must be smaller.
+// hops (nullable): if given, receives the total number of parent links walked.
+// The slots are walked in `parts` launches over consecutive ranges (later ranges
+// find the earlier ones' stamps); coherent selects device-scope stamp accesses.
 void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
-                      unsigned long long* word, IterCounters* ctr, hipStream_t s);
+                      unsigned long long* word, IterCounters* ctr, unsigned long long* hops, int parts,
+                      bool coherent, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
@@ -103,9 +107,10 @@ struct StepArgs {
   const int32_t* ext_of;  // caller id of each slot (tie-break key)
   int32_t* parent;
   float* pcost;
-  IterCounters* ctr;
+  IterCounters* ctr;  // kCounterSlots copies
+  int32_t max_blocks;  // persistent grid: about one residency of 256-thread workgroups
 };
-constexpr int kRowVariants = 4;
+constexpr int kRowVariants = 6;
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);
 void launch_improve(const StepArgs& a, int variant, hipStream_t s);
 
