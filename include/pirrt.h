@@ -165,6 +165,67 @@ int64_t pirrt_num_edges(const pirrt_graph* g); /* directed entries = 2 x undirec
 const char* pirrt_last_error(const pirrt_graph* g);
 const char* pirrt_strerror(int code);
 
+/*
+ * Batches of independent planning problems (many robots or many queries, each with
+ * its own RRG; the data-parallel form of Sec. IV applied across graphs).  One
+ * handle stores every problem's graph side by side in one device store, and one
+ * pirrt_batch_replan runs Alg. 2 for all of them at once: each iteration's
+ * threshold, promising set, domain, Improve, Evaluate and convergence test are per
+ * problem, and a problem that reached its fixed point takes no further part.  The
+ * result of each problem is exactly that of pirrt_replan on a graph holding that
+ * problem alone.
+ *
+ * Ids are local to a problem: vertex k of problem i is 0 <= k < n_i, and parents
+ * in policies are local ids.  Arrays of per-vertex values (h, g, parent, pcost)
+ * are concatenations of the problems in index order, problem i starting at
+ * pirrt_batch_problem_offset(b, i).  Error conventions are those of the graph
+ * handle above.
+ */
+typedef struct pirrt_batch pirrt_batch;
+
+/* Creates an empty batch on the configured device (cfg as for pirrt_graph_create;
+   max_iters caps every problem). */
+int pirrt_batch_create(pirrt_batch** out, const pirrt_config* cfg);
+
+/* Releases the batch and its device memory.  NULL is allowed. */
+int pirrt_batch_destroy(pirrt_batch* b);
+
+/*
+ * Adds a problem with n >= 1 vertices given as forward rows exactly as in
+ * pirrt_insert_batch, with local ids (row i lists neighbours j < i).  Local vertex
+ * 0 is the problem's x_init for the insertion-time policy.  *index (nullable)
+ * receives the problem's index (0, 1, ... in order of addition).
+ * Errors: EINVAL (n < 1, bad rows, total ids beyond INT32_MAX), ENOMEM, EDEVICE.
+ */
+int pirrt_batch_add_problem(pirrt_batch* b, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                            const float* cost, int mem_kind, int32_t* index);
+
+int32_t pirrt_batch_num_problems(const pirrt_batch* b);
+int64_t pirrt_batch_num_vertices(const pirrt_batch* b); /* all problems together */
+int64_t pirrt_batch_num_edges(const pirrt_batch* b);    /* directed entries, all problems */
+/* First position of problem i in concatenated per-vertex arrays (i == count gives
+   the total); -1 if out of range. */
+int64_t pirrt_batch_problem_offset(const pirrt_batch* b, int32_t problem);
+
+/*
+ * Replan (Alg. 2) for every problem.  roots / goals: host int32[P] local ids.  h,
+ * g_out, parent_out: concatenated per-vertex arrays (nullable) at mem_kind.  stats:
+ * host pirrt_stats[P] or NULL (phase timings are filled only for P = 1).
+ * Returns ENOTCONVERGED if any problem reached the cap (each problem's state is
+ * still a consistent policy with its g).
+ */
+int pirrt_batch_replan(pirrt_batch* b, const int32_t* roots, const int32_t* goals, const float* h,
+                       uint32_t flags, float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
+
+/* Policy of every problem (concatenated, local parent ids). */
+int pirrt_batch_get_policy(pirrt_batch* b, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind);
+
+/* As pirrt_snapshot_save / pirrt_snapshot_restore for the whole batch. */
+int pirrt_batch_snapshot_save(pirrt_batch* b);
+int pirrt_batch_snapshot_restore(pirrt_batch* b);
+
+const char* pirrt_batch_last_error(const pirrt_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

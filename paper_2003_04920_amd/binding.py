@@ -25,6 +25,10 @@ EXPORTS = [
     "pirrt_config_init", "pirrt_graph_create", "pirrt_graph_destroy", "pirrt_insert_batch", "pirrt_replan",
     "pirrt_get_policy", "pirrt_set_policy", "pirrt_snapshot_save", "pirrt_snapshot_restore",
     "pirrt_get_adjacency", "pirrt_num_vertices", "pirrt_num_edges", "pirrt_last_error", "pirrt_strerror",
+    "pirrt_batch_create", "pirrt_batch_destroy", "pirrt_batch_add_problem", "pirrt_batch_num_problems",
+    "pirrt_batch_num_vertices", "pirrt_batch_num_edges", "pirrt_batch_problem_offset", "pirrt_batch_replan",
+    "pirrt_batch_get_policy", "pirrt_batch_snapshot_save", "pirrt_batch_snapshot_restore",
+    "pirrt_batch_last_error",
 ]
 
 
@@ -80,6 +84,18 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_num_edges": (i64, [vp]),
         "pirrt_last_error": (ctypes.c_char_p, [vp]),
         "pirrt_strerror": (ctypes.c_char_p, [cint]),
+        "pirrt_batch_create": (cint, [ctypes.POINTER(vp), ctypes.POINTER(pirrt_config)]),
+        "pirrt_batch_destroy": (cint, [vp]),
+        "pirrt_batch_add_problem": (cint, [vp, i32, vp, vp, vp, cint, ctypes.POINTER(i32)]),
+        "pirrt_batch_num_problems": (i32, [vp]),
+        "pirrt_batch_num_vertices": (i64, [vp]),
+        "pirrt_batch_num_edges": (i64, [vp]),
+        "pirrt_batch_problem_offset": (i64, [vp, i32]),
+        "pirrt_batch_replan": (cint, [vp, vp, vp, vp, u32, vp, vp, cint, vp]),
+        "pirrt_batch_get_policy": (cint, [vp, vp, vp, vp, cint]),
+        "pirrt_batch_snapshot_save": (cint, [vp]),
+        "pirrt_batch_snapshot_restore": (cint, [vp]),
+        "pirrt_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -240,6 +256,115 @@ class Graph:
         cst = np.empty(max(self.nnz, 1), np.float32)
         self._check(self._lib.pirrt_get_adjacency(self._h, _ptr(ptr), _ptr(nbr), _ptr(cst), PIRRT_MEM_HOST))
         return ptr, nbr[: self.nnz], cst[: self.nnz]
+
+
+class Batch:
+    """One pirrt_batch handle: independent problems replanned together.  Vertex ids
+    are local to each problem; per-vertex arrays are the problems' arrays
+    concatenated in index order (``offsets`` gives where each starts)."""
+
+    def __init__(self, stream: Optional[int] = None, device: int = -1, max_iters: int = 0,
+                 vertex_capacity: int = 0, edge_capacity: int = 0, lib: Optional[ctypes.CDLL] = None):
+        self._lib = lib or load()
+        cfg = pirrt_config()
+        self._lib.pirrt_config_init(ctypes.byref(cfg))
+        cfg.vertex_capacity = vertex_capacity
+        cfg.edge_capacity = edge_capacity
+        cfg.hip_stream = stream or None
+        cfg.max_iters = max_iters
+        cfg.device = device
+        h = ctypes.c_void_p()
+        rc = self._lib.pirrt_batch_create(ctypes.byref(h), ctypes.byref(cfg))
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.pirrt_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int, allow=()):
+        if rc != PIRRT_OK and rc not in allow:
+            raise PirrtError(rc, self._lib.pirrt_batch_last_error(self._h).decode())
+        return rc
+
+    @property
+    def num_problems(self) -> int:
+        return int(self._lib.pirrt_batch_num_problems(self._h))
+
+    @property
+    def n(self) -> int:
+        return int(self._lib.pirrt_batch_num_vertices(self._h))
+
+    @property
+    def nnz(self) -> int:
+        return int(self._lib.pirrt_batch_num_edges(self._h))
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.array([self._lib.pirrt_batch_problem_offset(self._h, i) for i in range(self.num_problems + 1)],
+                        np.int64)
+
+    def add_problem(self, row_ptr, col, cost) -> int:
+        row_ptr = _check_dtype(row_ptr, np.int64, "int64")
+        col = _check_dtype(col, np.int32, "int32")
+        cost = _check_dtype(cost, np.float32, "float32")
+        kind = _mem_kind(row_ptr, col, cost)
+        idx = ctypes.c_int32(-1)
+        rc = self._lib.pirrt_batch_add_problem(self._h, int(row_ptr.shape[0]) - 1, _ptr(row_ptr),
+                                               _ptr(col) if len(col) else None, _ptr(cost) if len(cost) else None,
+                                               kind, ctypes.byref(idx))
+        self._check(rc)
+        return int(idx.value)
+
+    def replan(self, roots, goals, h=None, prune: bool = True, timing: bool = False, g_out=None,
+               parent_out=None, allow_not_converged: bool = False):
+        """Replans every problem.  Returns (g, parent, per-problem stats dicts)."""
+        P = self.num_problems
+        roots = np.ascontiguousarray(roots, np.int32)
+        goals = np.ascontiguousarray(goals, np.int32)
+        if roots.shape != (P,) or goals.shape != (P,):
+            raise ValueError("roots and goals need one entry per problem")
+        h = _check_dtype(h, np.float32, "float32")
+        n = self.n
+        if g_out is None and parent_out is None and _is_device(h):
+            import torch
+            g_out = torch.empty(n, dtype=torch.float32, device=h.device)
+            parent_out = torch.empty(n, dtype=torch.int32, device=h.device)
+        if g_out is None and parent_out is None:
+            g_out = np.empty(n, np.float32)
+            parent_out = np.empty(n, np.int32)
+        kind = _mem_kind(h, g_out, parent_out)
+        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0)
+        st = (pirrt_stats * max(P, 1))()
+        rc = self._lib.pirrt_batch_replan(self._h, _ptr(roots), _ptr(goals), _ptr(h), flags, _ptr(g_out),
+                                          _ptr(parent_out), kind, ctypes.cast(st, ctypes.c_void_p))
+        self._check(rc, allow=(PIRRT_ENOTCONVERGED,) if allow_not_converged else ())
+        stats = [dict(st[i].as_dict(), rc=rc) for i in range(P)]
+        return g_out, parent_out, stats
+
+    def get_policy(self, device=None):
+        n = self.n
+        if device is not None:
+            import torch
+            g = torch.empty(n, dtype=torch.float32, device=device)
+            p = torch.empty(n, dtype=torch.int32, device=device)
+            c = torch.empty(n, dtype=torch.float32, device=device)
+        else:
+            g, p, c = np.empty(n, np.float32), np.empty(n, np.int32), np.empty(n, np.float32)
+        self._check(self._lib.pirrt_batch_get_policy(self._h, _ptr(g), _ptr(p), _ptr(c), _mem_kind(g, p, c)))
+        return g, p, c
+
+    def snapshot_save(self) -> int:
+        return self._check(self._lib.pirrt_batch_snapshot_save(self._h))
+
+    def snapshot_restore(self) -> int:
+        return self._check(self._lib.pirrt_batch_snapshot_restore(self._h))
 
 
 def pirrt_strerror(code: int) -> str:

@@ -1,9 +1,11 @@
 // Host runtime and C ABI (declared in include/pirrt.h): graph storage on the device,
-// batch insertion, and the Replan driver of Alg. 2.
+// batch insertion, and the Replan driver of Alg. 2 for one graph or for a batch of
+// independent graphs ("problems") stored side by side.
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -18,12 +20,12 @@ namespace {
 
 constexpr int64_t kMinVertexCap = 1024;
 constexpr int64_t kMinEdgeCap = 4096;
+constexpr int kGraphIterCounts = 4;  // captured loop bodies of 1, 2, 4 and 8 iterations
 
-// Pinned host block read back once per Replan iteration.
+// Pinned host block for small read-backs.
 struct HostBlock {
-  IterCounters ctr[kCounterSlots];
+  LoopCtl ctl;
   unsigned long long hops;
-  EvalInfo info;
   int32_t flag;
   int32_t count[2];
   int64_t word;
@@ -35,13 +37,16 @@ __global__ void k_check_h(int32_t n, const float* __restrict__ h, int* __restric
   if (v < n && !(h[v] >= 0.0f)) atomicOr(bad, 1);
 }
 
+// parent ids are local to the problem [base, base + len) of each vertex.
 __global__ void k_check_policy(int32_t n, const int32_t* __restrict__ parent, const float* __restrict__ pcost,
+                               const int32_t* __restrict__ prob, const int64_t* __restrict__ base,
                                int* __restrict__ bad) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
+  const int64_t b = prob ? base[prob[v]] : 0, len = prob ? base[prob[v] + 1] - b : n;
   int32_t p = parent[v];
   uint32_t w = __float_as_uint(pcost[v]);
-  if (p < -1 || p >= n || p == v) atomicOr(bad, 1);
+  if (p < -1 || p >= len || p == v - b) atomicOr(bad, 1);
   if ((w >> 31) != 0 || (w & 0x7f800000u) == 0x7f800000u) atomicOr(bad, 2);
 }
 
@@ -52,11 +57,20 @@ inline unsigned grid_for(int64_t n, int per = 256) {
 
 thread_local std::string g_create_error;
 
+// Identity of a captured loop body: every pointer and size baked into its nodes.
+struct LoopKey {
+  const void* ptrs[16];
+  int64_t n, nnz;
+  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, pad;
+  bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
+};
+
 }  // namespace
 
 struct pirrt_graph {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture loop bodies
   int32_t max_iters = 0;
   int64_t n = 0, nnz = 0;
   int64_t vcap = 0, ecap = 0, ecap2 = 0;
@@ -76,28 +90,44 @@ struct pirrt_graph {
   int32_t* sparent = nullptr;
   float* spcost = nullptr;
   int64_t snap_n = -1, snap_cap = 0;
-  // Evaluate scratch
+  // Evaluate scratch (the level-synchronous evaluator; the child arrays double as
+  // renumbering scratch)
   int32_t* child_cnt = nullptr;
   int32_t* child_ptr = nullptr;
   int32_t* child = nullptr;
   int32_t* fr0 = nullptr;
   int32_t* fr1 = nullptr;
   int32_t* lvl = nullptr;
-  // promising / domain marks
+  // promising / domain marks and Evaluate stamps {epoch, g bits}
   uint32_t* stamp = nullptr;
-  uint32_t epoch = 0;
-  // Evaluate stamps {epoch, g bits}
   unsigned long long* word = nullptr;
-  uint32_t eval_epoch = 0;
-  bool eval_levels = false;  // level-synchronous Evaluate instead of the walk
-  int walk_parts = 1;        // walk launches over consecutive slot ranges
-  bool walk_coherent = true; // device-scope stamp accesses
+  bool eval_levels = false;   // level-synchronous Evaluate instead of the walk
+  int walk_parts = 1;         // walk launches over consecutive slot ranges
+  bool walk_coherent = true;  // device-scope stamp accesses
   // storage order: ext_of[slot] = caller id, slot_of[id] = slot (host mirror hslot)
   int32_t* ext_of = nullptr;
   int32_t* slot_of = nullptr;
   std::vector<int32_t> hslot;
-  int64_t reorder_n = 0;       // vertex count at the last renumbering
-  double reorder_growth = 1.25;  // renumber when n grows by this factor (0 = never)
+  int64_t reorder_n = 0;          // vertex count at the last renumbering
+  double reorder_growth = 1.25;   // renumber when n grows by this factor (0 = never)
+  bool renumber_pending = false;  // batch problems added since the last renumbering
+  // problems: problem i holds caller ids [pbase[i], pbase[i+1]) and the same slots
+  bool batched = false;
+  std::vector<int64_t> pbase{0, 0};
+  int32_t* prob = nullptr;  // problem of each slot (used by batches only)
+  int64_t* dbase = nullptr;  // device copy of pbase
+  int64_t dbase_cap = 0;
+  // per-problem Replan state
+  ProblemState* ps = nullptr;
+  ProblemState* hps = nullptr;  // pinned mirror
+  IterCounters* ctr = nullptr;
+  LoopCtl* ctl = nullptr;
+  int32_t* pscratch = nullptr;  // per-problem ints (renumbering counters)
+  int32_t* droots = nullptr;    // caller ids of the slots that carry root marks
+  int32_t nroots = 0;
+  std::vector<int32_t> hroots;       // host copy of droots
+  std::vector<int32_t> snap_roots;   // the root marks held by the snapshot
+  int64_t pcap = 0;
   // insertion / renumbering / translation scratch
   int32_t* add = nullptr;
   int32_t* deg = nullptr;
@@ -116,20 +146,27 @@ struct pirrt_graph {
   void* scan_scratch = nullptr;
   size_t scan_bytes = 0;
   // small device block and its pinned mirror
-  IterCounters* ctr = nullptr;
   EvalInfo* info = nullptr;
   int32_t* dflag = nullptr;
   int32_t* dcount = nullptr;
   unsigned long long* dhops = nullptr;
-  bool trace = false;  // per-iteration counters to stderr
+  bool trace = false;  // per-iteration counters to stderr (direct loop only)
   HostBlock* host = nullptr;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // captured loop bodies
+  bool use_graph = true;
+  hipGraphExec_t loop_exec[kGraphIterCounts] = {nullptr, nullptr, nullptr, nullptr};
+  LoopKey loop_key[kGraphIterCounts];
+  int32_t last_iterations = 0;  // iterations of the previous Replan (loop planning)
   // tuning
   int32_t mid_hint = 64;
-  int32_t max_blocks = 2048;  // persistent grids: CUs x 8 workgroups of 256 threads
-  int row_variant = 0;
+  int row_variant = 1;
   bool poisoned = false;
   std::string err;
+};
+
+struct pirrt_batch {
+  pirrt_graph* G;
 };
 
 namespace {
@@ -145,9 +182,9 @@ int fail_device(pirrt_graph* G, hipError_t e, const char* what) {
   return PIRRT_EDEVICE;
 }
 
-#define HIP_OR_FAIL(G, expr)                          \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
+#define HIP_OR_FAIL(G, expr)                                \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
     if (e_ != hipSuccess) return fail_device(G, e_, #expr); \
   } while (0)
 
@@ -177,8 +214,9 @@ int guard(pirrt_graph* G) {
   return PIRRT_OK;
 }
 
-hipMemcpyKind in_kind(int mem_kind) { return mem_kind == PIRRT_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
-hipMemcpyKind out_kind(int mem_kind) { return mem_kind == PIRRT_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+hipMemcpyKind in_kind(int mem_kind) {
+  return mem_kind == PIRRT_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
 
 int ensure_scan(pirrt_graph* G, int64_t n) {
   size_t need = scan_scratch_bytes(n);
@@ -194,24 +232,32 @@ int ensure_scan(pirrt_graph* G, int64_t n) {
   return PIRRT_OK;
 }
 
+void drop_loops(pirrt_graph* G) {
+  for (int k = 0; k < kGraphIterCounts; ++k)
+    if (G->loop_exec[k]) {
+      (void)hipGraphExecDestroy(G->loop_exec[k]);
+      G->loop_exec[k] = nullptr;
+    }
+}
+
 void free_vertex_arrays(pirrt_graph* G) {
   dfree(G->rp); dfree(G->rp2); dfree(G->g); dfree(G->parent); dfree(G->pcost); dfree(G->child_cnt);
   dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
   dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf); dfree(G->ext_of); dfree(G->slot_of);
-  dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word);
+  dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word); dfree(G->prob);
 }
 
 void forget_vertex_arrays(pirrt_graph* T) {
   T->rp = T->rp2 = nullptr;
   T->g = T->pcost = T->hbuf = T->g2 = T->pcost2 = nullptr;
   T->parent = T->child_cnt = T->child_ptr = T->child = T->fr0 = T->fr1 = T->lvl = nullptr;
-  T->add = T->deg = T->pending = T->ext_of = T->slot_of = T->parent2 = T->ext2 = nullptr;
+  T->add = T->deg = T->pending = T->ext_of = T->slot_of = T->parent2 = T->ext2 = T->prob = nullptr;
   T->stamp = nullptr;
   T->word = nullptr;
 }
 
-// Grows every per-vertex array to hold `need` vertices, keeping g / parent / pcost
-// and the row offsets.  On failure nothing changes.
+// Grows every per-vertex array to hold `need` vertices, keeping the policy, the
+// row offsets, the id maps and the problem map.  On failure nothing changes.
 int ensure_vcap(pirrt_graph* G, int64_t need) {
   if (need <= G->vcap) return PIRRT_OK;
   int64_t cap = G->vcap + G->vcap / 2;
@@ -224,7 +270,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(&T.lvl, cap + kMaxMidLaunches + 8) && dalloc(&T.stamp, cap) && dalloc(&T.add, cap) &&
             dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap) && dalloc(&T.ext_of, cap) &&
             dalloc(&T.slot_of, cap) && dalloc(&T.g2, cap) && dalloc(&T.parent2, cap) && dalloc(&T.pcost2, cap) &&
-            dalloc(&T.ext2, cap) && dalloc(&T.word, cap);
+            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -235,12 +281,14 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   HIP_OR_FAIL(G, hipMemsetAsync(T.word, 0, sizeof(unsigned long long) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.rp, 0, sizeof(int64_t) * (size_t)(cap + 1), s));
   if (G->n > 0) {
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.rp, G->rp, sizeof(int64_t) * (size_t)(G->n + 1), hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.g, G->g, sizeof(float) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.parent, G->parent, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.pcost, G->pcost, sizeof(float) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.ext_of, G->ext_of, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(T.slot_of, G->slot_of, sizeof(int32_t) * (size_t)G->n, hipMemcpyDeviceToDevice, s));
+    const size_t n = (size_t)G->n;
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.rp, G->rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.g, G->g, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.parent, G->parent, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.pcost, G->pcost, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.ext_of, G->ext_of, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.slot_of, G->slot_of, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(T.prob, G->prob, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
   }
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   free_vertex_arrays(G);
@@ -248,13 +296,58 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   G->child_cnt = T.child_cnt; G->child_ptr = T.child_ptr; G->child = T.child; G->fr0 = T.fr0; G->fr1 = T.fr1;
   G->lvl = T.lvl; G->stamp = T.stamp; G->add = T.add; G->deg = T.deg; G->pending = T.pending; G->hbuf = T.hbuf;
   G->ext_of = T.ext_of; G->slot_of = T.slot_of; G->g2 = T.g2; G->parent2 = T.parent2; G->pcost2 = T.pcost2;
-  G->ext2 = T.ext2;
-  G->word = T.word;
+  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob;
   forget_vertex_arrays(&T);
   G->vcap = cap;
-  G->epoch = 0;
-  G->eval_epoch = 0;
+  drop_loops(G);
   return ensure_scan(G, cap + 1);
+}
+
+// Per-problem state for `need` problems.
+int ensure_pcap(pirrt_graph* G, int64_t need) {
+  if (need <= G->pcap) return PIRRT_OK;
+  int64_t cap = G->pcap * 2 > need ? G->pcap * 2 : need;
+  if (cap < 16) cap = 16;
+  ProblemState* ps = nullptr;
+  IterCounters* ctr = nullptr;
+  int32_t* scr = nullptr;
+  int32_t* roots = nullptr;
+  ProblemState* hps = nullptr;
+  bool ok = dalloc(&ps, cap) && dalloc(&ctr, cap * kCounterSlots) && dalloc(&scr, cap) && dalloc(&roots, cap);
+  if (ok && hipHostMalloc((void**)&hps, sizeof(ProblemState) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    hps = nullptr;
+    ok = false;
+  }
+  if (!ok) {
+    dfree(ps); dfree(ctr); dfree(scr); dfree(roots);
+    return fail(G, PIRRT_ENOMEM, "allocation of per-problem state failed");
+  }
+  if (G->nroots > 0)
+    HIP_OR_FAIL(G, hipMemcpy(roots, G->droots, sizeof(int32_t) * (size_t)G->nroots, hipMemcpyDeviceToDevice));
+  dfree(G->ps); dfree(G->ctr); dfree(G->pscratch); dfree(G->droots);
+  if (G->hps) (void)hipHostFree(G->hps);
+  G->ps = ps; G->ctr = ctr; G->pscratch = scr; G->droots = roots; G->hps = hps;
+  G->pcap = cap;
+  drop_loops(G);
+  return PIRRT_OK;
+}
+
+int upload_bases(pirrt_graph* G) {
+  const int64_t m = (int64_t)G->pbase.size();
+  if (m > G->dbase_cap) {
+    int64_t* p = nullptr;
+    int64_t cap = m * 2 > 64 ? m * 2 : 64;
+    if (!dalloc(&p, cap)) return fail(G, PIRRT_ENOMEM, "allocation of problem table failed");
+    dfree(G->dbase);
+    G->dbase = p;
+    G->dbase_cap = cap;
+    drop_loops(G);
+  }
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->dbase, G->pbase.data(), sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice,
+                                G->stream));
+  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
+  return PIRRT_OK;
 }
 
 // Spare adjacency arrays able to hold `need` entries.
@@ -310,11 +403,15 @@ int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
 }
 
 void release_all(pirrt_graph* G) {
+  drop_loops(G);
   free_vertex_arrays(G);
   dfree(G->col); dfree(G->cst); dfree(G->col2); dfree(G->cst2);
   dfree(G->sg); dfree(G->sparent); dfree(G->spcost);
   dfree(G->brp); dfree(G->bcol); dfree(G->bslot); dfree(G->bcost);
-  dfree(G->ctr); dfree(G->info); dfree(G->dflag); dfree(G->dcount); dfree(G->dhops);
+  dfree(G->info); dfree(G->dflag); dfree(G->dcount); dfree(G->dhops);
+  dfree(G->ps); dfree(G->ctr); dfree(G->ctl); dfree(G->pscratch); dfree(G->droots); dfree(G->dbase);
+  if (G->hps) (void)hipHostFree(G->hps);
+  G->hps = nullptr;
   if (G->scan_scratch) (void)hipFree(G->scan_scratch);
   G->scan_scratch = nullptr;
   if (G->host) (void)hipHostFree(G->host);
@@ -324,6 +421,8 @@ void release_all(pirrt_graph* G) {
       (void)hipEventDestroy(e);
       e = nullptr;
     }
+  if (G->cap_stream) (void)hipStreamDestroy(G->cap_stream);
+  G->cap_stream = nullptr;
 }
 
 // Reads one device flag word back (synchronising the stream).
@@ -343,8 +442,11 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   return (double)ms;
 }
 
+int32_t* problem_map(pirrt_graph* G) { return G->batched ? G->prob : nullptr; }
+const int64_t* base_map(pirrt_graph* G) { return G->batched ? G->dbase : nullptr; }
+
 // Copies the policy out in caller order (device outputs are written directly;
-// host outputs go through device staging).
+// host outputs go through device staging).  In a batch, parents are local ids.
 int policy_out(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {
   const int32_t n = (int32_t)G->n;
   hipStream_t s = G->stream;
@@ -353,7 +455,8 @@ int policy_out(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_o
   float* gd = g_out ? (dev ? g_out : G->g2) : nullptr;
   int32_t* pd = parent_out ? (dev ? parent_out : G->parent2) : nullptr;
   float* cd = pcost_out ? (dev ? pcost_out : G->pcost2) : nullptr;
-  launch_policy_to_ext(n, G->slot_of, G->ext_of, G->g, G->parent, G->pcost, gd, pd, cd, s);
+  launch_policy_to_ext(n, G->slot_of, G->ext_of, problem_map(G), base_map(G), G->g, G->parent, G->pcost, gd, pd,
+                       cd, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (!dev) {
     if (g_out) HIP_OR_FAIL(G, hipMemcpyAsync(g_out, G->g2, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
@@ -365,35 +468,53 @@ int policy_out(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_o
   return PIRRT_OK;
 }
 
-// Renumbers the storage slots in breadth-first order of the graph from x_init
-// (vertex 0); vertices it cannot reach follow in their current order.
+// Renumbers the storage slots in breadth-first order of the graph, each problem
+// inside its own slot range from its x_init (its first vertex); vertices the BFS
+// cannot reach follow in their current order.
 int renumber(pirrt_graph* G) {
   const int32_t n = (int32_t)G->n;
+  const int32_t P = (int32_t)G->pbase.size() - 1;
   hipStream_t s = G->stream;
   int rc;
+  if (n == 0) return PIRRT_OK;
   if ((rc = ensure_spare(G, G->nnz))) return rc;
+  if ((rc = ensure_pcap(G, P))) return rc;
+  if ((rc = upload_bases(G))) return rc;
   int32_t* visited = G->pending;
-  int32_t* order = G->fr0;
+  int32_t* order = G->child;
+  int32_t* F = G->fr0;
+  int32_t* Fn = G->fr1;
+  // the problems' x_init slots
+  std::vector<int32_t> roots((size_t)P);
+  for (int32_t i = 0; i < P; ++i) roots[(size_t)i] = G->hslot[(size_t)G->pbase[(size_t)i]];
+  HIP_OR_FAIL(G, hipMemcpyAsync(Fn, roots.data(), sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(G, hipMemsetAsync(visited, 0, sizeof(int32_t) * (size_t)n, s));
-  launch_bfs_init(G->hslot[0], order, visited, &G->dcount[0], s);
-  int32_t lo = 0, hi = 1;
-  while (hi > lo) {
-    launch_graph_bfs_level(lo, hi, order, G->rp, G->col, visited, &G->dcount[0], s);
+  launch_bfs_init(P, Fn, G->dbase, order, visited, G->pscratch, F, &G->dcount[0], s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  int32_t fsize = P;
+  while (fsize > 0) {
+    HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[1], 0, sizeof(int32_t), s));
+    launch_graph_bfs_level(fsize, F, Fn, &G->dcount[1], order, problem_map(G), G->pscratch, G->rp, G->col, visited,
+                           s);
     HIP_OR_FAIL(G, hipGetLastError());
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[0], &G->dcount[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[1], &G->dcount[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    lo = hi;
-    hi = G->host->count[0];
-    if (hi > n) return fail_device(G, hipErrorUnknown, "renumbering visited too many vertices");
+    fsize = G->host->count[1];
+    if (fsize > n) return fail_device(G, hipErrorUnknown, "renumbering visited too many vertices");
+    std::swap(F, Fn);
   }
-  launch_append_unvisited(n, visited, order, &G->dcount[0], s);
-  HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[0], &G->dcount[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  launch_append_unvisited(n, visited, order, problem_map(G), G->pscratch, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  // every problem's range must be exactly full
+  std::vector<int32_t> cnt((size_t)P);
+  HIP_OR_FAIL(G, hipMemcpyAsync(cnt.data(), G->pscratch, sizeof(int32_t) * (size_t)P, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
-  if (G->host->count[0] != n) return fail_device(G, hipErrorUnknown, "renumbering lost vertices");
+  for (int32_t i = 0; i < P; ++i)
+    if (cnt[(size_t)i] != G->pbase[(size_t)i + 1]) return fail_device(G, hipErrorUnknown, "renumbering lost vertices");
   PermuteArgs a;
   a.n = n;
   a.order = order;
-  a.newslot = G->fr1;
+  a.newslot = G->child_ptr;
   a.deg = G->deg;
   a.rp = G->rp;
   a.col = G->col;
@@ -425,8 +546,498 @@ int renumber(pirrt_graph* G) {
   HIP_OR_FAIL(G, hipMemcpyAsync(G->hslot.data(), G->slot_of, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   G->reorder_n = n;
+  G->renumber_pending = false;
   G->snap_n = -1;  // a snapshot in the old order is no longer valid
+  drop_loops(G);
   return PIRRT_OK;
+}
+
+// Appends n_new vertices with forward rows.  With new_problem the block starts a
+// new problem of a batch and its rows use ids local to the block; otherwise the
+// rows use global ids and extend the last (only) problem.
+int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int32_t* col, const float* cost,
+                int mem_kind, bool new_problem) {
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if (n_new < 0) return fail(G, PIRRT_EINVAL, "n_new < 0");
+  if (n_new == 0 && !new_problem) return PIRRT_OK;
+  if (n_new == 0) return fail(G, PIRRT_EINVAL, "a problem needs at least one vertex");
+  if (!row_ptr) return fail(G, PIRRT_EINVAL, "row_ptr is NULL");
+  if (G->n + (int64_t)n_new > (int64_t)INT32_MAX - 1) return fail(G, PIRRT_EINVAL, "vertex ids beyond INT32_MAX");
+  hipStream_t s = G->stream;
+  int rc;
+  int64_t nnz_b = 0;
+  if (mem_kind == PIRRT_MEM_HOST) {
+    nnz_b = row_ptr[n_new];
+  } else {
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->word, row_ptr + n_new, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    nnz_b = G->host->word;
+  }
+  if (nnz_b < 0 || nnz_b > ((int64_t)1 << 40)) return fail(G, PIRRT_EINVAL, "row_ptr[n_new] out of range");
+  if (nnz_b > 0 && (!col || !cost)) return fail(G, PIRRT_EINVAL, "col or cost is NULL");
+  if ((rc = ensure_staging(G, n_new, nnz_b))) return rc;
+  const int64_t n_old = G->n, n1 = G->n + n_new;
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->brp, row_ptr, sizeof(int64_t) * (size_t)(n_new + 1), in_kind(mem_kind), s));
+  if (nnz_b > 0) {
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcol, col, sizeof(int32_t) * (size_t)nnz_b, in_kind(mem_kind), s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcost, cost, sizeof(float) * (size_t)nnz_b, in_kind(mem_kind), s));
+  }
+  if (new_problem) launch_offset_ids(nnz_b, (int32_t)n_old, G->bcol, s);  // local -> global ids
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
+  launch_validate_rows(n_new, n_old, new_problem ? n_old : 0, G->brp, G->bcol, G->bcost, nnz_b, G->dflag, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  int32_t bad = 0;
+  if ((rc = read_flag(G, &bad))) return rc;
+  if (bad) {
+    std::string m = "invalid batch:";
+    if (bad & 1) m += " row_ptr not 0-based / non-decreasing / bounded;";
+    if (bad & 2) m += new_problem ? " col outside [0, own local id);" : " col outside [0, own id);";
+    if (bad & 4) m += " cost not finite, negative or -0.0;";
+    return fail(G, PIRRT_EINVAL, m);
+  }
+  if ((rc = ensure_vcap(G, n1))) return rc;
+  if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) return rc;
+  // new vertices take the slots after the existing ones; neighbours to slots
+  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
+  launch_fill_i32(n_old, n1, new_problem ? (int32_t)G->pbase.size() - 1 : 0, G->prob, s);
+  launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
+  // adjacency rebuild into the spare arrays, then swap
+  launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
+                 G->deg, G->scan_scratch, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  std::swap(G->rp, G->rp2);
+  std::swap(G->col, G->col2);
+  std::swap(G->cst, G->cst2);
+  std::swap(G->ecap, G->ecap2);
+  G->n = n1;
+  G->nnz += 2 * nnz_b;
+  G->hslot.resize((size_t)n1);
+  for (int64_t v = n_old; v < n1; ++v) G->hslot[(size_t)v] = (int32_t)v;
+  if (new_problem)
+    G->pbase.push_back(n1);
+  else
+    G->pbase.back() = n1;
+  drop_loops(G);
+  // insertion-time policy, one dependency level at a time
+  const int32_t insert_root = new_problem ? (int32_t)n_old : (n_old == 0 ? 0 : -1);
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 2 * sizeof(int32_t), s));
+  launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  int64_t done = 0;
+  for (int level = 0;; ++level) {
+    const int cur = level & 1, nxt = cur ^ 1;
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[cur], &G->dcount[cur], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    const int32_t size = G->host->count[cur];
+    if (size == 0) break;
+    done += size;
+    if (done > n_new) return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
+    HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
+    launch_insert_level(size, cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp, G->bcol, G->bslot, G->bcost, G->rp,
+                        G->col, G->g, G->parent, G->pcost, G->pending, nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
+    HIP_OR_FAIL(G, hipGetLastError());
+  }
+  if (done != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
+  if (new_problem) {
+    G->renumber_pending = true;
+  } else if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
+    if ((rc = renumber(G))) return rc;
+  }
+  return PIRRT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The Replan loop.
+
+struct LoopArgs {
+  int32_t P;
+  bool prune;
+  StepArgs sa;
+  WalkArgs wa;
+  EvalArgs ea;
+};
+
+// Enqueues Evaluate for every problem that needs it (walk, or level-synchronous
+// for a single problem).
+void enqueue_evaluate(pirrt_graph* G, LoopArgs& L, hipStream_t s) {
+  if (G->eval_levels)
+    launch_evaluate(L.ea, s);
+  else
+    launch_eval_walk(L.wa, s);
+}
+
+// One iteration of Alg. 2 for every active problem.
+void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) {
+  launch_thresholds(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, s);
+  if (timing) (void)hipEventRecord(G->ev[2], s);
+  launch_mark(L.sa, G->row_variant, s);
+  if (timing) (void)hipEventRecord(G->ev[3], s);
+  launch_improve(L.sa, G->row_variant, s);
+  if (timing) (void)hipEventRecord(G->ev[4], s);
+  launch_finish(L.P, G->ps, G->ctr, G->ctl, s);
+  if (timing) (void)hipEventRecord(G->ev[0], s);
+  enqueue_evaluate(G, L, s);
+  if (timing) (void)hipEventRecord(G->ev[1], s);
+  launch_after_eval(L.P, G->ps, G->ctl, s);
+}
+
+LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
+  LoopKey k;
+  memset(&k, 0, sizeof(k));
+  const void* p[16] = {G->rp, G->col, G->cst, G->g, G->parent, G->pcost, G->stamp, G->word,
+                       G->ext_of, problem_map(G), G->ps, G->ctr, G->ctl, L.sa.h, G->child, G->lvl};
+  memcpy(k.ptrs, p, sizeof(p));
+  k.n = G->n;
+  k.nnz = G->nnz;
+  k.P = L.P;
+  k.prune = L.prune;
+  k.variant = G->row_variant;
+  k.walk_parts = G->walk_parts;
+  k.walk_coherent = G->walk_coherent;
+  k.eval_levels = G->eval_levels;
+  k.has_h = L.sa.h != nullptr;
+  k.iters = iters;
+  k.mid = L.ea.mid_launches;
+  return k;
+}
+
+// A captured loop body of 2^k iterations (built on first use, reused while every
+// baked pointer and size is unchanged).
+int loop_graph(pirrt_graph* G, LoopArgs& L, int k, hipGraphExec_t* out) {
+  const int iters = 1 << k;
+  const LoopKey key = loop_key(G, L, iters);
+  if (G->loop_exec[k] && G->loop_key[k] == key) {
+    *out = G->loop_exec[k];
+    return PIRRT_OK;
+  }
+  if (G->loop_exec[k]) {
+    (void)hipGraphExecDestroy(G->loop_exec[k]);
+    G->loop_exec[k] = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIP_OR_FAIL(G, hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < iters; ++i) enqueue_iteration(G, L, G->cap_stream, false);
+  hipError_t e = hipStreamEndCapture(G->cap_stream, &graph);
+  if (e != hipSuccess) return fail_device(G, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail_device(G, e, "hipGraphInstantiate");
+  G->loop_exec[k] = exec;
+  G->loop_key[k] = key;
+  *out = exec;
+  return PIRRT_OK;
+}
+
+// Runs Replan for P problems with the given root ids and root / goal slots.  h is
+// a device array in slot order (or NULL).  Fills per-problem stats (P entries,
+// nullable).
+int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t* root_slots,
+               const int32_t* goal_slots, const float* h, bool prune, bool timing, pirrt_stats* stats) {
+  hipStream_t s = G->stream;
+  int rc;
+  auto t_start = std::chrono::steady_clock::now();
+  if ((rc = ensure_pcap(G, P))) return rc;
+  const int32_t n = (int32_t)G->n;
+  const int64_t cap_iters = G->max_iters > 0 ? G->max_iters : 4 * (int64_t)n + 8;
+  for (int32_t i = 0; i < P; ++i) {
+    ProblemState& q = G->hps[i];
+    memset(&q, 0, sizeof(q));
+    q.root = root_slots[i];
+    q.goal = goal_slots[i];
+    q.active = 1;
+    q.needs_eval = 1;
+    q.cap = (int32_t)std::min<int64_t>(cap_iters, INT32_MAX);
+  }
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->ps, G->hps, sizeof(ProblemState) * (size_t)P, hipMemcpyHostToDevice, s));
+  // the previous roots lose their mark; the new roots get it
+  launch_unmark_roots(G->nroots, G->droots, G->slot_of, G->parent, s);
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, root_ids, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
+  G->nroots = P;
+  G->hroots.assign(root_ids, root_ids + P);
+  launch_replan_init(P, G->ps, G->parent, G->pcost, G->ctr, G->ctl, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+
+  LoopArgs L;
+  L.P = P;
+  L.prune = prune;
+  StepArgs& sa = L.sa;
+  sa.n = n;
+  sa.nnz = G->nnz;
+  sa.prob = problem_map(G);
+  sa.ps = G->ps;
+  sa.ctl = G->ctl;
+  sa.g = G->g;
+  sa.h = h;
+  sa.rp = G->rp;
+  sa.col = G->col;
+  sa.cst = G->cst;
+  sa.stamp = G->stamp;
+  sa.ext_of = G->ext_of;
+  sa.parent = G->parent;
+  sa.pcost = G->pcost;
+  sa.ctr = G->ctr;
+  WalkArgs& wa = L.wa;
+  wa.n = n;
+  wa.prob = problem_map(G);
+  wa.ps = G->ps;
+  wa.ctl = G->ctl;
+  wa.parent = G->parent;
+  wa.pcost = G->pcost;
+  wa.g = G->g;
+  wa.word = G->word;
+  wa.hops = G->trace ? G->dhops : nullptr;
+  wa.parts = G->walk_parts;
+  wa.coherent = G->walk_coherent;
+  EvalArgs& ea = L.ea;
+  ea.n = n;
+  ea.root = root_slots[0];
+  ea.ps = G->ps;
+  ea.parent = G->parent;
+  ea.pcost = G->pcost;
+  ea.g = G->g;
+  ea.child_cnt = G->child_cnt;
+  ea.child_ptr = G->child_ptr;
+  ea.child = G->child;
+  ea.fr0 = G->fr0;
+  ea.fr1 = G->fr1;
+  ea.lvl = G->lvl;
+  ea.info = G->info;
+  ea.scan_scratch = G->scan_scratch;
+  ea.mid_launches = std::max(0, std::min(std::min(G->mid_hint, kMaxMidLaunches), n));
+  int64_t lb = (int64_t)n / 2048;
+  ea.level_blocks = (int32_t)(lb < 16 ? 16 : (lb > 1024 ? 1024 : lb));
+  if (G->eval_levels && P != 1) return fail(G, PIRRT_EINVAL, "the level-synchronous Evaluate takes one problem");
+
+  pirrt_stats agg;
+  memset(&agg, 0, sizeof(agg));
+  // first Evaluate of every problem
+  if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[0], s));
+  if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
+  enqueue_evaluate(G, L, s);
+  if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
+  launch_after_eval(P, G->ps, G->ctl, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  if (timing) {
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    agg.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
+    agg.evaluate_calls += 1;
+  }
+
+  const bool direct = timing || G->trace || !G->use_graph;
+  int64_t done_iters = 0;
+  if (direct) {
+    for (int it = 0;; ++it) {
+      if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
+      enqueue_iteration(G, L, s, timing);
+      HIP_OR_FAIL(G, hipGetLastError());
+      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->ctl, G->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
+      if (G->trace) {
+        HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->hops, G->dhops, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(G, hipMemcpyAsync(G->hps, G->ps, sizeof(ProblemState) * (size_t)P, hipMemcpyDeviceToHost, s));
+      }
+      HIP_OR_FAIL(G, hipStreamSynchronize(s));
+      ++done_iters;
+      if (timing) {
+        agg.ms_mark += elapsed_ms(G->ev[2], G->ev[3]);
+        agg.ms_improve += elapsed_ms(G->ev[3], G->ev[4]);
+        agg.mark_launches += 1;
+        agg.improve_launches += 1;
+        if (G->host->ctl.any_active) {  // the Evaluate after the last Improve is a no-op
+          agg.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
+          agg.evaluate_calls += 1;
+        }
+      }
+      if (G->trace)
+        fprintf(stderr, "pirrt iter %d: problem 0 iterations %d edges %llu changed %llu; walk hops %llu\n", it + 1,
+                G->hps[0].iterations, (unsigned long long)G->hps[0].edges,
+                (unsigned long long)G->hps[0].changed_total, (unsigned long long)G->host->hops);
+      if (!G->host->ctl.any_active) break;
+      if (done_iters > cap_iters + 1) return fail_device(G, hipErrorUnknown, "Replan loop did not stop");
+    }
+  } else {
+    // Planned launches: as many loop bodies as the previous Replan needed, back to
+    // back, then one iteration at a time until every problem has stopped.
+    int64_t plan = G->last_iterations > 0 ? G->last_iterations : 8;
+    for (;;) {
+      const int k = plan >= 8 ? 3 : plan >= 4 ? 2 : plan >= 2 ? 1 : 0;
+      hipGraphExec_t exec = nullptr;
+      if ((rc = loop_graph(G, L, k, &exec))) return rc;
+      HIP_OR_FAIL(G, hipGraphLaunch(exec, s));
+      done_iters += 1 << k;
+      plan -= 1 << k;
+      if (plan > 0) continue;
+      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->ctl, G->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(G, hipStreamSynchronize(s));
+      if (!G->host->ctl.any_active) break;
+      if (done_iters > cap_iters + 8) return fail_device(G, hipErrorUnknown, "Replan loop did not stop");
+      plan = 1;
+    }
+  }
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->hps, G->ps, sizeof(ProblemState) * (size_t)P, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  int32_t most = 0;
+  bool capped = false;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  for (int32_t i = 0; i < P; ++i) {
+    const ProblemState& q = G->hps[i];
+    most = std::max(most, q.iterations);
+    capped = capped || q.status != 0;
+    if (stats) {
+      pirrt_stats& st = stats[i];
+      memset(&st, 0, sizeof(st));
+      st.iterations = q.iterations;
+      st.edges_examined = (int64_t)q.edges;
+      st.sum_P = (int64_t)q.sum_P;
+      st.sum_D = (int64_t)q.sum_D;
+      st.changed_total = (int64_t)q.changed_total;
+      st.ms_total = ms;
+      st.evaluate_calls = timing ? agg.evaluate_calls : q.iterations;
+      if (P == 1) {
+        st.ms_evaluate = agg.ms_evaluate;
+        st.ms_mark = agg.ms_mark;
+        st.ms_improve = agg.ms_improve;
+        st.improve_launches = agg.improve_launches;
+        st.mark_launches = agg.mark_launches;
+      }
+    }
+  }
+  G->last_iterations = most;
+  if (capped) return fail(G, PIRRT_ENOTCONVERGED, "iteration cap reached");
+  return PIRRT_OK;
+}
+
+// Copies and validates a caller h (caller order) into slot order in hbuf.
+int stage_h(pirrt_graph* G, const float* h, int mem_kind, const float** out) {
+  *out = nullptr;
+  if (!h) return PIRRT_OK;
+  const int32_t n = (int32_t)G->n;
+  hipStream_t s = G->stream;
+  int rc;
+  const float* hsrc = h;
+  if (mem_kind == PIRRT_MEM_HOST) {
+    for (int32_t v = 0; v < n; ++v)
+      if (!(h[v] >= 0.0f)) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->g2, h, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+    hsrc = G->g2;
+  } else {
+    HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_check_h, dim3(grid_for(n)), dim3(256), 0, s, n, h, G->dflag);
+    HIP_OR_FAIL(G, hipGetLastError());
+    int32_t bad = 0;
+    if ((rc = read_flag(G, &bad))) return rc;
+    if (bad) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
+  }
+  launch_gather_by_slot(n, G->ext_of, hsrc, G->hbuf, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  *out = G->hbuf;
+  return PIRRT_OK;
+}
+
+pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
+  *rc_out = PIRRT_OK;
+  pirrt_config c;
+  memset(&c, 0, sizeof(c));
+  c.device = -1;
+  if (cfg) c = *cfg;
+  if (c.vertex_capacity < 0 || c.edge_capacity < 0 || c.max_iters < 0) {
+    g_create_error = "negative capacity or iteration cap";
+    *rc_out = PIRRT_EINVAL;
+    return nullptr;
+  }
+  pirrt_graph* G = new (std::nothrow) pirrt_graph();
+  if (!G) {
+    *rc_out = PIRRT_ENOMEM;
+    return nullptr;
+  }
+  int dev = c.device;
+  if (dev < 0) {
+    if (hipGetDevice(&dev) != hipSuccess) {
+      (void)hipGetLastError();
+      delete G;
+      g_create_error = "no HIP device";
+      *rc_out = PIRRT_EDEVICE;
+      return nullptr;
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
+    (void)hipGetLastError();
+    delete G;
+    g_create_error = "HIP device not available";
+    *rc_out = PIRRT_EDEVICE;
+    return nullptr;
+  }
+  G->device = dev;
+  G->stream = (hipStream_t)c.hip_stream;
+  G->max_iters = c.max_iters;
+  if (hipSetDevice(dev) != hipSuccess) {
+    (void)hipGetLastError();
+    delete G;
+    g_create_error = "hipSetDevice failed";
+    *rc_out = PIRRT_EDEVICE;
+    return nullptr;
+  }
+  bool ok = dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 2) && dalloc(&G->dhops, 1) &&
+            dalloc(&G->ctl, 1);
+  if (ok && hipHostMalloc((void**)&G->host, sizeof(HostBlock), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    G->host = nullptr;
+    ok = false;
+  }
+  for (auto& e : G->ev)
+    if (ok && hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      ok = false;
+    }
+  if (ok && hipStreamCreate(&G->cap_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    G->cap_stream = nullptr;
+    ok = false;
+  }
+  if (ok && hipMemset(G->ctl, 0, sizeof(LoopCtl)) != hipSuccess) {
+    (void)hipGetLastError();
+    ok = false;
+  }
+  int rc = PIRRT_OK;
+  if (ok) rc = ensure_vcap(G, c.vertex_capacity > kMinVertexCap ? c.vertex_capacity : kMinVertexCap);
+  if (ok && rc == PIRRT_OK && c.edge_capacity > 0) {
+    rc = ensure_spare(G, c.edge_capacity);
+    if (rc == PIRRT_OK) {
+      std::swap(G->col, G->col2);
+      std::swap(G->cst, G->cst2);
+      std::swap(G->ecap, G->ecap2);
+      rc = ensure_spare(G, c.edge_capacity);
+    }
+  }
+  if (ok && rc == PIRRT_OK) rc = ensure_pcap(G, 1);
+  if (!ok || rc != PIRRT_OK || hipStreamSynchronize(G->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_error = ok ? G->err : "device allocation failed at create";
+    release_all(G);
+    delete G;
+    *rc_out = ok ? (rc ? rc : PIRRT_EDEVICE) : PIRRT_ENOMEM;
+    return nullptr;
+  }
+  const char* growth = getenv("PIRRT_REORDER_GROWTH");
+  if (growth) G->reorder_growth = atof(growth);
+  const char* tr = getenv("PIRRT_TRACE");
+  G->trace = tr && atoi(tr) > 0;
+  const char* ev = getenv("PIRRT_EVALUATE");
+  if (ev && strcmp(ev, "levels") == 0) G->eval_levels = true;
+  const char* wp = getenv("PIRRT_WALK_PARTS");
+  if (wp && atoi(wp) >= 1) G->walk_parts = atoi(wp);
+  const char* wc = getenv("PIRRT_WALK_COHERENT");
+  if (wc) G->walk_coherent = atoi(wc) != 0;
+  const char* gr = getenv("PIRRT_GRAPH");
+  if (gr) G->use_graph = atoi(gr) != 0;
+  const char* variant = getenv("PIRRT_ROW_VARIANT");
+  if (variant) {
+    int v = atoi(variant);
+    if (v >= 0 && v < kRowVariants) G->row_variant = v;
+  }
+  return G;
 }
 
 }  // namespace
@@ -443,108 +1054,9 @@ int pirrt_config_init(pirrt_config* cfg) {
 int pirrt_graph_create(pirrt_graph** out, const pirrt_config* cfg) {
   if (!out) return PIRRT_EINVAL;
   *out = nullptr;
-  pirrt_config c;
-  pirrt_config_init(&c);
-  if (cfg) c = *cfg;
-  if (c.vertex_capacity < 0 || c.edge_capacity < 0 || c.max_iters < 0) {
-    g_create_error = "negative capacity or iteration cap";
-    return PIRRT_EINVAL;
-  }
-  pirrt_graph* G = new (std::nothrow) pirrt_graph();
-  if (!G) return PIRRT_ENOMEM;
-  int dev = c.device;
-  if (dev < 0) {
-    if (hipGetDevice(&dev) != hipSuccess) {
-      (void)hipGetLastError();
-      delete G;
-      g_create_error = "no HIP device";
-      return PIRRT_EDEVICE;
-    }
-  }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
-    (void)hipGetLastError();
-    delete G;
-    g_create_error = "HIP device not available";
-    return PIRRT_EDEVICE;
-  }
-  G->device = dev;
-  G->stream = (hipStream_t)c.hip_stream;
-  {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      G->max_blocks = cus * 8;
-    else
-      (void)hipGetLastError();
-  }
-  G->max_iters = c.max_iters;
-  if (hipSetDevice(dev) != hipSuccess) {
-    (void)hipGetLastError();
-    delete G;
-    g_create_error = "hipSetDevice failed";
-    return PIRRT_EDEVICE;
-  }
-  bool ok = dalloc(&G->ctr, kCounterSlots) && dalloc(&G->dhops, 1) && dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 2);
-  if (ok && hipHostMalloc((void**)&G->host, sizeof(HostBlock), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    G->host = nullptr;
-    ok = false;
-  }
-  for (auto& e : G->ev)
-    if (ok && hipEventCreate(&e) != hipSuccess) {
-      (void)hipGetLastError();
-      e = nullptr;
-      ok = false;
-    }
-  int rc = PIRRT_OK;
-  if (ok && c.vertex_capacity > 0) rc = ensure_vcap(G, c.vertex_capacity);
-  if (ok && rc == PIRRT_OK && c.edge_capacity > 0) {
-    rc = ensure_spare(G, c.edge_capacity);
-    if (rc == PIRRT_OK) {
-      std::swap(G->col, G->col2);
-      std::swap(G->cst, G->cst2);
-      std::swap(G->ecap, G->ecap2);
-      rc = ensure_spare(G, c.edge_capacity);
-    }
-  }
-  if (!ok || rc != PIRRT_OK) {
-    g_create_error = ok ? G->err : "device allocation failed at create";
-    release_all(G);
-    delete G;
-    return ok ? rc : PIRRT_ENOMEM;
-  }
-  if (ensure_vcap(G, kMinVertexCap) != PIRRT_OK) {
-    g_create_error = G->err;
-    release_all(G);
-    delete G;
-    return PIRRT_ENOMEM;
-  }
-  // the row offsets of the empty graph
-  if (hipMemsetAsync(G->rp, 0, sizeof(int64_t), G->stream) != hipSuccess ||
-      hipStreamSynchronize(G->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    g_create_error = "initialising the graph failed";
-    release_all(G);
-    delete G;
-    return PIRRT_EDEVICE;
-  }
-  const char* growth = getenv("PIRRT_REORDER_GROWTH");
-  if (growth) G->reorder_growth = atof(growth);
-  const char* tr = getenv("PIRRT_TRACE");
-  G->trace = tr && atoi(tr) > 0;
-  const char* ev = getenv("PIRRT_EVALUATE");
-  if (ev && strcmp(ev, "levels") == 0) G->eval_levels = true;
-  const char* wp = getenv("PIRRT_WALK_PARTS");
-  if (wp && atoi(wp) >= 1) G->walk_parts = atoi(wp);
-  const char* wc = getenv("PIRRT_WALK_COHERENT");
-  if (wc) G->walk_coherent = atoi(wc) != 0;
-  const char* variant = getenv("PIRRT_ROW_VARIANT");
-  if (variant) {
-    int v = atoi(variant);
-    if (v >= 0 && v < kRowVariants) G->row_variant = v;
-  }
-  const char* blocks = getenv("PIRRT_MAX_BLOCKS");
-  if (blocks && atoi(blocks) >= 8) G->max_blocks = atoi(blocks);
+  int rc;
+  pirrt_graph* G = new_graph(cfg, &rc);
+  if (!G) return rc;
   *out = G;
   return PIRRT_OK;
 }
@@ -581,254 +1093,39 @@ int pirrt_insert_batch(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, co
                        int mem_kind) {
   int rc = guard(G);
   if (rc) return rc;
-  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
-  if (n_new < 0) return fail(G, PIRRT_EINVAL, "n_new < 0");
-  if (n_new == 0) return PIRRT_OK;
-  if (!row_ptr) return fail(G, PIRRT_EINVAL, "row_ptr is NULL");
-  if (G->n + (int64_t)n_new > (int64_t)INT32_MAX - 1) return fail(G, PIRRT_EINVAL, "vertex ids beyond INT32_MAX");
-  hipStream_t s = G->stream;
-  int64_t nnz_b = 0;
-  if (mem_kind == PIRRT_MEM_HOST) {
-    nnz_b = row_ptr[n_new];
-  } else {
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->word, row_ptr + n_new, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    nnz_b = G->host->word;
-  }
-  if (nnz_b < 0 || nnz_b > ((int64_t)1 << 40)) return fail(G, PIRRT_EINVAL, "row_ptr[n_new] out of range");
-  if (nnz_b > 0 && (!col || !cost)) return fail(G, PIRRT_EINVAL, "col or cost is NULL");
-  if ((rc = ensure_staging(G, n_new, nnz_b))) return rc;
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->brp, row_ptr, sizeof(int64_t) * (size_t)(n_new + 1), in_kind(mem_kind), s));
-  if (nnz_b > 0) {
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcol, col, sizeof(int32_t) * (size_t)nnz_b, in_kind(mem_kind), s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcost, cost, sizeof(float) * (size_t)nnz_b, in_kind(mem_kind), s));
-  }
-  HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
-  launch_validate_rows(n_new, G->n, G->brp, G->bcol, G->bcost, nnz_b, G->dflag, s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  int32_t bad = 0;
-  if ((rc = read_flag(G, &bad))) return rc;
-  if (bad) {
-    std::string m = "invalid batch:";
-    if (bad & 1) m += " row_ptr not 0-based / non-decreasing / bounded;";
-    if (bad & 2) m += " col outside [0, own id);";
-    if (bad & 4) m += " cost not finite, negative or -0.0;";
-    return fail(G, PIRRT_EINVAL, m);
-  }
-  const int64_t n_old = G->n, n1 = G->n + n_new;
-  if ((rc = ensure_vcap(G, n1))) return rc;
-  if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) return rc;
-  // new vertices take the slots after the existing ones; neighbours to slots
-  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
-  launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
-  // adjacency rebuild into the spare arrays, then swap
-  launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
-                 G->deg, G->scan_scratch, s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  std::swap(G->rp, G->rp2);
-  std::swap(G->col, G->col2);
-  std::swap(G->cst, G->cst2);
-  std::swap(G->ecap, G->ecap2);
-  G->n = n1;
-  G->nnz += 2 * nnz_b;
-  G->hslot.resize((size_t)n1);
-  for (int64_t v = n_old; v < n1; ++v) G->hslot[(size_t)v] = (int32_t)v;
-  // insertion-time policy, one dependency level at a time
-  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 2 * sizeof(int32_t), s));
-  launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  int64_t done = 0;
-  for (int level = 0;; ++level) {
-    const int cur = level & 1, nxt = cur ^ 1;
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[cur], &G->dcount[cur], sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    const int32_t size = G->host->count[cur];
-    if (size == 0) break;
-    done += size;
-    if (done > n_new) return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
-    HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
-    launch_insert_level(size, cur ? G->fr1 : G->fr0, n_old, G->brp, G->bcol, G->bslot, G->bcost, G->rp, G->col,
-                        G->g, G->parent, G->pcost, G->pending, nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
-    HIP_OR_FAIL(G, hipGetLastError());
-  }
-  if (done != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
-  if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
-    if ((rc = renumber(G))) return rc;
-  }
-  return PIRRT_OK;
+  if (G->batched) return fail(G, PIRRT_EINVAL, "this handle holds a batch of problems");
+  return insert_rows(G, n_new, row_ptr, col, cost, mem_kind, false);
 }
 
 int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uint32_t flags, float* g_out,
                  int32_t* parent_out, int mem_kind, pirrt_stats* stats) {
   int rc = guard(G);
   if (rc) return rc;
-  auto t_start = std::chrono::steady_clock::now();
+  if (G->batched) return fail(G, PIRRT_EINVAL, "this handle holds a batch of problems");
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
   if (G->n <= 0) return fail(G, PIRRT_EINVAL, "empty graph");
   if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
-  const int32_t n = (int32_t)G->n;
-  hipStream_t s = G->stream;
-  const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   const float* hdev = nullptr;
-  if (h) {
-    const float* hsrc = h;
-    if (mem_kind == PIRRT_MEM_HOST) {
-      for (int32_t v = 0; v < n; ++v)
-        if (!(h[v] >= 0.0f)) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
-      HIP_OR_FAIL(G, hipMemcpyAsync(G->g2, h, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
-      hsrc = G->g2;
-    } else {
-      HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
-      hipLaunchKernelGGL(k_check_h, dim3(grid_for(n)), dim3(256), 0, s, n, h, G->dflag);
-      HIP_OR_FAIL(G, hipGetLastError());
-      int32_t bad = 0;
-      if ((rc = read_flag(G, &bad))) return rc;
-      if (bad) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
-    }
-    launch_gather_by_slot(n, G->ext_of, hsrc, G->hbuf, s);
-    HIP_OR_FAIL(G, hipGetLastError());
-    hdev = G->hbuf;
-  }
-  const bool timing = (flags & PIRRT_TIMING) != 0;
-  const int64_t cap = G->max_iters > 0 ? G->max_iters : 4 * (int64_t)n + 8;
+  if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   pirrt_stats st;
-  memset(&st, 0, sizeof(st));
-
-  EvalArgs ea;
-  ea.n = n;
-  ea.root = rslot;
-  ea.parent = G->parent;
-  ea.pcost = G->pcost;
-  ea.g = G->g;
-  ea.child_cnt = G->child_cnt;
-  ea.child_ptr = G->child_ptr;
-  ea.child = G->child;
-  ea.fr0 = G->fr0;
-  ea.fr1 = G->fr1;
-  ea.lvl = G->lvl;
-  ea.info = G->info;
-  ea.ctr = G->ctr;
-  ea.scan_scratch = G->scan_scratch;
-  int64_t lb = (int64_t)n / 2048;
-  ea.level_blocks = (int32_t)(lb < 16 ? 16 : (lb > 1024 ? 1024 : lb));
-
-  StepArgs sa;
-  sa.n = n;
-  sa.root = rslot;
-  sa.goal = gslot;
-  sa.prune = (flags & PIRRT_NO_PRUNE) ? 0 : 1;
-  sa.g = G->g;
-  sa.h = hdev;
-  sa.rp = G->rp;
-  sa.col = G->col;
-  sa.cst = G->cst;
-  sa.stamp = G->stamp;
-  sa.ext_of = G->ext_of;
-  sa.parent = G->parent;
-  sa.pcost = G->pcost;
-  sa.ctr = G->ctr;
-  sa.max_blocks = G->max_blocks;
-
-  auto evaluate = [&]() -> int {
-    int32_t mid = G->mid_hint;
-    if (mid < 0) mid = 0;
-    if (mid > kMaxMidLaunches) mid = kMaxMidLaunches;
-    if (mid > n) mid = n;
-    ea.mid_launches = mid;
-    if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[0], s));
-    if (G->eval_levels) {
-      launch_evaluate(ea, s);
-    } else {
-      if (++G->eval_epoch == 0) {
-        HIP_OR_FAIL(G, hipMemsetAsync(G->word, 0, sizeof(unsigned long long) * (size_t)G->vcap, s));
-        G->eval_epoch = 1;
-      }
-      if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
-      launch_eval_walk(n, rslot, G->eval_epoch, G->parent, G->pcost, G->g, G->word, G->ctr,
-                       G->trace ? G->dhops : nullptr, G->walk_parts, G->walk_coherent, s);
-    }
-    HIP_OR_FAIL(G, hipGetLastError());
-    if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
-    st.evaluate_calls += 1;
-    return PIRRT_OK;
-  };
-
-  // the root has no parent (Alg. 2 walks the policy tree from x_init)
-  HIP_OR_FAIL(G, hipMemsetAsync(G->parent + rslot, 0xff, sizeof(int32_t), s));
-  HIP_OR_FAIL(G, hipMemsetAsync(G->pcost + rslot, 0, sizeof(float), s));
-  if ((rc = evaluate())) return rc;
-  bool pending_eval_time = timing;
-  for (;;) {
-    if (++G->epoch == 0) {
-      HIP_OR_FAIL(G, hipMemsetAsync(G->stamp, 0, sizeof(uint32_t) * (size_t)G->vcap, s));
-      G->epoch = 1;
-    }
-    sa.epoch = G->epoch;
-    if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[2], s));
-    launch_mark(sa, G->row_variant, s);
-    HIP_OR_FAIL(G, hipGetLastError());
-    if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[3], s));
-    launch_improve(sa, G->row_variant, s);
-    HIP_OR_FAIL(G, hipGetLastError());
-    if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[4], s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->ctr, G->ctr, sizeof(IterCounters) * kCounterSlots, hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->info, G->info, sizeof(EvalInfo), hipMemcpyDeviceToHost, s));
-    if (G->trace)
-      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->hops, G->dhops, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    if (timing) {
-      if (pending_eval_time) st.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
-      pending_eval_time = false;
-      st.ms_mark += elapsed_ms(G->ev[2], G->ev[3]);
-      st.ms_improve += elapsed_ms(G->ev[3], G->ev[4]);
-      st.mark_launches += 1;
-      st.improve_launches += 1;
-    }
-    IterCounters c{};
-    for (int k = 0; k < kCounterSlots; ++k) {
-      c.changed += G->host->ctr[k].changed;
-      c.nP += G->host->ctr[k].nP;
-      c.nD += G->host->ctr[k].nD;
-      c.edges += G->host->ctr[k].edges;
-    }
-    const EvalInfo info = G->host->info;
-    st.iterations += 1;
-    st.edges_examined += (int64_t)c.edges;
-    st.sum_P += c.nP;
-    st.sum_D += c.nD;
-    st.changed_total += c.changed;
-    if (G->trace)
-      fprintf(stderr, "pirrt iter %d: |P| %d |D| %d edges %llu changed %d walk hops %llu\n", st.iterations, c.nP,
-              c.nD, (unsigned long long)c.edges, c.changed, G->eval_levels ? 0ull : G->host->hops);
-    st.eval_levels = info.levels;
-    // wide level launches for the next walk: the large levels seen this time, plus slack
-    int32_t need = info.big_end - info.head_end;
-    G->mid_hint = (need > 0 ? need : 0) + 2;
-    if (c.changed == 0) break;
-    if ((rc = evaluate())) return rc;
-    pending_eval_time = timing;
-    if (st.iterations >= cap) {
-      rc = PIRRT_ENOTCONVERGED;
-      break;
-    }
-  }
-  if ((rc == PIRRT_OK || rc == PIRRT_ENOTCONVERGED) && (g_out || parent_out)) {
-    const int keep = rc;
+  rc = run_replan(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, (flags & PIRRT_TIMING) != 0,
+                  &st);
+  if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
+  const int keep = rc;
+  if (g_out || parent_out) {
     if ((rc = policy_out(G, g_out, parent_out, nullptr, mem_kind))) return rc;
-    rc = keep;
   }
-  HIP_OR_FAIL(G, hipStreamSynchronize(s));
-  if (timing && pending_eval_time) st.ms_evaluate += elapsed_ms(G->ev[0], G->ev[1]);
-  st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   if (stats) *stats = st;
-  if (rc == PIRRT_ENOTCONVERGED) return fail(G, rc, "iteration cap reached");
-  return PIRRT_OK;
+  return keep;
 }
 
 int pirrt_get_policy(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {
   int rc = guard(G);
   if (rc) return rc;
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if (G->batched && (rc = upload_bases(G))) return rc;
   if ((rc = policy_out(G, g_out, parent_out, pcost_out, mem_kind))) return rc;
   HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   return PIRRT_OK;
@@ -843,16 +1140,21 @@ int pirrt_set_policy(pirrt_graph* G, const float* g_in, const int32_t* parent_in
   const int32_t n = (int32_t)G->n;
   if (n == 0) return PIRRT_OK;
   hipStream_t s = G->stream;
+  if (G->batched && (rc = upload_bases(G))) return rc;
   if (mem_kind == PIRRT_MEM_HOST) {
+    size_t pi = 0;
     for (int32_t v = 0; v < n; ++v) {
+      while (G->batched && v >= G->pbase[pi + 1]) ++pi;
+      const int64_t b = G->batched ? G->pbase[pi] : 0, len = G->batched ? G->pbase[pi + 1] - b : n;
       uint32_t w;
       memcpy(&w, &pcost_in[v], 4);
-      if (parent_in[v] < -1 || parent_in[v] >= n || parent_in[v] == v) return fail(G, PIRRT_EINVAL, "bad parent");
+      if (parent_in[v] < -1 || parent_in[v] >= len || parent_in[v] == v - b) return fail(G, PIRRT_EINVAL, "bad parent");
       if ((w >> 31) != 0 || (w & 0x7f800000u) == 0x7f800000u) return fail(G, PIRRT_EINVAL, "bad pcost");
     }
   } else {
     HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_check_policy, dim3(grid_for(n)), dim3(256), 0, s, n, parent_in, pcost_in, G->dflag);
+    hipLaunchKernelGGL(k_check_policy, dim3(grid_for(n)), dim3(256), 0, s, n, parent_in, pcost_in, problem_map(G),
+                       base_map(G), G->dflag);
     HIP_OR_FAIL(G, hipGetLastError());
     int32_t bad = 0;
     if ((rc = read_flag(G, &bad))) return rc;
@@ -869,15 +1171,18 @@ int pirrt_set_policy(pirrt_graph* G, const float* g_in, const int32_t* parent_in
     ps = G->parent2;
     cs = G->pcost2;
   }
-  launch_policy_from_ext(n, G->slot_of, gs, ps, cs, G->g, G->parent, G->pcost, s);
+  launch_policy_from_ext(n, G->slot_of, problem_map(G), base_map(G), gs, ps, cs, G->g, G->parent, G->pcost, s);
   HIP_OR_FAIL(G, hipGetLastError());
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  G->nroots = 0;  // the new policy carries no root marks
+  G->hroots.clear();
   return PIRRT_OK;
 }
 
 int pirrt_snapshot_save(pirrt_graph* G) {
   int rc = guard(G);
   if (rc) return rc;
+  if (G->batched && G->renumber_pending && (rc = renumber(G))) return rc;
   const int64_t n = G->n;
   if (n > G->snap_cap) {
     float* a = nullptr;
@@ -905,6 +1210,7 @@ int pirrt_snapshot_save(pirrt_graph* G) {
   }
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   G->snap_n = n;
+  G->snap_roots = G->hroots;
   return PIRRT_OK;
 }
 
@@ -919,7 +1225,15 @@ int pirrt_snapshot_restore(pirrt_graph* G) {
     HIP_OR_FAIL(G, hipMemcpyAsync(G->parent, G->sparent, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost, G->spcost, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice, s));
   }
+  // the restored parents carry the snapshot's root marks
+  const int32_t m = (int32_t)G->snap_roots.size();
+  if ((rc = ensure_pcap(G, m))) return rc;
+  if (m > 0)
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, G->snap_roots.data(), sizeof(int32_t) * (size_t)m,
+                                  hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  G->nroots = m;
+  G->hroots = G->snap_roots;
   return PIRRT_OK;
 }
 
@@ -956,5 +1270,102 @@ int pirrt_get_adjacency(pirrt_graph* G, int64_t* ptr, int32_t* nbr, float* cost,
   if (m && cost) HIP_OR_FAIL(G, hipMemcpy(cost, out_cst.data(), sizeof(float) * m, kind));
   return PIRRT_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems.
+
+int pirrt_batch_create(pirrt_batch** out, const pirrt_config* cfg) {
+  if (!out) return PIRRT_EINVAL;
+  *out = nullptr;
+  int rc;
+  pirrt_graph* G = new_graph(cfg, &rc);
+  if (!G) return rc;
+  G->batched = true;
+  G->pbase.assign(1, 0);
+  pirrt_batch* B = new (std::nothrow) pirrt_batch();
+  if (!B) {
+    pirrt_graph_destroy(G);
+    return PIRRT_ENOMEM;
+  }
+  B->G = G;
+  *out = B;
+  return PIRRT_OK;
+}
+
+int pirrt_batch_destroy(pirrt_batch* B) {
+  if (!B) return PIRRT_OK;
+  pirrt_graph_destroy(B->G);
+  delete B;
+  return PIRRT_OK;
+}
+
+int pirrt_batch_add_problem(pirrt_batch* B, int32_t n, const int64_t* row_ptr, const int32_t* col, const float* cost,
+                            int mem_kind, int32_t* index) {
+  if (!B) return PIRRT_EINVAL;
+  pirrt_graph* G = B->G;
+  int rc = guard(G);
+  if (rc) return rc;
+  if (n <= 0) return fail(G, PIRRT_EINVAL, "a problem needs at least one vertex");
+  const int32_t id = (int32_t)G->pbase.size() - 1;
+  if ((rc = insert_rows(G, n, row_ptr, col, cost, mem_kind, true))) return rc;
+  if (index) *index = id;
+  return PIRRT_OK;
+}
+
+int32_t pirrt_batch_num_problems(const pirrt_batch* B) { return B ? (int32_t)B->G->pbase.size() - 1 : -1; }
+int64_t pirrt_batch_num_vertices(const pirrt_batch* B) { return B ? B->G->n : -1; }
+int64_t pirrt_batch_num_edges(const pirrt_batch* B) { return B ? B->G->nnz : -1; }
+
+int64_t pirrt_batch_problem_offset(const pirrt_batch* B, int32_t problem) {
+  if (!B || problem < 0 || problem >= (int32_t)B->G->pbase.size()) return -1;
+  return B->G->pbase[(size_t)problem];
+}
+
+int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goals, const float* h, uint32_t flags,
+                       float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats) {
+  if (!B) return PIRRT_EINVAL;
+  pirrt_graph* G = B->G;
+  int rc = guard(G);
+  if (rc) return rc;
+  const int32_t P = (int32_t)G->pbase.size() - 1;
+  if (P <= 0) return fail(G, PIRRT_EINVAL, "empty batch");
+  if (!roots || !goals) return fail(G, PIRRT_EINVAL, "roots or goals is NULL");
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  for (int32_t i = 0; i < P; ++i) {
+    const int64_t b = G->pbase[(size_t)i], len = G->pbase[(size_t)i + 1] - b;
+    if (roots[i] < 0 || roots[i] >= len || goals[i] < 0 || goals[i] >= len)
+      return fail(G, PIRRT_EINVAL, "root or goal out of range in problem " + std::to_string(i));
+  }
+  if (G->renumber_pending && (rc = renumber(G))) return rc;
+  if ((rc = upload_bases(G))) return rc;
+  std::vector<int32_t> rid((size_t)P), rs((size_t)P), gs((size_t)P);
+  for (int32_t i = 0; i < P; ++i) {
+    const int64_t b = G->pbase[(size_t)i];
+    rid[(size_t)i] = (int32_t)(b + roots[i]);
+    rs[(size_t)i] = G->hslot[(size_t)(b + roots[i])];
+    gs[(size_t)i] = G->hslot[(size_t)(b + goals[i])];
+  }
+  const float* hdev = nullptr;
+  if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  rc = run_replan(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0,
+                  (flags & PIRRT_TIMING) != 0, stats);
+  if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
+  const int keep = rc;
+  if (g_out || parent_out) {
+    if ((rc = policy_out(G, g_out, parent_out, nullptr, mem_kind))) return rc;
+  }
+  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
+  return keep;
+}
+
+int pirrt_batch_get_policy(pirrt_batch* B, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {
+  return B ? pirrt_get_policy(B->G, g_out, parent_out, pcost_out, mem_kind) : PIRRT_EINVAL;
+}
+
+int pirrt_batch_snapshot_save(pirrt_batch* B) { return B ? pirrt_snapshot_save(B->G) : PIRRT_EINVAL; }
+
+int pirrt_batch_snapshot_restore(pirrt_batch* B) { return B ? pirrt_snapshot_restore(B->G) : PIRRT_EINVAL; }
+
+const char* pirrt_batch_last_error(const pirrt_batch* B) { return B ? B->G->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -8,16 +8,41 @@ namespace pirrt {
 
 constexpr int kWave = 64;  // CDNA wavefront width
 
-// Per-iteration counters written by the mark / improve kernels.  Kernels add into
-// kCounterSlots copies (workgroup b uses copy b % kCounterSlots) so that the
-// atomics do not pile onto one address; the host sums the copies.
-constexpr int kCounterSlots = 256;
+// Parent value that marks a Replan root inside the library (callers see -1).
+constexpr int32_t kRootMark = -2;
+
+// Per-iteration counters of one problem, written by the mark / improve kernels.
+// Each problem has kCounterSlots copies (workgroup b adds into copy
+// b % kCounterSlots) so that the atomics do not pile onto one address; the finish
+// kernel sums and clears them.
+constexpr int kCounterSlots = 64;
 struct IterCounters {
   int32_t changed;           // parents switched by Improve
   int32_t nP;                // |promising set|
   int32_t nD;                // |Improve domain|
   int32_t pad;
   unsigned long long edges;  // sum of the degrees over the Improve domain
+};
+
+// Replan state of one problem (a graph, or one graph of a batch) on the device.
+struct ProblemState {
+  int32_t root;        // slot of x_init
+  int32_t goal;        // slot of x_goal
+  float thr;           // promising threshold G of the current iteration (-inf: idle)
+  int32_t active;      // still iterating
+  int32_t needs_eval;  // Evaluate after the current Improve
+  int32_t iterations;  // Improve passes so far
+  int32_t status;      // 0 running / converged, 1 iteration cap reached
+  int32_t cap;         // iteration cap
+  unsigned long long edges, sum_P, sum_D, changed_total;
+};
+
+// Device-side loop control shared by the kernels of one Replan.
+struct LoopCtl {
+  uint32_t epoch;       // stamp of the current promising-set / domain marks
+  uint32_t eval_epoch;  // stamp of the current Evaluate
+  int32_t any_active;   // some problem runs this iteration (set by the thresholds)
+  int32_t any_eval;     // some problem needs an Evaluate after this iteration
 };
 
 // Bookkeeping of one Evaluate (breadth-first walk of the policy tree).

@@ -1,0 +1,131 @@
+// Device side of the Replan loop (Alg. 2) for one or many problems: per-problem
+// thresholds, the per-iteration bookkeeping of the convergence test, and the root
+// marks.  The loop itself never waits on the host: each iteration is
+//   thresholds -> mark -> improve -> finish -> evaluate
+// and a problem whose Improve switched no parent stops (its threshold becomes
+// -inf, so the later kernels skip it), exactly when the serial loop would break.
+#include "internal.h"
+
+namespace pirrt {
+
+namespace {
+
+__device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ? 1u : e + 1; }
+
+// Marks the roots, clears the counters and takes fresh epochs.
+__global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, int32_t* __restrict__ parent,
+                              float* __restrict__ pcost, IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (int64_t)P * kCounterSlots) {
+    IterCounters& c = ctr[t];
+    c.changed = 0;
+    c.nP = 0;
+    c.nD = 0;
+    c.edges = 0ull;
+  }
+  if (t < P) {
+    const int32_t r = ps[t].root;
+    parent[r] = kRootMark;
+    pcost[r] = 0.0f;
+  }
+  if (t == 0) {
+    ctl->epoch = next_epoch(ctl->epoch);
+    ctl->eval_epoch = next_epoch(ctl->eval_epoch);
+    ctl->any_active = 1;
+    ctl->any_eval = 1;
+  }
+}
+
+// G of every problem for this iteration (Alg. 2's promising test against
+// g(x_goal)); -inf for a problem that has stopped.
+__global__ void k_thresholds(int32_t P, ProblemState* __restrict__ ps, const float* __restrict__ g, int prune,
+                             LoopCtl* __restrict__ ctl) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) ctl->any_eval = 0;
+  if (i >= P) return;
+  ProblemState& s = ps[i];
+  s.thr = s.active ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
+}
+
+// One workgroup of kCounterSlots threads per problem: sums and clears the counter
+// copies, then applies the convergence test and the iteration cap.
+__global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemState* __restrict__ ps,
+                                                          IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl) {
+  const int32_t i = blockIdx.x;
+  const int t = threadIdx.x;
+  IterCounters& c = ctr[(int64_t)i * kCounterSlots + t];
+  unsigned long long ch = (unsigned)c.changed, np = (unsigned)c.nP, nd = (unsigned)c.nD, ed = c.edges;
+  c.changed = 0;
+  c.nP = 0;
+  c.nD = 0;
+  c.edges = 0ull;
+#pragma unroll
+  for (int off = kCounterSlots / 2; off > 0; off >>= 1) {
+    ch += __shfl_xor(ch, off, kCounterSlots);
+    np += __shfl_xor(np, off, kCounterSlots);
+    nd += __shfl_xor(nd, off, kCounterSlots);
+    ed += __shfl_xor(ed, off, kCounterSlots);
+  }
+  if (t == 0) {
+    ProblemState& s = ps[i];
+    if (s.active) {
+      s.iterations += 1;
+      s.edges += ed;
+      s.sum_P += np;
+      s.sum_D += nd;
+      s.changed_total += ch;
+      if (ch == 0) {  // no parent switched: fixed point (dJ = 0)
+        s.active = 0;
+        s.needs_eval = 0;
+      } else {
+        s.needs_eval = 1;
+        if (s.iterations >= s.cap) {
+          s.active = 0;
+          s.status = 1;
+        }
+        atomicOr(&ctl->any_eval, 1);
+      }
+    } else {
+      s.needs_eval = 0;
+    }
+  }
+  if (i == 0 && t == 0) ctl->epoch = next_epoch(ctl->epoch);
+}
+
+// Runs after the evaluate of an iteration: a new evaluate epoch, and whether any
+// problem still iterates.
+__global__ void k_after_eval(int32_t P, const ProblemState* __restrict__ ps, LoopCtl* __restrict__ ctl) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < P; i += blockDim.x)
+    if (ps[i].active) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ctl->any_active = any;
+    ctl->eval_epoch = next_epoch(ctl->eval_epoch);
+  }
+}
+
+}  // namespace
+
+void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
+                        LoopCtl* ctl, hipStream_t s) {
+  const int64_t t = (int64_t)P * kCounterSlots;
+  hipLaunchKernelGGL(k_replan_init, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, P, ps, parent, pcost, ctr,
+                     ctl);
+}
+
+void launch_thresholds(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_thresholds, dim3((P + 255) / 256), dim3(256), 0, s, P, ps, g, prune, ctl);
+}
+
+void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(P), dim3(kCounterSlots), 0, s, P, ps, ctr, ctl);
+}
+
+void launch_after_eval(int32_t P, const ProblemState* ps, LoopCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(256), 0, s, P, ps, ctl);
+}
+
+}  // namespace pirrt

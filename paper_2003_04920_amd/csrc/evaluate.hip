@@ -43,14 +43,13 @@ __device__ __forceinline__ int32_t load_counter(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root, int32_t* __restrict__ parent,
-                                                       float* __restrict__ pcost, float* __restrict__ g,
+__global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root, const ProblemState* __restrict__ ps,
+                                                       const int32_t* __restrict__ parent, float* __restrict__ g,
                                                        int32_t* __restrict__ child_cnt) {
+  if (!ps->needs_eval) return;
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   if (v == root) {
-    parent[v] = -1;
-    pcost[v] = 0.0f;
     g[v] = 0.0f;
     return;
   }
@@ -59,9 +58,11 @@ __global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root,
   if (p >= 0) atomicAdd(&child_cnt[p], 1);
 }
 
-__global__ void __launch_bounds__(kThreads) k_eval_fill(int32_t n, int32_t root, const int32_t* __restrict__ parent,
+__global__ void __launch_bounds__(kThreads) k_eval_fill(int32_t n, int32_t root, const ProblemState* __restrict__ ps,
+                                                       const int32_t* __restrict__ parent,
                                                        const int32_t* __restrict__ child_ptr,
                                                        int32_t* __restrict__ child_cnt, int32_t* __restrict__ child) {
+  if (!ps->needs_eval) return;
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || v == root) return;
   int32_t p = parent[v];
@@ -104,9 +105,11 @@ struct Bfs {
   int32_t* fr1;
   int32_t* lvl;  // lvl[k] = size of level k
   EvalInfo* info;
+  const ProblemState* ps;  // the walk runs only when ps->needs_eval
 };
 
 __global__ void __launch_bounds__(kWgThreads) k_bfs_head(int32_t root, int32_t limit, Bfs B) {
+  if (!B.ps->needs_eval) return;
   if (threadIdx.x == 0) {
     B.fr0[0] = root;
     B.lvl[0] = 1;
@@ -139,6 +142,7 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_head(int32_t root, int32_t l
 // Level head_end + j.  lvl[k+1] was cleared by the launch of level k-1; this
 // launch clears lvl[k+2] for the next one, also when its own level is empty.
 __global__ void __launch_bounds__(kThreads) k_bfs_level(int32_t j, int32_t tail_limit, Bfs B) {
+  if (!B.ps->needs_eval) return;
   const int32_t k = B.info->head_end + j;
   const int32_t size = B.lvl[k];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -156,8 +160,8 @@ __global__ void __launch_bounds__(kThreads) k_bfs_level(int32_t j, int32_t tail_
   }
 }
 
-__global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tail_limit, Bfs B,
-                                                        IterCounters* __restrict__ ctr) {
+__global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tail_limit, Bfs B) {
+  if (!B.ps->needs_eval) return;
   int k = B.info->head_end + j0;
   int levels = 0, big_end = 0;
   for (;;) {
@@ -178,14 +182,6 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
   if (threadIdx.x == 0) {
     if (levels > B.info->levels) B.info->levels = levels;
     if (big_end > B.info->big_end) B.info->big_end = big_end;
-  }
-  if (threadIdx.x < kCounterSlots) {
-    // fresh counters for the promising-set / Improve pass that follows
-    IterCounters& c = ctr[threadIdx.x];
-    c.changed = 0;
-    c.nP = 0;
-    c.nD = 0;
-    c.edges = 0ull;
   }
 }
 
@@ -226,27 +222,22 @@ __device__ __forceinline__ void store_word(unsigned long long* p, unsigned long 
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool kCountHops, bool kCoherent>
-__global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t hi, int32_t n, int32_t root,
-                                                           uint32_t epoch,
+template <bool kCountHops, bool kCoherent, bool kBatched>
+__global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t hi, int32_t n,
+                                                           const int32_t* __restrict__ prob,
+                                                           const ProblemState* __restrict__ ps,
+                                                           const LoopCtl* __restrict__ ctl,
                                                            const int32_t* __restrict__ parent,
                                                            const float* __restrict__ pcost, float* __restrict__ g,
                                                            unsigned long long* __restrict__ word,
-                                                           IterCounters* __restrict__ ctr,
                                                            unsigned long long* __restrict__ hops) {
   __shared__ int32_t ring_v[kRing][kWalkThreads];
   __shared__ float ring_c[kRing][kWalkThreads];
+  if (ctl->any_eval == 0) return;  // no problem changed in this iteration
   const int64_t v = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (lo == 0 && blockIdx.x == 0 && threadIdx.x < kCounterSlots) {
-    // fresh counters for the promising-set / Improve pass that follows
-    IterCounters& c = ctr[threadIdx.x];
-    c.changed = 0;
-    c.nP = 0;
-    c.nD = 0;
-    c.edges = 0ull;
-  }
   if (v >= hi) return;
-  const unsigned long long tag = (unsigned long long)epoch << 32;
+  if (!ps[kBatched ? prob[v] : 0].needs_eval) return;
+  const unsigned long long tag = (unsigned long long)ctl->eval_epoch << 32;
   unsigned long long walked = 0;
   for (;;) {
     int32_t u = (int32_t)v;
@@ -261,7 +252,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
         top = (uint32_t)w;
         break;
       }
-      if (u == root) {
+      if (p == kRootMark) {  // a root: g = 0
         top = 0u;
         store_word<kCoherent>(&word[u], tag);
         g[u] = 0.0f;
@@ -292,22 +283,24 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
 
 }  // namespace
 
-void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
-                      unsigned long long* word, IterCounters* ctr, unsigned long long* hops, int parts,
-                      bool coherent, hipStream_t s) {
-  if (parts < 1) parts = 1;
-  const int64_t per = ((int64_t)n + parts - 1) / parts;
+void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
+  const int parts = a.parts < 1 ? 1 : a.parts;
+  const int64_t per = ((int64_t)a.n + parts - 1) / parts;
   for (int k = 0; k < parts; ++k) {
-    const int32_t lo = (int32_t)(k * per < n ? k * per : n), hi = (int32_t)((k + 1) * per < n ? (k + 1) * per : n);
+    const int32_t lo = (int32_t)(k * per < a.n ? k * per : a.n);
+    const int32_t hi = (int32_t)((k + 1) * per < a.n ? (k + 1) * per : a.n);
     if (hi <= lo && k > 0) break;
     const dim3 grid(blocks_for(hi - lo, kWalkThreads));
-#define PIRRT_WALK(H, C) \
-  hipLaunchKernelGGL((k_eval_walk<H, C>), grid, dim3(kWalkThreads), 0, s, lo, hi, n, root, epoch, parent, pcost, g, \
-                     word, ctr, hops)
-    if (hops) {
-      if (coherent) PIRRT_WALK(true, true); else PIRRT_WALK(true, false);
+#define PIRRT_WALK(H, C, B)                                                                                \
+  hipLaunchKernelGGL((k_eval_walk<H, C, B>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, a.ctl, \
+                     a.parent, a.pcost, a.g, a.word, a.hops)
+    const bool b = a.prob != nullptr;
+    if (a.hops) {
+      if (a.coherent) { if (b) PIRRT_WALK(true, true, true); else PIRRT_WALK(true, true, false); }
+      else { if (b) PIRRT_WALK(true, false, true); else PIRRT_WALK(true, false, false); }
     } else {
-      if (coherent) PIRRT_WALK(false, true); else PIRRT_WALK(false, false);
+      if (a.coherent) { if (b) PIRRT_WALK(false, true, true); else PIRRT_WALK(false, true, false); }
+      else { if (b) PIRRT_WALK(false, false, true); else PIRRT_WALK(false, false, false); }
     }
 #undef PIRRT_WALK
   }
@@ -315,16 +308,16 @@ void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* pa
 
 void launch_evaluate(const EvalArgs& a, hipStream_t s) {
   const int32_t n = a.n;
-  hipLaunchKernelGGL(k_eval_prep, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.parent, a.pcost, a.g,
+  hipLaunchKernelGGL(k_eval_prep, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.ps, a.parent, a.g,
                      a.child_cnt);
   scan_i32_to_i32(a.child_cnt, n, a.child_ptr, a.scan_scratch, s);
-  hipLaunchKernelGGL(k_eval_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.parent, a.child_ptr,
+  hipLaunchKernelGGL(k_eval_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.ps, a.parent, a.child_ptr,
                      a.child_cnt, a.child);
-  Bfs B{a.child_ptr, a.child, a.pcost, a.g, a.fr0, a.fr1, a.lvl, a.info};
+  Bfs B{a.child_ptr, a.child, a.pcost, a.g, a.fr0, a.fr1, a.lvl, a.info, a.ps};
   hipLaunchKernelGGL(k_bfs_head, dim3(1), dim3(kWgThreads), 0, s, a.root, (int32_t)kWgThreads, B);
   for (int32_t j = 0; j < a.mid_launches; ++j)
     hipLaunchKernelGGL(k_bfs_level, dim3(a.level_blocks), dim3(kThreads), 0, s, j, (int32_t)kWgThreads, B);
-  hipLaunchKernelGGL(k_bfs_tail, dim3(1), dim3(kWgThreads), 0, s, a.mid_launches, (int32_t)kWgThreads, B, a.ctr);
+  hipLaunchKernelGGL(k_bfs_tail, dim3(1), dim3(kWgThreads), 0, s, a.mid_launches, (int32_t)kWgThreads, B);
 }
 
 }  // namespace pirrt

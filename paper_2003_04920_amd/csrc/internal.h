@@ -11,8 +11,10 @@ void scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, void* scratch, 
 void scan_i32_to_i32(const int32_t* in, int64_t n, int32_t* out, void* scratch, hipStream_t s);
 
 // ---- store.hip ----
-void launch_validate_rows(int32_t n_new, int64_t n_old, const int64_t* rp, const int32_t* col, const float* cost,
-                          int64_t nnz, int* err, hipStream_t s);
+// Neighbour ids of row i must lie in [lo_bound, n_old + i).
+void launch_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound, const int64_t* rp, const int32_t* col,
+                          const float* cost, int64_t nnz, int* err, hipStream_t s);
+void launch_offset_ids(int64_t m, int32_t offset, int32_t* ids, hipStream_t s);
 void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
                     const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
                     int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
@@ -20,10 +22,11 @@ void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s);
 // bcol: neighbour ids as given (tie-break keys); bslot: the same in storage slots.
-void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
-                         const int32_t* bcol, const int32_t* bslot, const float* bcost, const int64_t* rp,
-                         const int32_t* col, float* g, int32_t* parent, float* pcost, int32_t* pending,
-                         int32_t* next, int32_t* ncount, hipStream_t s);
+// insert_root: the new vertex that gets g = 0 (x_init), or -1.
+void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, int32_t insert_root,
+                         const int64_t* brp, const int32_t* bcol, const int32_t* bslot, const float* bcost,
+                         const int64_t* rp, const int32_t* col, float* g, int32_t* parent, float* pcost,
+                         int32_t* pending, int32_t* next, int32_t* ncount, hipStream_t s);
 
 // ---- reorder.hip ----
 struct PermuteArgs {
@@ -50,22 +53,31 @@ struct PermuteArgs {
 };
 void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
 void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s);
-void launch_bfs_init(int32_t root, int32_t* order, int32_t* visited, int32_t* count, hipStream_t s);
-void launch_graph_bfs_level(int32_t lo, int32_t hi, int32_t* order, const int64_t* rp, const int32_t* col,
-                            int32_t* visited, int32_t* count, hipStream_t s);
-void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, int32_t* count, hipStream_t s);
+void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStream_t s);
+void launch_unmark_roots(int32_t m, const int32_t* ids, const int32_t* slot_of, int32_t* parent, hipStream_t s);
+void launch_bfs_init(int32_t P, const int32_t* roots, const int64_t* base, int32_t* order, int32_t* visited,
+                     int32_t* pcnt, int32_t* frontier, int32_t* fcount, hipStream_t s);
+void launch_graph_bfs_level(int32_t fsize, const int32_t* frontier, int32_t* next, int32_t* ncount, int32_t* order,
+                            const int32_t* prob, int32_t* pcnt, const int64_t* rp, const int32_t* col,
+                            int32_t* visited, hipStream_t s);
+void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,
+                             hipStream_t s);
 void launch_permute(const PermuteArgs& a, hipStream_t s);
 void launch_gather_by_slot(int32_t n, const int32_t* ext_of, const float* src_ext, float* dst_slot, hipStream_t s);
-void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const float* g,
-                          const int32_t* parent, const float* pcost, float* g_ext, int32_t* parent_ext,
-                          float* pcost_ext, hipStream_t s);
-void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const float* g_ext, const int32_t* parent_ext,
-                            const float* pcost_ext, float* g, int32_t* parent, float* pcost, hipStream_t s);
+// prob/base (nullable): parents are reported relative to the first id of the
+// vertex's problem.
+void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const int32_t* prob,
+                          const int64_t* base, const float* g, const int32_t* parent, const float* pcost,
+                          float* g_ext, int32_t* parent_ext, float* pcost_ext, hipStream_t s);
+void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const int32_t* prob, const int64_t* base,
+                            const float* g_ext, const int32_t* parent_ext, const float* pcost_ext, float* g,
+                            int32_t* parent, float* pcost, hipStream_t s);
 
 // ---- evaluate.hip ----
 struct EvalArgs {
   int32_t n;
   int32_t root;
+  const ProblemState* ps;  // one problem; the walk runs only when ps->needs_eval
   int32_t* parent;
   float* pcost;
   float* g;
@@ -76,41 +88,54 @@ struct EvalArgs {
   int32_t* fr1;         // n
   int32_t* lvl;         // level sizes, n + kMaxMidLaunches + 4
   EvalInfo* info;
-  IterCounters* ctr;    // kCounterSlots copies, cleared at the end of the walk
   void* scan_scratch;
   int32_t mid_launches; // wide level launches between head and tail
   int32_t level_blocks; // grid of each wide level launch
 };
 constexpr int32_t kMaxMidLaunches = 1024;
 void launch_evaluate(const EvalArgs& a, hipStream_t s);
-// word: n 64-bit {epoch, g bits} stamps; epochs of earlier calls must be smaller.
-// hops (nullable): if given, receives the total number of parent links walked.
-// The slots are walked in `parts` launches over consecutive ranges (later ranges
-// find the earlier ones' stamps); coherent selects device-scope stamp accesses.
-void launch_eval_walk(int32_t n, int32_t root, uint32_t epoch, const int32_t* parent, const float* pcost, float* g,
-                      unsigned long long* word, IterCounters* ctr, unsigned long long* hops, int parts,
-                      bool coherent, hipStream_t s);
+// Walk evaluation of every problem with needs_eval (see evaluate.hip).
+struct WalkArgs {
+  int32_t n;
+  const int32_t* prob;     // problem of each slot, or NULL for a single problem
+  const ProblemState* ps;
+  const LoopCtl* ctl;      // eval_epoch, any_eval
+  const int32_t* parent;   // roots carry kRootMark
+  const float* pcost;
+  float* g;
+  unsigned long long* word;  // n {epoch, g bits} stamps
+  unsigned long long* hops;  // nullable: total parent links walked
+  int parts;               // launches over consecutive slot ranges
+  bool coherent;           // device-scope stamp accesses
+};
+void launch_eval_walk(const WalkArgs& a, hipStream_t s);
+
+// ---- driver.hip ----
+void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
+                        LoopCtl* ctl, hipStream_t s);
+void launch_thresholds(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s);
+void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s);
+void launch_after_eval(int32_t P, const ProblemState* ps, LoopCtl* ctl, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
   int32_t n;
-  int32_t root;
-  int32_t goal;
-  int32_t prune;
+  int64_t nnz;               // adjacency entries (selects 32-bit offsets when they fit)
+  const int32_t* prob;       // problem of each slot, or NULL for a single problem
+  const ProblemState* ps;    // thresholds and roots
+  const LoopCtl* ctl;        // epoch, any_active
   const float* g;
-  const float* h;  // nullable
+  const float* h;            // nullable
   const int64_t* rp;
   const int32_t* col;
   const float* cst;
   uint32_t* stamp;
-  uint32_t epoch;
-  const int32_t* ext_of;  // caller id of each slot (tie-break key)
+  const int32_t* ext_of;     // caller id of each slot (tie-break key)
   int32_t* parent;
   float* pcost;
-  IterCounters* ctr;  // kCounterSlots copies
-  int32_t max_blocks;  // persistent grid: about one residency of 256-thread workgroups
+  IterCounters* ctr;         // kCounterSlots copies per problem
 };
-constexpr int kRowVariants = 6;
+constexpr int kRowVariants = 4;
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);
 void launch_improve(const StepArgs& a, int variant, hipStream_t s);
 

@@ -37,6 +37,22 @@ __global__ void __launch_bounds__(kThreads) k_identity_ids(int64_t lo, int64_t h
   slot_of[s] = (int32_t)s;
 }
 
+__global__ void __launch_bounds__(kThreads) k_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* __restrict__ a) {
+  int64_t s = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < hi) a[s] = value;
+}
+
+// parent[slot_of[id]] = -1 for the given caller ids whose parent carries the root
+// mark (the roots of an earlier Replan).
+__global__ void __launch_bounds__(kThreads) k_unmark_roots(int32_t m, const int32_t* __restrict__ ids,
+                                                          const int32_t* __restrict__ slot_of,
+                                                          int32_t* __restrict__ parent) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t s = slot_of[ids[i]];
+  if (parent[s] == kRootMark) parent[s] = -1;
+}
+
 __global__ void __launch_bounds__(kThreads) k_translate(int64_t m, const int32_t* __restrict__ ids,
                                                        const int32_t* __restrict__ slot_of,
                                                        int32_t* __restrict__ out) {
@@ -44,37 +60,52 @@ __global__ void __launch_bounds__(kThreads) k_translate(int64_t m, const int32_t
   if (j < m) out[j] = slot_of[ids[j]];
 }
 
-__global__ void k_bfs_init(int32_t root, int32_t* __restrict__ order, int32_t* __restrict__ visited,
-                           int32_t* __restrict__ count) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    order[0] = root;
-    visited[root] = 1;
-    *count = 1;
-  }
+// Sources of the renumbering BFS: problem i starts at slot roots[i] and fills
+// order[base_i ..] of its own slot range (problems occupy contiguous ranges).
+__global__ void k_bfs_init(int32_t P, const int32_t* __restrict__ roots, const int64_t* __restrict__ base,
+                           int32_t* __restrict__ order, int32_t* __restrict__ visited, int32_t* __restrict__ pcnt,
+                           int32_t* __restrict__ frontier, int32_t* __restrict__ fcount) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *fcount = P;
+  if (i >= P) return;
+  const int32_t r = roots[i];
+  order[base[i]] = r;
+  visited[r] = 1;
+  pcnt[i] = (int32_t)base[i] + 1;
+  frontier[i] = r;
 }
 
-// One breadth-first level over the graph: order[lo, hi) is the frontier; newly
-// reached vertices are appended to order[] (the queue is the new storage order).
-__global__ void __launch_bounds__(kThreads) k_graph_bfs_level(int32_t lo, int32_t hi, int32_t* __restrict__ order,
+// One breadth-first level over the graph: each newly reached vertex takes the next
+// position of its problem's range in order[] (the queue order is the new storage
+// order) and joins the next frontier.
+__global__ void __launch_bounds__(kThreads) k_graph_bfs_level(int32_t fsize, const int32_t* __restrict__ frontier,
+                                                             int32_t* __restrict__ next, int32_t* __restrict__ ncount,
+                                                             int32_t* __restrict__ order,
+                                                             const int32_t* __restrict__ prob,
+                                                             int32_t* __restrict__ pcnt,
                                                              const int64_t* __restrict__ rp,
                                                              const int32_t* __restrict__ col,
-                                                             int32_t* __restrict__ visited,
-                                                             int32_t* __restrict__ count) {
-  int64_t t = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= hi) return;
-  const int32_t u = order[t];
+                                                             int32_t* __restrict__ visited) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= fsize) return;
+  const int32_t u = frontier[t];
+  int32_t* cnt = &pcnt[prob ? prob[u] : 0];
   for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
     const int32_t w = col[j];
-    if (visited[w] == 0 && atomicExch(&visited[w], 1) == 0) order[atomicAdd(count, 1)] = w;
+    if (visited[w] == 0 && atomicExch(&visited[w], 1) == 0) {
+      order[atomicAdd(cnt, 1)] = w;
+      next[atomicAdd(ncount, 1)] = w;
+    }
   }
 }
 
+// Vertices the BFS did not reach follow in their problem's range.
 __global__ void __launch_bounds__(kThreads) k_append_unvisited(int32_t n, const int32_t* __restrict__ visited,
-                                                              int32_t* __restrict__ order, int32_t* __restrict__ count) {
+                                                              int32_t* __restrict__ order,
+                                                              const int32_t* __restrict__ prob,
+                                                              int32_t* __restrict__ pcnt) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int take = (s < n && visited[s] == 0) ? 1 : 0;
-  const int slot = wave_reserve(count, take);
-  if (take) order[slot] = (int32_t)s;
+  if (s < n && visited[s] == 0) order[atomicAdd(&pcnt[prob ? prob[s] : 0], 1)] = (int32_t)s;
 }
 
 __global__ void __launch_bounds__(kThreads) k_invert(int32_t n, const int32_t* __restrict__ order,
@@ -120,7 +151,7 @@ __global__ void __launch_bounds__(kThreads) k_permute_vertices(int32_t n, const 
   const int32_t o = order[k];
   g2[k] = g[o];
   const int32_t p = parent[o];
-  parent2[k] = p >= 0 ? newslot[p] : -1;
+  parent2[k] = p >= 0 ? newslot[p] : p;  // -1 and the root mark stay
   pcost2[k] = pcost[o];
   const int32_t e = ext_of[o];
   ext2[k] = e;
@@ -136,6 +167,8 @@ __global__ void __launch_bounds__(kThreads) k_gather_by_slot(int32_t n, const in
 
 __global__ void __launch_bounds__(kThreads) k_policy_to_ext(int32_t n, const int32_t* __restrict__ slot_of,
                                                            const int32_t* __restrict__ ext_of,
+                                                           const int32_t* __restrict__ prob,
+                                                           const int64_t* __restrict__ base,
                                                            const float* __restrict__ g,
                                                            const int32_t* __restrict__ parent,
                                                            const float* __restrict__ pcost, float* __restrict__ g_ext,
@@ -147,12 +180,14 @@ __global__ void __launch_bounds__(kThreads) k_policy_to_ext(int32_t n, const int
   if (g_ext) g_ext[e] = g[s];
   if (parent_ext) {
     const int32_t p = parent[s];
-    parent_ext[e] = p >= 0 ? ext_of[p] : -1;
+    parent_ext[e] = p >= 0 ? (int32_t)(ext_of[p] - (prob ? base[prob[s]] : 0)) : -1;
   }
   if (pcost_ext) pcost_ext[e] = pcost[s];
 }
 
 __global__ void __launch_bounds__(kThreads) k_policy_from_ext(int32_t n, const int32_t* __restrict__ slot_of,
+                                                             const int32_t* __restrict__ prob,
+                                                             const int64_t* __restrict__ base,
                                                              const float* __restrict__ g_ext,
                                                              const int32_t* __restrict__ parent_ext,
                                                              const float* __restrict__ pcost_ext,
@@ -163,7 +198,7 @@ __global__ void __launch_bounds__(kThreads) k_policy_from_ext(int32_t n, const i
   const int32_t s = slot_of[e];
   g[s] = g_ext[e];
   const int32_t p = parent_ext[e];
-  parent[s] = p >= 0 ? slot_of[p] : -1;
+  parent[s] = p >= 0 ? slot_of[p + (prob ? base[prob[s]] : 0)] : -1;
   pcost[s] = pcost_ext[e];
 }
 
@@ -178,19 +213,31 @@ void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int
   if (m > 0) hipLaunchKernelGGL(k_translate, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, ids, slot_of, out);
 }
 
-void launch_bfs_init(int32_t root, int32_t* order, int32_t* visited, int32_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, root, order, visited, count);
+void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStream_t s) {
+  if (hi > lo) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, value, a);
 }
 
-void launch_graph_bfs_level(int32_t lo, int32_t hi, int32_t* order, const int64_t* rp, const int32_t* col,
-                            int32_t* visited, int32_t* count, hipStream_t s) {
-  if (hi > lo)
-    hipLaunchKernelGGL(k_graph_bfs_level, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, order, rp, col,
-                       visited, count);
+void launch_unmark_roots(int32_t m, const int32_t* ids, const int32_t* slot_of, int32_t* parent, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_unmark_roots, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, ids, slot_of, parent);
 }
 
-void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, int32_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_append_unvisited, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, visited, order, count);
+void launch_bfs_init(int32_t P, const int32_t* roots, const int64_t* base, int32_t* order, int32_t* visited,
+                     int32_t* pcnt, int32_t* frontier, int32_t* fcount, hipStream_t s) {
+  hipLaunchKernelGGL(k_bfs_init, dim3(blocks_for(P)), dim3(kThreads), 0, s, P, roots, base, order, visited, pcnt,
+                     frontier, fcount);
+}
+
+void launch_graph_bfs_level(int32_t fsize, const int32_t* frontier, int32_t* next, int32_t* ncount, int32_t* order,
+                            const int32_t* prob, int32_t* pcnt, const int64_t* rp, const int32_t* col,
+                            int32_t* visited, hipStream_t s) {
+  if (fsize > 0)
+    hipLaunchKernelGGL(k_graph_bfs_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, next,
+                       ncount, order, prob, pcnt, rp, col, visited);
+}
+
+void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_append_unvisited, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, visited, order, prob, pcnt);
 }
 
 void launch_permute(const PermuteArgs& a, hipStream_t s) {
@@ -206,17 +253,18 @@ void launch_gather_by_slot(int32_t n, const int32_t* ext_of, const float* src_ex
   hipLaunchKernelGGL(k_gather_by_slot, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, ext_of, src_ext, dst_slot);
 }
 
-void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const float* g,
-                          const int32_t* parent, const float* pcost, float* g_ext, int32_t* parent_ext,
-                          float* pcost_ext, hipStream_t s) {
-  hipLaunchKernelGGL(k_policy_to_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, ext_of, g, parent,
-                     pcost, g_ext, parent_ext, pcost_ext);
+void launch_policy_to_ext(int32_t n, const int32_t* slot_of, const int32_t* ext_of, const int32_t* prob,
+                          const int64_t* base, const float* g, const int32_t* parent, const float* pcost,
+                          float* g_ext, int32_t* parent_ext, float* pcost_ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_policy_to_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, ext_of, prob, base, g,
+                     parent, pcost, g_ext, parent_ext, pcost_ext);
 }
 
-void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const float* g_ext, const int32_t* parent_ext,
-                            const float* pcost_ext, float* g, int32_t* parent, float* pcost, hipStream_t s) {
-  hipLaunchKernelGGL(k_policy_from_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, g_ext, parent_ext,
-                     pcost_ext, g, parent, pcost);
+void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const int32_t* prob, const int64_t* base,
+                            const float* g_ext, const int32_t* parent_ext, const float* pcost_ext, float* g,
+                            int32_t* parent, float* pcost, hipStream_t s) {
+  hipLaunchKernelGGL(k_policy_from_ext, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, slot_of, prob, base, g_ext,
+                     parent_ext, pcost_ext, g, parent, pcost);
 }
 
 }  // namespace pirrt

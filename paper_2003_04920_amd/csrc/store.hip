@@ -27,7 +27,7 @@ inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
 // Error bits raised by validation.
 enum { kErrRowPtr = 1, kErrCol = 2, kErrCost = 4 };
 
-__global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64_t n_old,
+__global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound,
                                                            const int64_t* __restrict__ rp,
                                                            const int32_t* __restrict__ col,
                                                            const float* __restrict__ cost, int64_t nnz,
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64
   for (int64_t j = a; j < b; ++j) {
     int32_t c = col[j];
     uint32_t w = __float_as_uint(cost[j]);
-    if (c < 0 || (int64_t)c >= self) bad |= kErrCol;
+    if ((int64_t)c < lo_bound || (int64_t)c >= self) bad |= kErrCol;
     // finite, >= 0 and sign bit clear (rejects NaN, inf, negatives and -0.0)
     if ((w >> 31) != 0 || (w & 0x7f800000u) == 0x7f800000u) bad |= kErrCost;
   }
@@ -142,7 +142,8 @@ __global__ void __launch_bounds__(kThreads) k_pending(int32_t n_new, int64_t n_o
 // minimum is over (g(u) + c, u, c) with u the caller's id (bcol); g is read at the
 // storage slot (bslot).  New vertices occupy slots equal to their ids.
 __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const int32_t* __restrict__ frontier,
-                                                          int64_t n_old, const int64_t* __restrict__ brp,
+                                                          int64_t n_old, int32_t insert_root,
+                                                          const int64_t* __restrict__ brp,
                                                           const int32_t* __restrict__ bcol,
                                                           const int32_t* __restrict__ bslot,
                                                           const float* __restrict__ bcost,
@@ -156,10 +157,10 @@ __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const 
   const int32_t v = frontier[t];
   const int64_t i = v - n_old;
   const int64_t a = brp[i], b = brp[i + 1];
-  if (v == 0) {
-    g[0] = 0.0f;
-    parent[0] = -1;
-    pcost[0] = 0.0f;
+  if (v == insert_root) {  // x_init of the graph (or of a new problem of a batch)
+    g[v] = 0.0f;
+    parent[v] = -1;
+    pcost[v] = 0.0f;
   } else {
     uint32_t bv = 0xffffffffu, bc = 0xffffffffu;
     int32_t be = 0x7fffffff;
@@ -194,10 +195,10 @@ __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const 
 
 }  // namespace
 
-void launch_validate_rows(int32_t n_new, int64_t n_old, const int64_t* rp, const int32_t* col,
+void launch_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound, const int64_t* rp, const int32_t* col,
                           const float* cost, int64_t nnz, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate_rows, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, rp, col,
-                     cost, nnz, err);
+  hipLaunchKernelGGL(k_validate_rows, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, lo_bound, rp,
+                     col, cost, nnz, err);
 }
 
 void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
@@ -224,12 +225,22 @@ void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
                      frontier, fcount);
 }
 
-void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, const int64_t* brp,
-                         const int32_t* bcol, const int32_t* bslot, const float* bcost, const int64_t* rp,
-                         const int32_t* col, float* g, int32_t* parent, float* pcost, int32_t* pending,
-                         int32_t* next, int32_t* ncount, hipStream_t s) {
-  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, n_old, brp,
-                     bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
+void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, int32_t insert_root,
+                         const int64_t* brp, const int32_t* bcol, const int32_t* bslot, const float* bcost,
+                         const int64_t* rp, const int32_t* col, float* g, int32_t* parent, float* pcost,
+                         int32_t* pending, int32_t* next, int32_t* ncount, hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, n_old,
+                     insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
+}
+
+__global__ void __launch_bounds__(kThreads) k_offset_ids(int64_t m, int32_t offset, int32_t* __restrict__ ids) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) ids[j] += offset;
+}
+
+void launch_offset_ids(int64_t m, int32_t offset, int32_t* ids, hipStream_t s) {
+  if (m > 0 && offset != 0)
+    hipLaunchKernelGGL(k_offset_ids, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, offset, ids);
 }
 
 }  // namespace pirrt
