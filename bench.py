@@ -14,6 +14,9 @@ oracle on this host's cores for one Replan of the same graph.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+IMPROVE_SRC = os.path.join(ROOT, "paper_2003_04920_amd", "csrc", "improve.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_6d_1m_traffic.txt")
+CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
 def log(*a):
@@ -39,6 +45,81 @@ def improve_bytes(edges: int, sum_d: int, n: int, launches: int) -> int:
     return 8 * edges + 24 * sum_d + 8 * n * launches
 
 
+def source_digest() -> str:
+    with open(IMPROVE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_improve launch from the committed counter summary, or None
+    when the summary is missing or was taken on another version of the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("improve_hip_sha256_16") != source_digest():
+        return None
+    try:
+        return int(vals["k_improve_traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _short(name: str) -> str:
+    name = name.replace("pirrt::(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def profile_summary(paths):
+    """Summarises rocprofv3 CSV output: kernel statistics (--kernel-trace --stats)
+    and per-dispatch counters (--pmc FETCH_SIZE, --pmc WRITE_SIZE, in KiB).  The
+    counters are scaled by what they read for the calibration kernel (a 1 GiB
+    elementwise negation: 1 GiB read, 1 GiB written)."""
+    out = []
+    for path in paths:
+        for f in sorted(glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True)):
+            out.append("kernel statistics (%s):" % os.path.basename(f))
+            out.append("  %-60s %7s %12s %12s %7s" % ("kernel", "calls", "total_us", "avg_us", "pct"))
+            with open(f) as fh:
+                for row in list(csv.DictReader(fh))[:16]:
+                    out.append("  %-60s %7s %12.1f %12.2f %7.2f" % (
+                        _short(row["Name"])[:60], row["Calls"], float(row["TotalDurationNs"]) / 1e3,
+                        float(row["AverageNs"]) / 1e3, float(row["Percentage"])))
+    per = {}
+    for path in paths:
+        for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    key = (_short(row["Kernel_Name"]), row["Counter_Name"])
+                    per.setdefault(key, []).append(float(row["Counter_Value"]))
+    if per:
+        out.append("counters, mean KiB per dispatch:")
+        for (k, c), v in sorted(per.items()):
+            out.append("  %-60s %-11s dispatches %5d mean %14.1f" % (k[:60] or "(unnamed)", c, len(v),
+                                                                      sum(v) / len(v)))
+        def mean(pred, counter):
+            v = [x for (k, c), xs in per.items() if c == counter and pred(k) for x in xs]
+            return sum(v) / len(v) if v else None
+        calib = lambda k: "native::neg" in k
+        imp = lambda k: k.startswith("k_improve")
+        cf, cw = mean(calib, "FETCH_SIZE"), mean(calib, "WRITE_SIZE")
+        f_imp, w_imp = mean(imp, "FETCH_SIZE"), mean(imp, "WRITE_SIZE")
+        if cf and cw and f_imp is not None and w_imp is not None:
+            sf, sw = CALIB_BYTES / (cf * 1024), CALIB_BYTES / (cw * 1024)
+            traffic = int(round(f_imp * 1024 * sf + w_imp * 1024 * sw))
+            out.append("calibration: FETCH_SIZE reads %.1f KiB and WRITE_SIZE %.1f KiB for 1 GiB each: "
+                       "scale %.4f (fetch), %.4f (write)" % (cf, cw, sf, sw))
+            out.append("k_improve_fetch_bytes_per_launch: %d" % int(round(f_imp * 1024 * sf)))
+            out.append("k_improve_write_bytes_per_launch: %d" % int(round(w_imp * 1024 * sw)))
+            out.append("k_improve_traffic_bytes_per_launch: %d" % traffic)
+            out.append("improve_hip_sha256_16: %s" % source_digest())
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,8 +130,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 1 GiB device copy (reference for HBM byte counters)")
+                    help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
+    ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
+                    help="summarise rocprofv3 CSV output under DIR(s) and exit")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Replan library runs on a single device and "
               "this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
@@ -114,7 +200,7 @@ def main():
     nbytes = improve_bytes(tst["edges_examined"], tst["sum_D"], n, tst["improve_launches"])
     achieved = nbytes / (tst["ms_improve"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_improve", "launches": tst["improve_launches"],
                 "avg_launch_us": round(1e3 * tst["ms_improve"] / max(1, tst["improve_launches"]), 2),
                 "bytes_per_launch": int(nbytes / max(1, tst["improve_launches"]))}
@@ -159,11 +245,11 @@ def main():
         log("cpu baseline: %s" % json.dumps(cpu))
 
     if args.copy_calibration:
-        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         x.fill_(1.0)
         torch.cuda.synchronize()
-        y.copy_(x)
+        torch.neg(x, out=y)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
 
