@@ -120,6 +120,108 @@ def profile_summary(paths):
     print("\n".join(out))
 
 
+def bench_multi(args):
+    """Batched multi-graph Replan: `args.problems` independent problems (d in
+    {2,3,4,6,8}, n log-uniform in [5k, 200k], 10-40 sphere / box obstacles), each
+    sampled and connected on the device, replanned together by one pirrt_batch
+    call per step, beside the same problems replanned one pirrt_replan call at a
+    time."""
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    specs = [W.multi_problem_spec(i) for i in range(args.problems)]
+    B = P.Batch(stream=stream)
+    rrgs, hs = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp in specs:
+        R = P.Rrg(sp.d, sp.obstacles, stream=stream, point_capacity=sp.n)
+        R.add_points(np.stack([np.full(sp.d, 0.05), np.full(sp.d, 0.95)]))
+        R.sample(sp.sample_seed, 0, 0, sp.n - 2)
+        R.connect_problem(sp.radius, B)
+        hs.append(R.heuristic(1, out=torch.empty(sp.n, dtype=torch.float32, device=dev)))
+        rrgs.append(R)
+        if len(rrgs) % 64 == 0:
+            log("built %d problems (%.1fs)" % (len(rrgs), time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    n, nnz = B.n, B.nnz
+    log("batch: %d problems, %d vertices, %d directed edges, built on the device in %.2fs" %
+        (len(specs), n, nnz, build_s))
+    h = torch.cat(hs)
+    g_out = torch.empty(n, dtype=torch.float32, device=dev)
+    p_out = torch.empty(n, dtype=torch.int32, device=dev)
+    B.snapshot_save()
+    roots = np.zeros(len(specs), np.int32)
+    goals = np.ones(len(specs), np.int32)
+
+    def batch_step():
+        B.snapshot_restore()
+        return B.replan(roots, goals, h, True, g_out=g_out, parent_out=p_out)[2]
+
+    for _ in range(args.warmup):
+        st = batch_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = batch_step()
+    torch.cuda.synchronize()
+    ms_batch = 1e3 * (time.perf_counter() - t0) / max(1, args.steps)
+    edges = sum(x["edges_examined"] for x in st)
+    iters = [x["iterations"] for x in st]
+    log("batched: %.3f ms per Replan of all problems, %.1f GTEPS, iterations max %d mean %.1f" %
+        (ms_batch, edges / ms_batch / 1e6, max(iters), sum(iters) / len(iters)))
+    # the same problems, one graph handle and one pirrt_replan call each
+    graphs = []
+    off = B.offsets
+    for i, (R, sp) in enumerate(zip(rrgs, specs)):
+        G = P.Graph(stream=stream)
+        R.connect(0, sp.radius, G)
+        G.snapshot_save()
+        graphs.append((G, h[off[i]:off[i + 1]], g_out[off[i]:off[i + 1]], p_out[off[i]:off[i + 1]]))
+
+    def seq_step():
+        tot = 0
+        for G, hh, gg, pp in graphs:
+            G.snapshot_restore()
+            tot += G.replan(0, 1, hh, True, g_out=gg, parent_out=pp)[2]["edges_examined"]
+        return tot
+
+    for _ in range(max(1, args.warmup // 2)):
+        seq_edges = seq_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps // 2)
+    for _ in range(reps):
+        seq_edges = seq_step()
+    torch.cuda.synchronize()
+    ms_seq = 1e3 * (time.perf_counter() - t0) / reps
+    assert seq_edges == edges, (seq_edges, edges)
+    log("sequential: %.3f ms for %d pirrt_replan calls" % (ms_seq, len(graphs)))
+    out = {
+        "metric": "Batched multi-graph Replan GTEPS (%d problems, one pirrt_batch_replan per step)" % len(specs),
+        "value": round(edges / ms_batch / 1e6, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d independent RRG problems, d in {2,3,4,6,8}, n log-uniform in [5k, 200k], "
+                               "10-40 sphere/box obstacles, r = (ln n/n)^(1/d); sampled and connected on the "
+                               "device; pruning on, h = Euclidean distance to goal" % len(specs),
+                   "problems": len(specs), "vertices": n, "directed_edges": nnz,
+                   "edges_examined_per_step": edges, "iterations_max": max(iters),
+                   "parallelism": "single GPU"},
+        "sequential_ms": round(ms_seq, 3), "speedup_vs_sequential": round(ms_seq / ms_batch, 2),
+        "sequential_gteps": round(edges / ms_seq / 1e6, 3),
+        "device_build_s": round(build_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +235,9 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
+    ap.add_argument("--workload", choices=["plain6d", "multi"], default="plain6d",
+                    help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan")
+    ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary)
@@ -141,6 +246,9 @@ def main():
         print("bench.py measures one GPU only: the Replan library runs on a single device and "
               "this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
         sys.exit(2)
+    if args.workload == "multi":
+        bench_multi(args)
+        return
 
     import numpy as np
     import torch

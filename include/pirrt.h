@@ -226,6 +226,81 @@ int pirrt_batch_snapshot_restore(pirrt_batch* b);
 
 const char* pirrt_batch_last_error(const pirrt_batch* b);
 
+/*
+ * Exploration support: growing the random geometric graph on the device (Sec. III,
+ * Extend: sample a state, connect it to the earlier vertices within the connection
+ * radius by collision-free straight segments, cache each edge's cost; Alg. 3 does
+ * this for batches of S samples).  A pirrt_rrg handle holds a scene (the unit cube
+ * [0,1]^d with sphere and axis-aligned box obstacles, all closed sets) and a list of
+ * points in binary64, row-major, d per point, kept in device memory.  Its rows go
+ * into a pirrt_graph or a pirrt_batch without leaving the device.
+ *
+ * Definitions (bit-exact contract):
+ *   - Sampling: candidate k of stream s under seed q has coordinate i equal to
+ *     (w_i >> 8) * 2^-24, where w_0..w_3 = Philox4x32-10(counter {k mod 2^32,
+ *     k >> 32, s, 0}, key {q mod 2^32, q >> 32}) and w_4..w_7 the same with counter
+ *     word 3 = 1 (Salmon et al., SC'11).  A candidate inside or on an obstacle is
+ *     rejected; free candidates are appended in order of k.
+ *   - Obstacles: sphere = sum over axes (x_k - c_k)^2 <= R^2; box = every
+ *     |x_k - c_k| <= s_k.
+ *   - Edge u-v (u < v): d2 = sum over axes in order of (x_u - x_v)^2 in binary64 with
+ *     0 < d2 <= r*r, and the closed segment from x_u to x_v meets no obstacle (sphere:
+ *     the segment point closest to the centre, parameter ((c - x_u).e)/(e.e) clamped
+ *     to [0, 1] with e = x_v - x_u, lies within R; box: slab test).  Cost = binary32
+ *     rounding of sqrt(d2).  Rows list u ascending.
+ *   - Heuristic: binary32 rounding of the binary64 distance to the goal point.
+ */
+typedef struct pirrt_rrg pirrt_rrg;
+
+typedef struct {
+  int32_t d;              /* dimension, 1..8 */
+  int32_t n_obstacles;    /* >= 0 */
+  const int32_t* kind;    /* host int32[n_obstacles]: 0 = sphere, 1 = box; copied */
+  const double* centre;   /* host float64[n_obstacles * d]; copied */
+  const double* size;     /* host float64[n_obstacles * d]: sphere radius in entry 0,
+                             box half-sides; finite, >= 0; copied */
+  int64_t point_capacity; /* initial reservation in points (grows on demand) */
+  void* hip_stream;       /* hipStream_t for all device work; NULL = the null stream */
+  int32_t device;         /* HIP device ordinal; -1 = the device current at create */
+} pirrt_rrg_config;
+
+/* Creates a handle with no points.  Errors: EINVAL (d outside 1..8, bad obstacle),
+   ENOMEM, EDEVICE. */
+int pirrt_rrg_create(pirrt_rrg** out, const pirrt_rrg_config* cfg);
+int pirrt_rrg_destroy(pirrt_rrg* r);
+int64_t pirrt_rrg_num_points(const pirrt_rrg* r);
+
+/* Appends count given points (float64[count * d], finite; e.g. x_init and x_goal). */
+int pirrt_rrg_add_points(pirrt_rrg* r, int32_t count, const double* pts, int mem_kind);
+
+/* Appends count free samples of stream `stream` under `seed`, starting at candidate
+   *counter; on return *counter is one past the last candidate taken, so successive
+   calls continue the same sequence.  EINVAL if no free sample turns up. */
+int pirrt_rrg_sample(pirrt_rrg* r, uint64_t seed, uint32_t stream, uint64_t* counter, int32_t count);
+
+/* Copies points first .. first+count-1 out (float64[count * d]). */
+int pirrt_rrg_get_points(pirrt_rrg* r, int64_t first, int64_t count, double* out, int mem_kind);
+
+/* Forward rows of points n_old .. n-1 against all earlier points at the given
+   radius: row_ptr int64[n - n_old + 1], col int32 / cost float[*nnz] (col and cost
+   may be NULL).  *nnz receives the entry count; EINVAL if it exceeds capacity. */
+int pirrt_rrg_rows(pirrt_rrg* r, int64_t n_old, double radius, int64_t* row_ptr, int32_t* col, float* cost,
+                   int64_t capacity, int64_t* nnz, int mem_kind);
+
+/* Builds the rows of points n_old .. n-1 and inserts them into g, which must hold
+   exactly the points 0 .. n_old-1 as its vertices (pirrt_insert_batch on device
+   buffers; g and r on the same device). */
+int pirrt_rrg_connect(pirrt_rrg* r, int64_t n_old, double radius, pirrt_graph* g);
+
+/* Builds the rows of all points and adds them to b as one new problem
+   (pirrt_batch_add_problem); *index (nullable) receives its index. */
+int pirrt_rrg_connect_problem(pirrt_rrg* r, double radius, pirrt_batch* b, int32_t* index);
+
+/* h_out float[n]: heuristic of every point towards point `goal`. */
+int pirrt_rrg_heuristic(pirrt_rrg* r, int64_t goal, float* h_out, int mem_kind);
+
+const char* pirrt_rrg_last_error(const pirrt_rrg* r);
+
 #ifdef __cplusplus
 }
 #endif

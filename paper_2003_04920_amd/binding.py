@@ -29,12 +29,21 @@ EXPORTS = [
     "pirrt_batch_num_vertices", "pirrt_batch_num_edges", "pirrt_batch_problem_offset", "pirrt_batch_replan",
     "pirrt_batch_get_policy", "pirrt_batch_snapshot_save", "pirrt_batch_snapshot_restore",
     "pirrt_batch_last_error",
+    "pirrt_rrg_create", "pirrt_rrg_destroy", "pirrt_rrg_num_points", "pirrt_rrg_add_points", "pirrt_rrg_sample",
+    "pirrt_rrg_get_points", "pirrt_rrg_rows", "pirrt_rrg_connect", "pirrt_rrg_connect_problem",
+    "pirrt_rrg_heuristic", "pirrt_rrg_last_error",
 ]
 
 
 class pirrt_config(ctypes.Structure):
     _fields_ = [("vertex_capacity", ctypes.c_int64), ("edge_capacity", ctypes.c_int64),
                 ("hip_stream", ctypes.c_void_p), ("max_iters", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class pirrt_rrg_config(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n_obstacles", ctypes.c_int32), ("kind", ctypes.c_void_p),
+                ("centre", ctypes.c_void_p), ("size", ctypes.c_void_p), ("point_capacity", ctypes.c_int64),
+                ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32)]
 
 
 class pirrt_stats(ctypes.Structure):
@@ -96,6 +105,17 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_batch_snapshot_save": (cint, [vp]),
         "pirrt_batch_snapshot_restore": (cint, [vp]),
         "pirrt_batch_last_error": (ctypes.c_char_p, [vp]),
+        "pirrt_rrg_create": (cint, [ctypes.POINTER(vp), ctypes.POINTER(pirrt_rrg_config)]),
+        "pirrt_rrg_destroy": (cint, [vp]),
+        "pirrt_rrg_num_points": (i64, [vp]),
+        "pirrt_rrg_add_points": (cint, [vp, i32, vp, cint]),
+        "pirrt_rrg_sample": (cint, [vp, ctypes.c_uint64, u32, ctypes.POINTER(ctypes.c_uint64), i32]),
+        "pirrt_rrg_get_points": (cint, [vp, i64, i64, vp, cint]),
+        "pirrt_rrg_rows": (cint, [vp, i64, ctypes.c_double, vp, vp, vp, i64, ctypes.POINTER(i64), cint]),
+        "pirrt_rrg_connect": (cint, [vp, i64, ctypes.c_double, vp]),
+        "pirrt_rrg_connect_problem": (cint, [vp, ctypes.c_double, vp, ctypes.POINTER(i32)]),
+        "pirrt_rrg_heuristic": (cint, [vp, i64, vp, cint]),
+        "pirrt_rrg_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -365,6 +385,98 @@ class Batch:
 
     def snapshot_restore(self) -> int:
         return self._check(self._lib.pirrt_batch_snapshot_restore(self._h))
+
+
+class Rrg:
+    """One pirrt_rrg handle: a scene (unit cube, sphere / box obstacles) and its
+    points on the device.  `obstacles` has .d, .kind, .centre and .size arrays (or
+    is None for free space)."""
+
+    def __init__(self, d: int, obstacles=None, stream: Optional[int] = None, device: int = -1,
+                 point_capacity: int = 0, lib: Optional[ctypes.CDLL] = None):
+        self._lib = lib or load()
+        self.d = int(d)
+        m = 0 if obstacles is None else len(obstacles.kind)
+        self._kind = np.ascontiguousarray(obstacles.kind if m else np.zeros(1), np.int32)
+        self._centre = np.ascontiguousarray(obstacles.centre if m else np.zeros((1, d)), np.float64)
+        self._size = np.ascontiguousarray(obstacles.size if m else np.zeros((1, d)), np.float64)
+        cfg = pirrt_rrg_config()
+        cfg.d = self.d
+        cfg.n_obstacles = m
+        cfg.kind = self._kind.ctypes.data
+        cfg.centre = self._centre.ctypes.data
+        cfg.size = self._size.ctypes.data
+        cfg.point_capacity = point_capacity
+        cfg.hip_stream = stream or None
+        cfg.device = device
+        h = ctypes.c_void_p()
+        rc = self._lib.pirrt_rrg_create(ctypes.byref(h), ctypes.byref(cfg))
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_rrg_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.pirrt_rrg_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_rrg_last_error(self._h).decode())
+        return rc
+
+    @property
+    def n(self) -> int:
+        return int(self._lib.pirrt_rrg_num_points(self._h))
+
+    def add_points(self, pts) -> int:
+        pts = _check_dtype(pts, np.float64, "float64")
+        count = int(pts.shape[0]) if pts.ndim > 1 else int(pts.shape[0]) // self.d
+        return self._check(self._lib.pirrt_rrg_add_points(self._h, count, _ptr(pts), _mem_kind(pts)))
+
+    def sample(self, seed: int, stream: int, counter: int, count: int) -> int:
+        """Appends `count` free samples; returns the next counter."""
+        c = ctypes.c_uint64(counter)
+        self._check(self._lib.pirrt_rrg_sample(self._h, int(seed), int(stream), ctypes.byref(c), int(count)))
+        return int(c.value)
+
+    def points(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.n - first if count is None else count
+        out = np.empty((max(count, 0), self.d), np.float64)
+        self._check(self._lib.pirrt_rrg_get_points(self._h, first, count, _ptr(out), PIRRT_MEM_HOST))
+        return out
+
+    def rows(self, n_old: int, radius: float):
+        """Forward rows (row_ptr, col, cost) of points n_old .. n-1, on the host."""
+        nnz = ctypes.c_int64(0)
+        rp = np.empty(self.n - n_old + 1, np.int64)
+        rc = self._lib.pirrt_rrg_rows(self._h, n_old, radius, _ptr(rp), None, None, 0, ctypes.byref(nnz),
+                                      PIRRT_MEM_HOST)
+        if rc not in (PIRRT_OK, PIRRT_EINVAL) or (rc == PIRRT_EINVAL and nnz.value == 0 and self.n > n_old):
+            self._check(rc)
+        m = int(nnz.value)
+        col = np.empty(max(m, 1), np.int32)
+        cost = np.empty(max(m, 1), np.float32)
+        self._check(self._lib.pirrt_rrg_rows(self._h, n_old, radius, _ptr(rp), _ptr(col), _ptr(cost), m,
+                                             ctypes.byref(nnz), PIRRT_MEM_HOST))
+        return rp, col[:m], cost[:m]
+
+    def connect(self, n_old: int, radius: float, graph: "Graph") -> int:
+        return self._check(self._lib.pirrt_rrg_connect(self._h, n_old, radius, graph.handle))
+
+    def connect_problem(self, radius: float, batch: "Batch") -> int:
+        idx = ctypes.c_int32(-1)
+        self._check(self._lib.pirrt_rrg_connect_problem(self._h, radius, batch._h, ctypes.byref(idx)))
+        return int(idx.value)
+
+    def heuristic(self, goal: int, out=None):
+        out = np.empty(self.n, np.float32) if out is None else out
+        self._check(self._lib.pirrt_rrg_heuristic(self._h, goal, _ptr(out), _mem_kind(out)))
+        return out
 
 
 def pirrt_strerror(code: int) -> str:

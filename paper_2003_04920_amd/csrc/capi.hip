@@ -371,6 +371,33 @@ int ensure_spare(pirrt_graph* G, int64_t need) {
   return PIRRT_OK;
 }
 
+// Room for `need` entries in the current adjacency arrays (keeping the entries).
+int ensure_adjacency(pirrt_graph* G, int64_t need) {
+  if (need <= G->ecap) return PIRRT_OK;
+  int64_t cap = G->ecap + G->ecap / 2;
+  if (cap < need) cap = need;
+  if (cap < kMinEdgeCap) cap = kMinEdgeCap;
+  int32_t* c = nullptr;
+  float* w = nullptr;
+  if (!dalloc(&c, cap) || !dalloc(&w, cap)) {
+    dfree(c);
+    dfree(w);
+    return fail(G, PIRRT_ENOMEM, "device allocation for adjacency failed");
+  }
+  if (G->nnz > 0) {
+    HIP_OR_FAIL(G, hipMemcpyAsync(c, G->col, sizeof(int32_t) * (size_t)G->nnz, hipMemcpyDeviceToDevice, G->stream));
+    HIP_OR_FAIL(G, hipMemcpyAsync(w, G->cst, sizeof(float) * (size_t)G->nnz, hipMemcpyDeviceToDevice, G->stream));
+  }
+  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
+  dfree(G->col);
+  dfree(G->cst);
+  G->col = c;
+  G->cst = w;
+  G->ecap = cap;
+  drop_loops(G);
+  return PIRRT_OK;
+}
+
 int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
   if (rows + 1 > G->brows_cap) {
     int64_t* p = nullptr;
@@ -596,19 +623,30 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
     return fail(G, PIRRT_EINVAL, m);
   }
   if ((rc = ensure_vcap(G, n1))) return rc;
-  if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) return rc;
+  if (new_problem) {
+    if ((rc = ensure_adjacency(G, G->nnz + 2 * nnz_b))) return rc;
+  } else if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) {
+    return rc;
+  }
   // new vertices take the slots after the existing ones; neighbours to slots
   launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
   launch_fill_i32(n_old, n1, new_problem ? (int32_t)G->pbase.size() - 1 : 0, G->prob, s);
   launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
-  // adjacency rebuild into the spare arrays, then swap
-  launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
-                 G->deg, G->scan_scratch, s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  std::swap(G->rp, G->rp2);
-  std::swap(G->col, G->col2);
-  std::swap(G->cst, G->cst2);
-  std::swap(G->ecap, G->ecap2);
+  if (new_problem) {
+    // a new problem shares no edge with the older ones: its rows are appended
+    launch_append(n_new, n_old, G->nnz, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->add, G->deg, G->rp2,
+                  G->scan_scratch, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+  } else {
+    // adjacency rebuild into the spare arrays, then swap
+    launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2,
+                   G->add, G->deg, G->scan_scratch, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    std::swap(G->rp, G->rp2);
+    std::swap(G->col, G->col2);
+    std::swap(G->cst, G->cst2);
+    std::swap(G->ecap, G->ecap2);
+  }
   G->n = n1;
   G->nnz += 2 * nnz_b;
   G->hslot.resize((size_t)n1);

@@ -19,6 +19,12 @@ void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
                     const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
                     int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
                     hipStream_t s);
+// Appends a block whose entries all lie inside it (a new problem of a batch): its
+// rows go after the nnz_old existing entries of rp / col / cst, which must have room
+// for nnz_old + 2 * brp[n_new] entries; older rows are untouched.  tmp: n_new + 1.
+void launch_append(int32_t n_new, int64_t n_old, int64_t nnz_old, const int64_t* brp, const int32_t* bcol,
+                   const float* bcost, int64_t* rp, int32_t* col, float* cst, int32_t* add, int32_t* deg,
+                   int64_t* tmp, void* scan_scratch, hipStream_t s);
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s);
 // bcol: neighbour ids as given (tie-break keys); bslot: the same in storage slots.

@@ -219,6 +219,39 @@ void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
                        bcost, rp_new, add, col_new, cst_new);
 }
 
+namespace {
+
+// Degrees of the vertices of an appended block (no entry touches an older row).
+__global__ void __launch_bounds__(kThreads) k_degrees_append(int32_t n_new, int64_t n_old,
+                                                            const int64_t* __restrict__ brp,
+                                                            int32_t* __restrict__ add, int32_t* __restrict__ deg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_new) return;
+  deg[i] = add[n_old + i];
+  add[n_old + i] = (int32_t)(brp[i + 1] - brp[i]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_offset_rows(int32_t n_new, int64_t n_old, int64_t base,
+                                                         const int64_t* __restrict__ tmp, int64_t* __restrict__ rp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n_new) rp[n_old + i] = base + tmp[i];
+}
+
+}  // namespace
+
+void launch_append(int32_t n_new, int64_t n_old, int64_t nnz_old, const int64_t* brp, const int32_t* bcol,
+                   const float* bcost, int64_t* rp, int32_t* col, float* cst, int32_t* add, int32_t* deg,
+                   int64_t* tmp, void* scan_scratch, hipStream_t s) {
+  hipMemsetAsync(add + n_old, 0, sizeof(int32_t) * (size_t)n_new, s);
+  hipLaunchKernelGGL(k_count_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add);
+  hipLaunchKernelGGL(k_degrees_append, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, add, deg);
+  scan_i32_to_i64(deg, n_new, tmp, scan_scratch, s);
+  hipLaunchKernelGGL(k_offset_rows, dim3(blocks_for((int64_t)n_new + 1)), dim3(kThreads), 0, s, n_new, n_old, nnz_old,
+                     tmp, rp);
+  hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, bcost,
+                     rp, add, col, cst);
+}
+
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s) {
   hipLaunchKernelGGL(k_pending, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, pending,

@@ -75,3 +75,60 @@ def test_plain_6d_1m(P, big):
     assert_same_policy("replan +10k", gg, pp, st.g, st.parent)
     assert_same_stats("replan +10k", sg, so)
     print("+10k replan stats", sg, flush=True)
+
+
+def test_multi_graph_512(P):
+    """The 512-problem multi-graph set (28.6M vertices) built on the device and
+    replanned by one batched call, as the benchmark's multi workload does.  Eight
+    problems of different dimensions are compared with the oracle on its own build
+    (points, rows and Replan); every problem is checked for a consistent, rooted
+    policy (g(v) = g(parent) + pcost bit for bit, g(root) = 0) and for stopping."""
+    import torch
+    from oracle import rrg as RR
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    specs = [W.multi_problem_spec(i) for i in range(512)]
+    B = P.Batch(stream=stream)
+    hs, rrgs = [], []
+    for sp in specs:
+        R = P.Rrg(sp.d, sp.obstacles, stream=stream, point_capacity=sp.n)
+        R.add_points(np.stack([np.full(sp.d, 0.05), np.full(sp.d, 0.95)]))
+        R.sample(sp.sample_seed, 0, 0, sp.n - 2)
+        R.connect_problem(sp.radius, B)
+        hs.append(R.heuristic(1, out=torch.empty(sp.n, dtype=torch.float32, device=dev)))
+        rrgs.append(R)
+    print("built %d problems: n=%d nnz=%d" % (len(specs), B.n, B.nnz), flush=True)
+    h = torch.cat(hs)
+    g, parent, stats = B.replan(np.zeros(512, np.int32), np.ones(512, np.int32), h)
+    assert all(s["rc"] == 0 for s in stats)
+    off = B.offsets
+    # invariants on every problem (device arithmetic: binary32 adds, no contraction)
+    gd, pd, cd = B.get_policy(device=dev)
+    base = torch.from_numpy(np.repeat(off[:-1], np.diff(off))).to(dev)
+    has = pd >= 0
+    gp = gd[(pd.long() + base)[has]]
+    assert torch.equal((gp + cd[has]).view(torch.int32), gd[has].view(torch.int32))
+    assert torch.all(gd[torch.from_numpy(off[:-1]).to(dev)] == 0)
+    # sampled problems against the oracle's own build
+    picked, seen = [], set()
+    for sp in specs:
+        if sp.n <= 12000 and (sp.d, sp.n > 8000) not in seen:
+            seen.add((sp.d, sp.n > 8000))
+            picked.append(sp)
+        if len(picked) == 8:
+            break
+    for sp in picked:
+        i = sp.index
+        pts = np.concatenate([np.stack([np.full(sp.d, 0.05), np.full(sp.d, 0.95)]),
+                              RR.sample(sp.d, sp.sample_seed, 0, 0, sp.n - 2, sp.obstacles)[0]])
+        assert np.array_equal(rrgs[i].points(), pts)
+        rp, col, cost = RR.build_rows(pts, 0, sp.radius, sp.obstacles)
+        orc = O.Graph()
+        assert orc.insert_batch(W.Batch(0, sp.n, rp, col, cost, sp.radius)) == 0
+        rc, so = orc.replan(0, 1, RR.heuristic(pts, pts[1]), True)
+        assert rc == 0
+        st = orc.state()
+        assert_same_policy("problem %d (d=%d n=%d)" % (i, sp.d, sp.n), g[off[i]:off[i + 1]],
+                           parent[off[i]:off[i + 1]], st.g, st.parent)
+        assert_same_stats("problem %d" % i, stats[i], so)
+    print("compared problems %s with the oracle" % [sp.index for sp in picked], flush=True)

@@ -271,6 +271,33 @@ def multi_problem(index: int, base_seed: int = 1000, n_min: int = 5000, n_max: i
                 [samples if samples is not None else max(1, n - 2)])
 
 
+@dataclass
+class ProblemSpec:
+    """A multi-graph problem without its samples: the device samples them (Philox,
+    stream 0 under `sample_seed`) after x_init = (0.05)^d and x_goal = (0.95)^d."""
+    index: int
+    d: int
+    n: int                 # vertices including x_init and x_goal
+    obstacles: Obstacles
+    sample_seed: int
+
+    @property
+    def radius(self) -> float:
+        return radius(self.n, self.d)
+
+
+def multi_problem_spec(index: int, base_seed: int = 1000, n_min: int = 5000,
+                       n_max: int = 200_000) -> ProblemSpec:
+    """Problem `index` of the multi-graph set with the same d, n and obstacles as
+    multi_problem(index, ...)."""
+    rng = _rng(base_seed + index)
+    d = int(rng.choice([2, 3, 4, 6, 8]))
+    n = int(round(math.exp(math.log(n_min) + rng.random() * (math.log(n_max) - math.log(n_min)))))
+    k = int(rng.integers(10, 41))
+    obs = make_obstacles(d, k, "mixed", base_seed + 100_000 + index)
+    return ProblemSpec(index, d, max(n, 3), obs, base_seed + 200_000 + index)
+
+
 def path_graph(n: int, costs: np.ndarray) -> Batch:
     """A path 0-1-2-...-(n-1); costs[i] is the cost of edge (i, i+1)."""
     row_ptr = np.zeros(n + 1, np.int64)
