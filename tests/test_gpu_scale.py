@@ -100,6 +100,7 @@ def test_multi_graph_512(P):
     print("built %d problems: n=%d nnz=%d" % (len(specs), B.n, B.nnz), flush=True)
     h = torch.cat(hs)
     g, parent, stats = B.replan(np.zeros(512, np.int32), np.ones(512, np.int32), h)
+    g, parent = g.cpu().numpy(), parent.cpu().numpy()
     assert all(s["rc"] == 0 for s in stats)
     off = B.offsets
     # invariants on every problem (device arithmetic: binary32 adds, no contraction)
