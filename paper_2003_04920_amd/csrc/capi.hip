@@ -21,6 +21,7 @@ namespace {
 constexpr int64_t kMinVertexCap = 1024;
 constexpr int64_t kMinEdgeCap = 4096;
 constexpr int kGraphIterCounts = 4;  // captured loop bodies of 1, 2, 4 and 8 iterations
+constexpr int64_t kAdjSlack = 4;     // entries past the end of the adjacency arrays (quad loads)
 
 // Pinned host block for small read-backs.
 struct HostBlock {
@@ -99,7 +100,7 @@ struct pirrt_graph {
   int32_t* fr1 = nullptr;
   int32_t* lvl = nullptr;
   // promising / domain marks and Evaluate stamps {epoch, g bits}
-  uint32_t* stamp = nullptr;
+  uint8_t* stamp = nullptr;
   unsigned long long* word = nullptr;
   bool eval_levels = false;   // level-synchronous Evaluate instead of the walk
   int walk_parts = 1;         // walk launches over consecutive slot ranges
@@ -123,6 +124,7 @@ struct pirrt_graph {
   IterCounters* ctr = nullptr;
   LoopCtl* ctl = nullptr;
   int32_t* pscratch = nullptr;  // per-problem ints (renumbering counters)
+  int32_t* pstart = nullptr;    // per-problem ints (renumbering level starts)
   int32_t* droots = nullptr;    // caller ids of the slots that carry root marks
   int32_t nroots = 0;
   std::vector<int32_t> hroots;       // host copy of droots
@@ -277,7 +279,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   }
   hipStream_t s = G->stream;
   HIP_OR_FAIL(G, hipMemsetAsync(T.child_cnt, 0, sizeof(int32_t) * (size_t)cap, s));
-  HIP_OR_FAIL(G, hipMemsetAsync(T.stamp, 0, sizeof(uint32_t) * (size_t)cap, s));
+  HIP_OR_FAIL(G, hipMemsetAsync(T.stamp, 0, (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.word, 0, sizeof(unsigned long long) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.rp, 0, sizeof(int64_t) * (size_t)(cap + 1), s));
   if (G->n > 0) {
@@ -313,21 +315,23 @@ int ensure_pcap(pirrt_graph* G, int64_t need) {
   int32_t* scr = nullptr;
   int32_t* roots = nullptr;
   ProblemState* hps = nullptr;
-  bool ok = dalloc(&ps, cap) && dalloc(&ctr, cap * kCounterSlots) && dalloc(&scr, cap) && dalloc(&roots, cap);
+  int32_t* pst = nullptr;
+  bool ok = dalloc(&ps, cap) && dalloc(&ctr, cap * kCounterSlots) && dalloc(&scr, cap) && dalloc(&roots, cap) &&
+            dalloc(&pst, cap);
   if (ok && hipHostMalloc((void**)&hps, sizeof(ProblemState) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     hps = nullptr;
     ok = false;
   }
   if (!ok) {
-    dfree(ps); dfree(ctr); dfree(scr); dfree(roots);
+    dfree(ps); dfree(ctr); dfree(scr); dfree(roots); dfree(pst);
     return fail(G, PIRRT_ENOMEM, "allocation of per-problem state failed");
   }
   if (G->nroots > 0)
     HIP_OR_FAIL(G, hipMemcpy(roots, G->droots, sizeof(int32_t) * (size_t)G->nroots, hipMemcpyDeviceToDevice));
-  dfree(G->ps); dfree(G->ctr); dfree(G->pscratch); dfree(G->droots);
+  dfree(G->ps); dfree(G->ctr); dfree(G->pscratch); dfree(G->droots); dfree(G->pstart);
   if (G->hps) (void)hipHostFree(G->hps);
-  G->ps = ps; G->ctr = ctr; G->pscratch = scr; G->droots = roots; G->hps = hps;
+  G->ps = ps; G->ctr = ctr; G->pscratch = scr; G->droots = roots; G->hps = hps; G->pstart = pst;
   G->pcap = cap;
   drop_loops(G);
   return PIRRT_OK;
@@ -358,7 +362,7 @@ int ensure_spare(pirrt_graph* G, int64_t need) {
   if (cap < kMinEdgeCap) cap = kMinEdgeCap;
   int32_t* c = nullptr;
   float* w = nullptr;
-  if (!dalloc(&c, cap) || !dalloc(&w, cap)) {
+  if (!dalloc(&c, cap + kAdjSlack) || !dalloc(&w, cap + kAdjSlack)) {
     dfree(c);
     dfree(w);
     return fail(G, PIRRT_ENOMEM, "device allocation for adjacency failed");
@@ -379,7 +383,7 @@ int ensure_adjacency(pirrt_graph* G, int64_t need) {
   if (cap < kMinEdgeCap) cap = kMinEdgeCap;
   int32_t* c = nullptr;
   float* w = nullptr;
-  if (!dalloc(&c, cap) || !dalloc(&w, cap)) {
+  if (!dalloc(&c, cap + kAdjSlack) || !dalloc(&w, cap + kAdjSlack)) {
     dfree(c);
     dfree(w);
     return fail(G, PIRRT_ENOMEM, "device allocation for adjacency failed");
@@ -437,6 +441,7 @@ void release_all(pirrt_graph* G) {
   dfree(G->brp); dfree(G->bcol); dfree(G->bslot); dfree(G->bcost);
   dfree(G->info); dfree(G->dflag); dfree(G->dcount); dfree(G->dhops);
   dfree(G->ps); dfree(G->ctr); dfree(G->ctl); dfree(G->pscratch); dfree(G->droots); dfree(G->dbase);
+  dfree(G->pstart);
   if (G->hps) (void)hipHostFree(G->hps);
   G->hps = nullptr;
   if (G->scan_scratch) (void)hipFree(G->scan_scratch);
@@ -518,16 +523,27 @@ int renumber(pirrt_graph* G) {
   HIP_OR_FAIL(G, hipMemsetAsync(visited, 0, sizeof(int32_t) * (size_t)n, s));
   launch_bfs_init(P, Fn, G->dbase, order, visited, G->pscratch, F, &G->dcount[0], s);
   HIP_OR_FAIL(G, hipGetLastError());
-  int32_t fsize = P;
+  // scratch of the level ordering (all free until the permutation below)
+  int32_t* key = G->add;
+  int32_t* cand = G->deg;
+  int32_t* hist = G->lvl;
+  int32_t* cursor = G->child_ptr;
+  int64_t* off = G->rp2;
+  launch_fill_i32(0, n, INT32_MAX, key, s);
+  int32_t fsize = P, tag = 2, levels = 0;
   while (fsize > 0) {
     HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[1], 0, sizeof(int32_t), s));
-    launch_graph_bfs_level(fsize, F, Fn, &G->dcount[1], order, problem_map(G), G->pscratch, G->rp, G->col, visited,
-                           s);
+    launch_bfs_discover(fsize, F, tag, G->rp, G->col, visited, key, cand, &G->dcount[1], s);
     HIP_OR_FAIL(G, hipGetLastError());
     HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[1], &G->dcount[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    fsize = G->host->count[1];
-    if (fsize > n) return fail_device(G, hipErrorUnknown, "renumbering visited too many vertices");
+    const int32_t m = G->host->count[1];
+    if (m > n || ++levels > n) return fail_device(G, hipErrorUnknown, "renumbering visited too many vertices");
+    launch_bfs_order_level(fsize, m, cand, key, hist, off, cursor, Fn, problem_map(G), G->pstart, G->pscratch, order,
+                           G->scan_scratch, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    fsize = m;
+    ++tag;
     std::swap(F, Fn);
   }
   launch_append_unvisited(n, visited, order, problem_map(G), G->pscratch, s);
@@ -788,6 +804,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
     q.cap = (int32_t)std::min<int64_t>(cap_iters, INT32_MAX);
   }
   HIP_OR_FAIL(G, hipMemcpyAsync(G->ps, G->hps, sizeof(ProblemState) * (size_t)P, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(G, hipMemsetAsync(G->stamp, 0, (size_t)n, s));  // no stamp older than this Replan
   // the previous roots lose their mark; the new roots get it
   launch_unmark_roots(G->nroots, G->droots, G->slot_of, G->parent, s);
   HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, root_ids, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));

@@ -12,6 +12,10 @@ namespace {
 
 __device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ? 1u : e + 1; }
 
+// Mark epochs are stored as their low byte: skip the values whose low byte is 0
+// (the cleared stamp).
+__device__ __forceinline__ uint32_t next_mark_epoch(uint32_t e) { return ((e + 1) & 0xffu) == 0 ? e + 2 : e + 1; }
+
 // Marks the roots, clears the counters and takes fresh epochs.
 __global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, int32_t* __restrict__ parent,
                               float* __restrict__ pcost, IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl) {
@@ -29,7 +33,7 @@ __global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, in
     pcost[r] = 0.0f;
   }
   if (t == 0) {
-    ctl->epoch = next_epoch(ctl->epoch);
+    ctl->epoch = next_mark_epoch(ctl->epoch);
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
     ctl->any_active = 1;
     ctl->any_eval = 1;
@@ -89,7 +93,7 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
       s.needs_eval = 0;
     }
   }
-  if (i == 0 && t == 0) ctl->epoch = next_epoch(ctl->epoch);
+  if (i == 0 && t == 0) ctl->epoch = next_mark_epoch(ctl->epoch);
 }
 
 // Runs after the evaluate of an iteration: a new evaluate epoch, and whether any

@@ -10,13 +10,17 @@
 //           when that value is strictly below g(v).  g is only read (Jacobi step),
 //           so all rows are independent.
 //
-// Work split: one group of GW lanes per vertex slot, U row entries per lane in
-// flight (GW x U = 64 entries per pass over a row); the grid covers all slots, and
-// a wave whose vertices are all outside the set leaves after one round trip,
-// freeing its slot for the next.  Loads are issued unconditionally (row positions
-// past the end re-read the first entry and are masked): `vmcnt` is an in-order
-// counter, so a load under a branch would make every later load wait for it.  The
-// per-row minimum is a DPP butterfly.
+// Work split: one group of GW lanes per vertex slot, Q aligned quads of row entries
+// per lane in flight (GW x Q x 4 = 64 entries per pass over a row by default); the
+// grid covers all slots.  Loads are issued unconditionally (quads past the end of
+// the row re-read the first one and are masked): `vmcnt` is an in-order counter, so
+// a load under a branch would make every later load wait for it.  The per-row
+// minimum is a DPP butterfly.
+//
+// Stamps are one byte: the low byte of the mark epoch (never 0).  The host clears
+// them before every Replan, and Improve clears every stamp it reads in the
+// iteration after which the low byte would wrap, so a stamp never survives 255
+// epochs.
 //
 // kBatched: several problems share the arrays; prob[slot] names the problem of a
 // slot.  Without it every slot belongs to problem 0.
@@ -83,15 +87,21 @@ __device__ __forceinline__ void flush_counters(IterCounters* ctr, int p, bool le
 
 // Idx: uint32_t when every adjacency offset fits (32-bit offsets let the loads use a
 // scalar base plus a 32-bit vector offset), int64_t otherwise.
-template <int GW, int U, typename Idx, bool kBatched>
+//
+// Rows are read in aligned quads of entries (16-byte loads of neighbour slots and of
+// costs): quad k holds entries 4k .. 4k+3, and the entries of a quad that lie outside
+// the row [a, b) are masked (their neighbour is replaced by slot 0 before any
+// gather).  The adjacency arrays keep at least three entries of slack past the last
+// one, so the last quad of the last row stays inside the allocation.
+template <int GW, int Q, typename Idx, bool kBatched>
 __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __restrict__ prob,
                                                   const ProblemState* __restrict__ ps,
                                                   const LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                   const float* __restrict__ h, const int64_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col, uint32_t* __restrict__ stamp,
+                                                  const int32_t* __restrict__ col, uint8_t* __restrict__ stamp,
                                                   IterCounters* __restrict__ ctr) {
   if (ctl->any_active == 0) return;  // every problem has converged
-  const uint32_t epoch = ctl->epoch;
+  const uint8_t ep = (uint8_t)ctl->epoch;
   const int gl = threadIdx.x % GW;
   const int64_t v = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
   const int32_t x = v < n ? (int32_t)v : n - 1;
@@ -101,68 +111,98 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
   const Idx ra = (Idx)rp[x], rb = (Idx)rp[x + 1];
   const bool in = v < n && add_rn(gx, hx) < G;
   if (in) {
-    if (gl == 0) stamp[x] = epoch;
-    for (Idx j = ra + gl; j < rb; j += GW * U) {
-      int32_t w[U];
+    if (gl == 0) stamp[x] = ep;
+    const int4* col4 = reinterpret_cast<const int4*>(col);
+    const Idx qa = ra >> 2, qb = (rb + 3) >> 2;
+    for (Idx k = qa + gl; k < qb; k += GW * Q) {
+      int4 w[Q];
 #pragma unroll
-      for (int q = 0; q < U; ++q) w[q] = col[j + q * GW < rb ? j + q * GW : ra];
+      for (int q = 0; q < Q; ++q) w[q] = col4[k + q * GW < qb ? k + q * GW : qa];
 #pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (j + q * GW < rb) stamp[w[q]] = epoch;
+      for (int q = 0; q < Q; ++q) {
+        if (k + q * GW >= qb) continue;
+        const Idx j0 = (k + q * GW) * 4;
+        const int32_t u[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j0 + e >= ra && j0 + e < rb) stamp[u[e]] = ep;
+      }
     }
   }
   flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0);
 }
 
-template <int GW, int U, typename Idx, bool kBatched>
+template <int GW, int Q, typename Idx, bool kBatched>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* __restrict__ prob,
                                                      const ProblemState* __restrict__ ps,
                                                      const LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ cst, const uint32_t* __restrict__ stamp,
+                                                     const float* __restrict__ cst, uint8_t* __restrict__ stamp,
                                                      const int32_t* __restrict__ ext_of,
                                                      int32_t* __restrict__ parent, float* __restrict__ pcost,
                                                      IterCounters* __restrict__ ctr) {
   if (ctl->any_active == 0) return;  // every problem has converged
   const uint32_t epoch = ctl->epoch;
+  const uint8_t ep = (uint8_t)epoch;
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane / GW, gl = threadIdx.x % GW;
   const int64_t v = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
   const int32_t x = v < n ? (int32_t)v : n - 1;
   const int p = kBatched ? prob[x] : 0;
-  const uint32_t sx = stamp[x];
+  const uint8_t sx = stamp[x];
   const float gx = g[x];
   const Idx ra = (Idx)rp[x], rb = (Idx)rp[x + 1];
-  const bool in = v < n && sx == epoch && x != ps[p].root;
+  const bool in = v < n && sx == ep && x != ps[p].root;
+  // the next mark epoch wraps its low byte: leave every stamp cleared
+  if ((epoch & 0xffu) == 0xffu && v < n && gl == 0 && sx != 0) stamp[x] = 0;
   const Idx a = in ? ra : 0, b = in ? rb : 0;
+  const int4* col4 = reinterpret_cast<const int4*>(col);
+  const float4* cst4 = reinterpret_cast<const float4*>(cst);
   // lane-local minimum of (g(u) + c, caller id of u, c); bu = slot of u
   uint32_t bv = 0xffffffffu, bc = 0xffffffffu;
   int32_t bu = -1;
-  for (Idx j = a + gl; j < b; j += GW * U) {
-    int32_t u[U];
-    float c[U];
+  const Idx qa = a >> 2, qb = (b + 3) >> 2;
+  for (Idx k = qa + gl; k < qb; k += GW * Q) {
+    int4 w[Q];
+    float4 cw[Q];
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const Idx jj = j + q * GW < b ? j + q * GW : a;
-      u[q] = col[jj];
-      c[q] = cst[jj];
+    for (int q = 0; q < Q; ++q) {
+      const Idx kk = k + q * GW < qb ? k + q * GW : qa;
+      w[q] = col4[kk];
+      cw[q] = cst4[kk];
     }
-    float gu[U];
+    int32_t u[4 * Q];
+    float c[4 * Q];
+    bool ok[4 * Q];
 #pragma unroll
-    for (int q = 0; q < U; ++q) gu[q] = g[u[q]];
+    for (int q = 0; q < Q; ++q) {
+      const Idx j0 = (k + q * GW) * 4;
+      const bool live = k + q * GW < qb;
+      const int32_t uu[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
+      const float cc[4] = {cw[q].x, cw[q].y, cw[q].z, cw[q].w};
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      if (j + q * GW >= b) continue;
-      const uint32_t vb = __float_as_uint(add_rn(gu[q], c[q])), cb = __float_as_uint(c[q]);
+      for (int e = 0; e < 4; ++e) {
+        ok[4 * q + e] = live && j0 + e >= a && j0 + e < b;
+        u[4 * q + e] = ok[4 * q + e] ? uu[e] : 0;
+        c[4 * q + e] = cc[e];
+      }
+    }
+    float gu[4 * Q];
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i) gu[i] = g[u[i]];
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i) {
+      if (!ok[i]) continue;
+      const uint32_t vb = __float_as_uint(add_rn(gu[i], c[i])), cb = __float_as_uint(c[i]);
       if (vb >= 0x7f800000u) continue;  // +inf never improves anything
       if (vb < bv) {
         bv = vb;
-        bu = u[q];
+        bu = u[i];
         bc = cb;
       } else if (vb == bv) {  // equal candidates within one lane: rare
-        const int32_t e1 = ext_of[u[q]], e0 = ext_of[bu];
+        const int32_t e1 = ext_of[u[i]], e0 = ext_of[bu];
         if (e1 < e0 || (e1 == e0 && cb < bc)) {
-          bu = u[q];
+          bu = u[i];
           bc = cb;
         }
       }
@@ -228,22 +268,22 @@ void launch_improve_b(const StepArgs& a, hipStream_t s) {
 
 }  // namespace
 
-// Variants: lanes per row x entries per lane in flight.
+// Variants: lanes per row x quads per lane in flight (GW x Q x 4 entries per pass).
 void launch_mark(const StepArgs& a, int variant, hipStream_t s) {
   switch (variant) {
-    case 0: launch_mark_b<16, 4>(a, s); break;
-    case 1: launch_mark_b<8, 8>(a, s); break;
-    case 2: launch_mark_b<32, 2>(a, s); break;
-    default: launch_mark_b<4, 16>(a, s); break;
+    case 0: launch_mark_b<16, 1>(a, s); break;
+    case 1: launch_mark_b<8, 2>(a, s); break;
+    case 2: launch_mark_b<4, 4>(a, s); break;
+    default: launch_mark_b<8, 1>(a, s); break;
   }
 }
 
 void launch_improve(const StepArgs& a, int variant, hipStream_t s) {
   switch (variant) {
-    case 0: launch_improve_b<16, 4>(a, s); break;
-    case 1: launch_improve_b<8, 8>(a, s); break;
-    case 2: launch_improve_b<32, 2>(a, s); break;
-    default: launch_improve_b<4, 16>(a, s); break;
+    case 0: launch_improve_b<16, 1>(a, s); break;
+    case 1: launch_improve_b<8, 2>(a, s); break;
+    case 2: launch_improve_b<4, 4>(a, s); break;
+    default: launch_improve_b<8, 1>(a, s); break;
   }
 }
 

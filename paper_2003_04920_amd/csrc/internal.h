@@ -63,9 +63,16 @@ void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStrea
 void launch_unmark_roots(int32_t m, const int32_t* ids, const int32_t* slot_of, int32_t* parent, hipStream_t s);
 void launch_bfs_init(int32_t P, const int32_t* roots, const int64_t* base, int32_t* order, int32_t* visited,
                      int32_t* pcnt, int32_t* frontier, int32_t* fcount, hipStream_t s);
-void launch_graph_bfs_level(int32_t fsize, const int32_t* frontier, int32_t* next, int32_t* ncount, int32_t* order,
-                            const int32_t* prob, int32_t* pcnt, const int64_t* rp, const int32_t* col,
-                            int32_t* visited, hipStream_t s);
+// One level of the renumbering BFS.  discover lists the newly reached vertices in
+// cand (unordered, *ccount of them) with key = lowest discovering frontier index;
+// order_level groups them by key into next (the next frontier) and appends each
+// problem's part to its range of order.  visited: 0 = unreached, else the tag of
+// the level that reached the vertex.  key starts at INT32_MAX for every vertex.
+void launch_bfs_discover(int32_t fsize, const int32_t* frontier, int32_t tag, const int64_t* rp, const int32_t* col,
+                         int32_t* visited, int32_t* key, int32_t* cand, int32_t* ccount, hipStream_t s);
+void launch_bfs_order_level(int32_t fsize, int32_t m, const int32_t* cand, const int32_t* key, int32_t* hist,
+                            int64_t* off, int32_t* cursor, int32_t* next, const int32_t* prob, int32_t* pstart,
+                            int32_t* pcnt, int32_t* order, void* scan_scratch, hipStream_t s);
 void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,
                              hipStream_t s);
 void launch_permute(const PermuteArgs& a, hipStream_t s);
@@ -135,7 +142,7 @@ struct StepArgs {
   const int64_t* rp;
   const int32_t* col;
   const float* cst;
-  uint32_t* stamp;
+  uint8_t* stamp;            // low byte of the mark epoch per slot
   const int32_t* ext_of;     // caller id of each slot (tie-break key)
   int32_t* parent;
   float* pcost;

@@ -75,28 +75,84 @@ __global__ void k_bfs_init(int32_t P, const int32_t* __restrict__ roots, const i
   frontier[i] = r;
 }
 
-// One breadth-first level over the graph: each newly reached vertex takes the next
-// position of its problem's range in order[] (the queue order is the new storage
-// order) and joins the next frontier.
-__global__ void __launch_bounds__(kThreads) k_graph_bfs_level(int32_t fsize, const int32_t* __restrict__ frontier,
-                                                             int32_t* __restrict__ next, int32_t* __restrict__ ncount,
-                                                             int32_t* __restrict__ order,
-                                                             const int32_t* __restrict__ prob,
-                                                             int32_t* __restrict__ pcnt,
-                                                             const int64_t* __restrict__ rp,
-                                                             const int32_t* __restrict__ col,
-                                                             int32_t* __restrict__ visited) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One breadth-first level, in the order a sequential queue would produce: the
+// vertices a level reaches are grouped by the frontier index of their first
+// discoverer (the lowest frontier index among their neighbours), in frontier order.
+// Children of one parent thus sit together and next to their parent's siblings'
+// children, which keeps a vertex's neighbours in few cache lines of g.
+//
+// discover: every frontier vertex offers its index to each unvisited neighbour
+//           (atomicMin on key); the first offer also lists the neighbour.  A
+//           neighbour reached in this level is tagged `tag` (not 0), so later offers
+//           of the same level still reach the minimum.
+__global__ void __launch_bounds__(kThreads) k_bfs_discover(int32_t fsize, const int32_t* __restrict__ frontier,
+                                                          int32_t tag, const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          int32_t* __restrict__ visited, int32_t* __restrict__ key,
+                                                          int32_t* __restrict__ cand, int32_t* __restrict__ ccount) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= fsize) return;
   const int32_t u = frontier[t];
-  int32_t* cnt = &pcnt[prob ? prob[u] : 0];
   for (int64_t j = rp[u]; j < rp[u + 1]; ++j) {
     const int32_t w = col[j];
-    if (visited[w] == 0 && atomicExch(&visited[w], 1) == 0) {
-      order[atomicAdd(cnt, 1)] = w;
-      next[atomicAdd(ncount, 1)] = w;
-    }
+    const int32_t st = visited[w];
+    if (st != 0 && st != tag) continue;
+    atomicMin(&key[w], (int32_t)t);
+    if (st == 0 && atomicCAS(&visited[w], 0, tag) == 0) cand[atomicAdd(ccount, 1)] = w;
   }
+}
+
+// hist[key]++ over the reached vertices.
+__global__ void __launch_bounds__(kThreads) k_bfs_hist(int32_t m, const int32_t* __restrict__ cand,
+                                                      const int32_t* __restrict__ key, int32_t* __restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) atomicAdd(&hist[key[cand[i]]], 1);
+}
+
+// next[off[key] + k]: the reached vertices grouped by discoverer (the order inside a
+// group is arbitrary).
+__global__ void __launch_bounds__(kThreads) k_bfs_scatter(int32_t m, const int32_t* __restrict__ cand,
+                                                         const int32_t* __restrict__ key,
+                                                         const int64_t* __restrict__ off,
+                                                         int32_t* __restrict__ cursor, int32_t* __restrict__ next) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t w = cand[i], t = key[w];
+  next[off[t] + atomicAdd(&cursor[t], 1)] = w;
+}
+
+// The level is grouped by problem in problem order (frontiers are); pstart[p] = the
+// first index of problem p in next.
+__global__ void __launch_bounds__(kThreads) k_bfs_starts(int32_t m, const int32_t* __restrict__ next,
+                                                        const int32_t* __restrict__ prob,
+                                                        int32_t* __restrict__ pstart) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t p = prob ? prob[next[i]] : 0;
+  if (i == 0 || (prob ? prob[next[i - 1]] : 0) != p) pstart[p] = (int32_t)i;
+}
+
+// order positions: problem p's part of the level follows its earlier levels.
+__global__ void __launch_bounds__(kThreads) k_bfs_place(int32_t m, const int32_t* __restrict__ next,
+                                                       const int32_t* __restrict__ prob,
+                                                       const int32_t* __restrict__ pstart,
+                                                       const int32_t* __restrict__ pcnt, int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t w = next[i];
+  const int32_t p = prob ? prob[w] : 0;
+  order[pcnt[p] + ((int32_t)i - pstart[p])] = w;
+}
+
+// pcnt[p] += size of problem p's part (written by the part's last element).
+__global__ void __launch_bounds__(kThreads) k_bfs_advance(int32_t m, const int32_t* __restrict__ next,
+                                                         const int32_t* __restrict__ prob,
+                                                         const int32_t* __restrict__ pstart,
+                                                         int32_t* __restrict__ pcnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t p = prob ? prob[next[i]] : 0;
+  if (i == m - 1 || (prob ? prob[next[i + 1]] : 0) != p) pcnt[p] += (int32_t)i - pstart[p] + 1;
 }
 
 // Vertices the BFS did not reach follow in their problem's range.
@@ -118,7 +174,13 @@ __global__ void __launch_bounds__(kThreads) k_invert(int32_t n, const int32_t* _
   deg[k] = (int32_t)(rp[o + 1] - rp[o]);
 }
 
-// Row k of the new adjacency is old row order[k] with its neighbours renamed.
+// Row k of the new adjacency is old row order[k] with its neighbours renamed and
+// sorted by their new slot (ties, i.e. parallel edges, keep their order), so the
+// entries that Improve reads together gather g from nearby slots.  One wave per row:
+// the row's keys go to LDS and every entry moves to its rank.  Rows longer than
+// kSortCap keep their order.
+constexpr int kSortCap = 512;
+
 __global__ void __launch_bounds__(kThreads) k_permute_rows(int32_t n, const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ newslot,
                                                           const int64_t* __restrict__ rp,
@@ -126,14 +188,34 @@ __global__ void __launch_bounds__(kThreads) k_permute_rows(int32_t n, const int3
                                                           const float* __restrict__ cst,
                                                           const int64_t* __restrict__ rp_new,
                                                           int32_t* __restrict__ col_new, float* __restrict__ cst_new) {
-  const int lane = threadIdx.x & (kWave - 1);
+  __shared__ int32_t skey[kThreads / kWave][kSortCap];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   if (k >= n) return;
   const int32_t o = order[k];
   const int64_t a = rp[o], b = rp[o + 1], dst = rp_new[k];
-  for (int64_t j = a + lane; j < b; j += kWave) {
-    col_new[dst + (j - a)] = newslot[col[j]];
-    cst_new[dst + (j - a)] = cst[j];
+  const int64_t len = b - a;
+  if (len > kSortCap) {
+    for (int64_t j = a + lane; j < b; j += kWave) {
+      col_new[dst + (j - a)] = newslot[col[j]];
+      cst_new[dst + (j - a)] = cst[j];
+    }
+    return;
+  }
+  const int m = (int)len;
+  for (int j = lane; j < m; j += kWave) skey[w][j] = newslot[col[a + j]];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int j = lane; j < m; j += kWave) {
+    const int32_t key = skey[w][j];
+    int rank = 0;
+    for (int i = 0; i < m; ++i) {
+      const int32_t ki = skey[w][i];
+      rank += (ki < key || (ki == key && i < j)) ? 1 : 0;
+    }
+    col_new[dst + rank] = key;
+    cst_new[dst + rank] = cst[a + j];
   }
 }
 
@@ -227,12 +309,25 @@ void launch_bfs_init(int32_t P, const int32_t* roots, const int64_t* base, int32
                      frontier, fcount);
 }
 
-void launch_graph_bfs_level(int32_t fsize, const int32_t* frontier, int32_t* next, int32_t* ncount, int32_t* order,
-                            const int32_t* prob, int32_t* pcnt, const int64_t* rp, const int32_t* col,
-                            int32_t* visited, hipStream_t s) {
+void launch_bfs_discover(int32_t fsize, const int32_t* frontier, int32_t tag, const int64_t* rp, const int32_t* col,
+                         int32_t* visited, int32_t* key, int32_t* cand, int32_t* ccount, hipStream_t s) {
   if (fsize > 0)
-    hipLaunchKernelGGL(k_graph_bfs_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, next,
-                       ncount, order, prob, pcnt, rp, col, visited);
+    hipLaunchKernelGGL(k_bfs_discover, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, tag, rp, col,
+                       visited, key, cand, ccount);
+}
+
+void launch_bfs_order_level(int32_t fsize, int32_t m, const int32_t* cand, const int32_t* key, int32_t* hist,
+                            int64_t* off, int32_t* cursor, int32_t* next, const int32_t* prob, int32_t* pstart,
+                            int32_t* pcnt, int32_t* order, void* scan_scratch, hipStream_t s) {
+  if (m <= 0) return;
+  hipMemsetAsync(hist, 0, sizeof(int32_t) * (size_t)fsize, s);
+  hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)fsize, s);
+  hipLaunchKernelGGL(k_bfs_hist, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, cand, key, hist);
+  scan_i32_to_i64(hist, fsize, off, scan_scratch, s);
+  hipLaunchKernelGGL(k_bfs_scatter, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, cand, key, off, cursor, next);
+  hipLaunchKernelGGL(k_bfs_starts, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart);
+  hipLaunchKernelGGL(k_bfs_place, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart, pcnt, order);
+  hipLaunchKernelGGL(k_bfs_advance, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart, pcnt);
 }
 
 void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,
