@@ -101,6 +101,7 @@ struct pirrt_graph {
   int32_t* lvl = nullptr;
   // promising / domain marks and Evaluate stamps {epoch, g bits}
   uint8_t* stamp = nullptr;
+  int32_t* dlist = nullptr;  // compacted Improve domain
   unsigned long long* word = nullptr;
   bool eval_levels = false;   // level-synchronous Evaluate instead of the walk
   int walk_parts = 1;         // walk launches over consecutive slot ranges
@@ -162,7 +163,7 @@ struct pirrt_graph {
   int32_t last_iterations = 0;  // iterations of the previous Replan (loop planning)
   // tuning
   int32_t mid_hint = 64;
-  int row_variant = 1;
+  int row_variant = 2;
   bool poisoned = false;
   std::string err;
 };
@@ -247,6 +248,7 @@ void free_vertex_arrays(pirrt_graph* G) {
   dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
   dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf); dfree(G->ext_of); dfree(G->slot_of);
   dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word); dfree(G->prob);
+  dfree(G->dlist);
 }
 
 void forget_vertex_arrays(pirrt_graph* T) {
@@ -255,6 +257,7 @@ void forget_vertex_arrays(pirrt_graph* T) {
   T->parent = T->child_cnt = T->child_ptr = T->child = T->fr0 = T->fr1 = T->lvl = nullptr;
   T->add = T->deg = T->pending = T->ext_of = T->slot_of = T->parent2 = T->ext2 = T->prob = nullptr;
   T->stamp = nullptr;
+  T->dlist = nullptr;
   T->word = nullptr;
 }
 
@@ -272,7 +275,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(&T.lvl, cap + kMaxMidLaunches + 8) && dalloc(&T.stamp, cap) && dalloc(&T.add, cap) &&
             dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap) && dalloc(&T.ext_of, cap) &&
             dalloc(&T.slot_of, cap) && dalloc(&T.g2, cap) && dalloc(&T.parent2, cap) && dalloc(&T.pcost2, cap) &&
-            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap);
+            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap) && dalloc(&T.dlist, cap);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -298,7 +301,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   G->child_cnt = T.child_cnt; G->child_ptr = T.child_ptr; G->child = T.child; G->fr0 = T.fr0; G->fr1 = T.fr1;
   G->lvl = T.lvl; G->stamp = T.stamp; G->add = T.add; G->deg = T.deg; G->pending = T.pending; G->hbuf = T.hbuf;
   G->ext_of = T.ext_of; G->slot_of = T.slot_of; G->g2 = T.g2; G->parent2 = T.parent2; G->pcost2 = T.pcost2;
-  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob;
+  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob; G->dlist = T.dlist;
   forget_vertex_arrays(&T);
   G->vcap = cap;
   drop_loops(G);
@@ -721,10 +724,11 @@ void enqueue_evaluate(pirrt_graph* G, LoopArgs& L, hipStream_t s) {
 }
 
 // One iteration of Alg. 2 for every active problem.
+// (The thresholds of an iteration come from the after-eval step before it.)
 void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) {
-  launch_thresholds(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, s);
   if (timing) (void)hipEventRecord(G->ev[2], s);
   launch_mark(L.sa, G->row_variant, s);
+  launch_domain_list(L.sa, s);
   if (timing) (void)hipEventRecord(G->ev[3], s);
   launch_improve(L.sa, G->row_variant, s);
   if (timing) (void)hipEventRecord(G->ev[4], s);
@@ -732,7 +736,7 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   if (timing) (void)hipEventRecord(G->ev[0], s);
   enqueue_evaluate(G, L, s);
   if (timing) (void)hipEventRecord(G->ev[1], s);
-  launch_after_eval(L.P, G->ps, G->ctl, s);
+  launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
@@ -832,6 +836,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.parent = G->parent;
   sa.pcost = G->pcost;
   sa.ctr = G->ctr;
+  sa.dlist = G->dlist;
   WalkArgs& wa = L.wa;
   wa.n = n;
   wa.prob = problem_map(G);
@@ -871,7 +876,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
   enqueue_evaluate(G, L, s);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
-  launch_after_eval(P, G->ps, G->ctl, s);
+  launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
@@ -904,8 +909,11 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
         }
       }
       if (G->trace)
-        fprintf(stderr, "pirrt iter %d: problem 0 iterations %d edges %llu changed %llu; walk hops %llu\n", it + 1,
-                G->hps[0].iterations, (unsigned long long)G->hps[0].edges,
+        fprintf(stderr,
+                "pirrt iter %d: problem 0 iterations %d edges %llu sum_P %llu sum_D %llu changed %llu; walk hops "
+                "%llu\n",
+                it + 1, G->hps[0].iterations, (unsigned long long)G->hps[0].edges,
+                (unsigned long long)G->hps[0].sum_P, (unsigned long long)G->hps[0].sum_D,
                 (unsigned long long)G->hps[0].changed_total, (unsigned long long)G->host->hops);
       if (!G->host->ctl.any_active) break;
       if (done_iters > cap_iters + 1) return fail_device(G, hipErrorUnknown, "Replan loop did not stop");

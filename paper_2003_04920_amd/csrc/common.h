@@ -43,6 +43,8 @@ struct LoopCtl {
   uint32_t eval_epoch;  // stamp of the current Evaluate
   int32_t any_active;   // some problem runs this iteration (set by the thresholds)
   int32_t any_eval;     // some problem needs an Evaluate after this iteration
+  int32_t ndomain;      // entries of the compacted Improve domain of this iteration
+  int32_t pad[3];
 };
 
 // Bookkeeping of one Evaluate (breadth-first walk of the policy tree).

@@ -1,7 +1,7 @@
 // Device side of the Replan loop (Alg. 2) for one or many problems: per-problem
 // thresholds, the per-iteration bookkeeping of the convergence test, and the root
 // marks.  The loop itself never waits on the host: each iteration is
-//   thresholds -> mark -> improve -> finish -> evaluate
+//   mark -> domain list -> improve -> finish -> evaluate -> after-eval (thresholds)
 // and a problem whose Improve switched no parent stops (its threshold becomes
 // -inf, so the later kernels skip it), exactly when the serial loop would break.
 #include "internal.h"
@@ -38,17 +38,6 @@ __global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, in
     ctl->any_active = 1;
     ctl->any_eval = 1;
   }
-}
-
-// G of every problem for this iteration (Alg. 2's promising test against
-// g(x_goal)); -inf for a problem that has stopped.
-__global__ void k_thresholds(int32_t P, ProblemState* __restrict__ ps, const float* __restrict__ g, int prune,
-                             LoopCtl* __restrict__ ctl) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) ctl->any_eval = 0;
-  if (i >= P) return;
-  ProblemState& s = ps[i];
-  s.thr = s.active ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
 }
 
 // One workgroup of kCounterSlots threads per problem: sums and clears the counter
@@ -96,17 +85,25 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
   if (i == 0 && t == 0) ctl->epoch = next_mark_epoch(ctl->epoch);
 }
 
-// Runs after the evaluate of an iteration: a new evaluate epoch, and whether any
-// problem still iterates.
-__global__ void k_after_eval(int32_t P, const ProblemState* __restrict__ ps, LoopCtl* __restrict__ ctl) {
+// Runs after the Evaluate of an iteration (and after the first Evaluate of a
+// Replan): a new evaluate epoch, whether any problem still iterates, and each
+// problem's promising threshold G for the next iteration (Alg. 2's test against
+// g(x_goal), +inf without pruning, -inf for a problem that has stopped).
+__global__ void k_after_eval(int32_t P, ProblemState* __restrict__ ps, const float* __restrict__ g, int prune,
+                             LoopCtl* __restrict__ ctl) {
   __shared__ int any;
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
-  for (int32_t i = threadIdx.x; i < P; i += blockDim.x)
-    if (ps[i].active) any = 1;
+  for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
+    ProblemState& s = ps[i];
+    if (s.active) any = 1;
+    s.thr = s.active ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     ctl->any_active = any;
+    ctl->any_eval = 0;
+    ctl->ndomain = 0;
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
   }
 }
@@ -120,16 +117,12 @@ void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, floa
                      ctl);
 }
 
-void launch_thresholds(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_thresholds, dim3((P + 255) / 256), dim3(256), 0, s, P, ps, g, prune, ctl);
-}
-
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(P), dim3(kCounterSlots), 0, s, P, ps, ctr, ctl);
 }
 
-void launch_after_eval(int32_t P, const ProblemState* ps, LoopCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(256), 0, s, P, ps, ctl);
+void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(256), 0, s, P, ps, g, prune, ctl);
 }
 
 }  // namespace pirrt

@@ -18,9 +18,9 @@
 // minimum is a DPP butterfly.
 //
 // Stamps are one byte: the low byte of the mark epoch (never 0).  The host clears
-// them before every Replan, and Improve clears every stamp it reads in the
-// iteration after which the low byte would wrap, so a stamp never survives 255
-// epochs.
+// them before every Replan, and the domain compaction clears every stamp it reads in
+// the iteration after which the low byte would wrap, so a stamp never survives 255
+// epochs.  Improve runs over the compacted domain list, not over all slots.
 //
 // kBatched: several problems share the arrays; prob[slot] names the problem of a
 // slot.  Without it every slot belongs to problem 0.
@@ -132,29 +132,94 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
   flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0);
 }
 
+// Compacted Improve domain: the slots stamped with this iteration's epoch.  Each
+// thread tests kListPer consecutive stamps (one 16-byte load), a workgroup scan
+// places them, and one atomic per workgroup reserves the workgroup's chunk
+// (ascending inside the chunk).  When the next mark epoch wraps its low byte, every
+// stamp is cleared here after being read.
+constexpr int kListPer = 16;
+
+__global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __restrict__ ctl,
+                                                         uint8_t* __restrict__ stamp, int32_t* __restrict__ dlist) {
+  if (ctl->any_active == 0) return;  // every problem has converged
+  const uint32_t epoch = ctl->epoch;
+  const uint8_t ep = (uint8_t)epoch;
+  const bool wrap = (epoch & 0xffu) == 0xffu;
+  const int64_t v0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kListPer;
+  uint32_t mask = 0;
+  if (v0 + kListPer <= n) {
+    uint4* p4 = reinterpret_cast<uint4*>(stamp + v0);
+    const uint4 w = *p4;
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (((words[q] >> (8 * b)) & 0xffu) == ep) mask |= 1u << (4 * q + b);
+    if (wrap && (w.x | w.y | w.z | w.w) != 0u) *p4 = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    for (int i = 0; i < kListPer; ++i) {
+      if (v0 + i >= n) break;
+      const uint8_t sv = stamp[v0 + i];
+      if (sv == ep) mask |= 1u << i;
+      if (wrap && sv != 0) stamp[v0 + i] = 0;
+    }
+  }
+  // workgroup exclusive scan of the per-thread counts
+  __shared__ int wsum[kThreads / kWave];
+  __shared__ int base;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int c = __popc(mask);
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      const int x = wsum[w];
+      wsum[w] = t;
+      t += x;
+    }
+    base = t ? atomicAdd(&ctl->ndomain, t) : 0;
+  }
+  __syncthreads();
+  int pos = base + wsum[wid] + incl - c;
+  while (mask) {
+    const int i = __ffs(mask) - 1;
+    mask &= mask - 1;
+    dlist[pos++] = (int32_t)(v0 + i);
+  }
+}
+
+// Improve over the compacted domain: group i takes entry i of dlist; workgroups past
+// the domain's end leave at once.
 template <int GW, int Q, typename Idx, bool kBatched>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* __restrict__ prob,
                                                      const ProblemState* __restrict__ ps,
                                                      const LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                     const float* __restrict__ cst, uint8_t* __restrict__ stamp,
+                                                     const float* __restrict__ cst, const int32_t* __restrict__ dlist,
                                                      const int32_t* __restrict__ ext_of,
                                                      int32_t* __restrict__ parent, float* __restrict__ pcost,
                                                      IterCounters* __restrict__ ctr) {
   if (ctl->any_active == 0) return;  // every problem has converged
-  const uint32_t epoch = ctl->epoch;
-  const uint8_t ep = (uint8_t)epoch;
+  const int64_t cnt = ctl->ndomain;
+  const int64_t first = (int64_t)blockIdx.x * (kThreads / GW);
+  if (first >= cnt) return;  // the whole workgroup is past the domain
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane / GW, gl = threadIdx.x % GW;
-  const int64_t v = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
-  const int32_t x = v < n ? (int32_t)v : n - 1;
+  const int64_t gi = first + threadIdx.x / GW;
+  const bool valid = gi < cnt;
+  const int32_t x = dlist[valid ? gi : cnt - 1];
   const int p = kBatched ? prob[x] : 0;
-  const uint8_t sx = stamp[x];
   const float gx = g[x];
   const Idx ra = (Idx)rp[x], rb = (Idx)rp[x + 1];
-  const bool in = v < n && sx == ep && x != ps[p].root;
-  // the next mark epoch wraps its low byte: leave every stamp cleared
-  if ((epoch & 0xffu) == 0xffu && v < n && gl == 0 && sx != 0) stamp[x] = 0;
+  const bool in = valid && x != ps[p].root;
   const Idx a = in ? ra : 0, b = in ? rb : 0;
   const int4* col4 = reinterpret_cast<const int4*>(col);
   const float4* cst4 = reinterpret_cast<const float4*>(cst);
@@ -226,7 +291,7 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
     pcost[x] = __uint_as_float(wc);
     changed = 1;
   }
-  flush_counters(ctr, p, v < n && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
+  flush_counters(ctr, p, valid && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
 }
 
 inline dim3 grid_for(int64_t n, int gw) {
@@ -250,10 +315,10 @@ void launch_improve_t(const StepArgs& a, hipStream_t s) {
   const dim3 grid = grid_for(a.n, GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
     hipLaunchKernelGGL((k_improve<GW, U, uint32_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
-                       a.rp, a.col, a.cst, a.stamp, a.ext_of, a.parent, a.pcost, a.ctr);
+                       a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);
   else
     hipLaunchKernelGGL((k_improve<GW, U, int64_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
-                       a.rp, a.col, a.cst, a.stamp, a.ext_of, a.parent, a.pcost, a.ctr);
+                       a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);
 }
 
 template <int GW, int U>
@@ -267,6 +332,12 @@ void launch_improve_b(const StepArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+void launch_domain_list(const StepArgs& a, hipStream_t s) {
+  const int64_t per_block = (int64_t)kThreads * kListPer;
+  hipLaunchKernelGGL(k_domain_list, dim3((unsigned)((a.n + per_block - 1) / per_block)), dim3(kThreads), 0, s, a.n,
+                     a.ctl, a.stamp, a.dlist);
+}
 
 // Variants: lanes per row x quads per lane in flight (GW x Q x 4 entries per pass).
 void launch_mark(const StepArgs& a, int variant, hipStream_t s) {

@@ -126,9 +126,8 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 // ---- driver.hip ----
 void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
                         LoopCtl* ctl, hipStream_t s);
-void launch_thresholds(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s);
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s);
-void launch_after_eval(int32_t P, const ProblemState* ps, LoopCtl* ctl, hipStream_t s);
+void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
@@ -136,7 +135,7 @@ struct StepArgs {
   int64_t nnz;               // adjacency entries (selects 32-bit offsets when they fit)
   const int32_t* prob;       // problem of each slot, or NULL for a single problem
   const ProblemState* ps;    // thresholds and roots
-  const LoopCtl* ctl;        // epoch, any_active
+  LoopCtl* ctl;              // epoch, any_active, ndomain
   const float* g;
   const float* h;            // nullable
   const int64_t* rp;
@@ -147,9 +146,13 @@ struct StepArgs {
   int32_t* parent;
   float* pcost;
   IterCounters* ctr;         // kCounterSlots copies per problem
+  int32_t* dlist;            // compacted Improve domain (n entries of room)
 };
 constexpr int kRowVariants = 4;
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);
+// Compacts the stamped slots into dlist / ctl->ndomain (and clears every stamp when
+// the next mark epoch wraps its low byte).
+void launch_domain_list(const StepArgs& a, hipStream_t s);
 void launch_improve(const StepArgs& a, int variant, hipStream_t s);
 
 }  // namespace pirrt
