@@ -102,6 +102,7 @@ struct pirrt_graph {
   // promising / domain marks and Evaluate stamps {epoch, g bits}
   uint8_t* stamp = nullptr;
   int32_t* dlist = nullptr;  // compacted Improve domain
+  int32_t* tiles = nullptr;  // batches: active tile list
   unsigned long long* word = nullptr;
   bool eval_levels = false;   // level-synchronous Evaluate instead of the walk
   int walk_parts = 1;         // walk launches over consecutive slot ranges
@@ -248,7 +249,7 @@ void free_vertex_arrays(pirrt_graph* G) {
   dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
   dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf); dfree(G->ext_of); dfree(G->slot_of);
   dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word); dfree(G->prob);
-  dfree(G->dlist);
+  dfree(G->dlist); dfree(G->tiles);
 }
 
 void forget_vertex_arrays(pirrt_graph* T) {
@@ -258,6 +259,7 @@ void forget_vertex_arrays(pirrt_graph* T) {
   T->add = T->deg = T->pending = T->ext_of = T->slot_of = T->parent2 = T->ext2 = T->prob = nullptr;
   T->stamp = nullptr;
   T->dlist = nullptr;
+  T->tiles = nullptr;
   T->word = nullptr;
 }
 
@@ -275,7 +277,8 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(&T.lvl, cap + kMaxMidLaunches + 8) && dalloc(&T.stamp, cap) && dalloc(&T.add, cap) &&
             dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap) && dalloc(&T.ext_of, cap) &&
             dalloc(&T.slot_of, cap) && dalloc(&T.g2, cap) && dalloc(&T.parent2, cap) && dalloc(&T.pcost2, cap) &&
-            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap) && dalloc(&T.dlist, cap);
+            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap) && dalloc(&T.dlist, cap) &&
+            dalloc(&T.tiles, cap / kTileSlots + 2);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -301,7 +304,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   G->child_cnt = T.child_cnt; G->child_ptr = T.child_ptr; G->child = T.child; G->fr0 = T.fr0; G->fr1 = T.fr1;
   G->lvl = T.lvl; G->stamp = T.stamp; G->add = T.add; G->deg = T.deg; G->pending = T.pending; G->hbuf = T.hbuf;
   G->ext_of = T.ext_of; G->slot_of = T.slot_of; G->g2 = T.g2; G->parent2 = T.parent2; G->pcost2 = T.pcost2;
-  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob; G->dlist = T.dlist;
+  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob; G->dlist = T.dlist; G->tiles = T.tiles;
   forget_vertex_arrays(&T);
   G->vcap = cap;
   drop_loops(G);
@@ -736,7 +739,7 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   if (timing) (void)hipEventRecord(G->ev[0], s);
   enqueue_evaluate(G, L, s);
   if (timing) (void)hipEventRecord(G->ev[1], s);
-  launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, s);
+  launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), G->tiles, s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
@@ -837,6 +840,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.pcost = G->pcost;
   sa.ctr = G->ctr;
   sa.dlist = G->dlist;
+  sa.tiles = G->tiles;
   WalkArgs& wa = L.wa;
   wa.n = n;
   wa.prob = problem_map(G);
@@ -849,6 +853,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.hops = G->trace ? G->dhops : nullptr;
   wa.parts = G->walk_parts;
   wa.coherent = G->walk_coherent;
+  wa.tiles = G->tiles;
   EvalArgs& ea = L.ea;
   ea.n = n;
   ea.root = root_slots[0];
@@ -876,7 +881,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
   enqueue_evaluate(G, L, s);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
-  launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, s);
+  launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), G->tiles, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));

@@ -44,8 +44,33 @@ struct LoopCtl {
   int32_t any_active;   // some problem runs this iteration (set by the thresholds)
   int32_t any_eval;     // some problem needs an Evaluate after this iteration
   int32_t ndomain;      // entries of the compacted Improve domain of this iteration
-  int32_t pad[3];
+  int32_t ntiles;       // batches: entries of the active tile list; -1 = every tile
+  int32_t pad[2];
 };
+
+// Batches run their per-slot kernels over tiles of kTileSlots consecutive slots;
+// after each Evaluate the tiles that overlap a problem still iterating are listed
+// (LoopCtl::ntiles, -1 = all tiles in slot order).
+constexpr int kTileSlots = 4096;
+
+// Work units of a batch: every active tile is cut into kTileSlots / per_unit units
+// of per_unit consecutive slots.  Kernels loop over the units with a grid stride.
+__device__ __forceinline__ int64_t tile_units(const LoopCtl* ctl, int32_t n, int per_unit) {
+  const int32_t nt = ctl->ntiles;
+  const int64_t T = nt < 0 ? ((int64_t)n + kTileSlots - 1) / kTileSlots : nt;
+  return T * (kTileSlots / per_unit);
+}
+
+__device__ __forceinline__ int64_t tile_unit_slot(const LoopCtl* ctl, const int32_t* tiles, int per_unit,
+                                                  int64_t w) {
+  const int64_t upt = kTileSlots / per_unit;
+  const int64_t ti = w / upt;
+  const int64_t t = ctl->ntiles < 0 ? ti : tiles[ti];
+  return t * kTileSlots + (w % upt) * per_unit;
+}
+
+// Workgroups of a batch kernel's grid-stride launch.
+constexpr int kBatchBlocks = 2048;
 
 // Bookkeeping of one Evaluate (breadth-first walk of the policy tree).
 struct EvalInfo {

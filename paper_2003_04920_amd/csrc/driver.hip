@@ -37,6 +37,7 @@ __global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, in
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
     ctl->any_active = 1;
     ctl->any_eval = 1;
+    ctl->ntiles = -1;
   }
 }
 
@@ -89,21 +90,38 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
 // Replan): a new evaluate epoch, whether any problem still iterates, and each
 // problem's promising threshold G for the next iteration (Alg. 2's test against
 // g(x_goal), +inf without pruning, -inf for a problem that has stopped).
+// In a batch it also lists the tiles that overlap a problem still iterating (a tile
+// spans at most a few problems: each holds thousands of slots).
 __global__ void k_after_eval(int32_t P, ProblemState* __restrict__ ps, const float* __restrict__ g, int prune,
-                             LoopCtl* __restrict__ ctl) {
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
+                             LoopCtl* __restrict__ ctl, int32_t n, const int32_t* __restrict__ prob,
+                             int32_t* __restrict__ tiles) {
+  __shared__ int any, count;
+  if (threadIdx.x == 0) {
+    any = 0;
+    count = 0;
+  }
   __syncthreads();
   for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
     ProblemState& s = ps[i];
     if (s.active) any = 1;
     s.thr = s.active ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
   }
+  if (prob) {
+    const int32_t T = (n + kTileSlots - 1) / kTileSlots;
+    for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
+      const int64_t s0 = (int64_t)t * kTileSlots;
+      const int64_t s1 = (s0 + kTileSlots < n ? s0 + kTileSlots : n) - 1;
+      bool act = false;
+      for (int32_t p = prob[s0]; p <= prob[s1]; ++p) act = act || ps[p].active != 0;
+      if (act) tiles[atomicAdd(&count, 1)] = t;
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     ctl->any_active = any;
     ctl->any_eval = 0;
     ctl->ndomain = 0;
+    ctl->ntiles = prob ? count : -1;
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
   }
 }
@@ -121,8 +139,9 @@ void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl,
   hipLaunchKernelGGL(k_finish, dim3(P), dim3(kCounterSlots), 0, s, P, ps, ctr, ctl);
 }
 
-void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(256), 0, s, P, ps, g, prune, ctl);
+void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
+                       const int32_t* prob, int32_t* tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(1024), 0, s, P, ps, g, prune, ctl, n, prob, tiles);
 }
 
 }  // namespace pirrt

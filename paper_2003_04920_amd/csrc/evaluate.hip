@@ -230,15 +230,20 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
                                                            const int32_t* __restrict__ parent,
                                                            const float* __restrict__ pcost, float* __restrict__ g,
                                                            unsigned long long* __restrict__ word,
-                                                           unsigned long long* __restrict__ hops) {
+                                                           unsigned long long* __restrict__ hops,
+                                                           const int32_t* __restrict__ tiles) {
   __shared__ int32_t ring_v[kRing][kWalkThreads];
   __shared__ float ring_c[kRing][kWalkThreads];
   if (ctl->any_eval == 0) return;  // no problem changed in this iteration
-  const int64_t v = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= hi) return;
-  if (!ps[kBatched ? prob[v] : 0].needs_eval) return;
   const unsigned long long tag = (unsigned long long)ctl->eval_epoch << 32;
   unsigned long long walked = 0;
+  // a batch loops over the units of its active tiles; a single graph has one unit
+  const int64_t units = kBatched ? tile_units(ctl, n, kWalkThreads) : 1;
+  for (int64_t wu = kBatched ? blockIdx.x : 0; wu < units; wu += kBatched ? gridDim.x : 1) {
+  const int64_t v = (kBatched ? tile_unit_slot(ctl, tiles, kWalkThreads, wu) : lo + (int64_t)blockIdx.x * blockDim.x) +
+                    threadIdx.x;
+  if (v >= hi) continue;
+  if (!ps[kBatched ? prob[v] : 0].needs_eval) continue;
   for (;;) {
     int32_t u = (int32_t)v;
     int64_t k = 0;
@@ -278,22 +283,26 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
     }
     if (stop == 0) break;
   }
+  }
   if (kCountHops) atomicAdd(hops, walked);
 }
 
 }  // namespace
 
 void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
-  const int parts = a.parts < 1 ? 1 : a.parts;
+  const int parts = a.prob ? 1 : (a.parts < 1 ? 1 : a.parts);
   const int64_t per = ((int64_t)a.n + parts - 1) / parts;
   for (int k = 0; k < parts; ++k) {
     const int32_t lo = (int32_t)(k * per < a.n ? k * per : a.n);
     const int32_t hi = (int32_t)((k + 1) * per < a.n ? (k + 1) * per : a.n);
     if (hi <= lo && k > 0) break;
-    const dim3 grid(blocks_for(hi - lo, kWalkThreads));
+    // batches launch whole tiles (the live ones are picked on the device)
+    const int64_t units = (((int64_t)a.n + kTileSlots - 1) / kTileSlots) * (kTileSlots / kWalkThreads);
+    const dim3 grid(a.prob ? (unsigned)(units < kBatchBlocks ? (units > 0 ? units : 1) : kBatchBlocks)
+                           : blocks_for(hi - lo, kWalkThreads));
 #define PIRRT_WALK(H, C, B)                                                                                \
   hipLaunchKernelGGL((k_eval_walk<H, C, B>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, a.ctl, \
-                     a.parent, a.pcost, a.g, a.word, a.hops)
+                     a.parent, a.pcost, a.g, a.word, a.hops, a.tiles)
     const bool b = a.prob != nullptr;
     if (a.hops) {
       if (a.coherent) { if (b) PIRRT_WALK(true, true, true); else PIRRT_WALK(true, true, false); }

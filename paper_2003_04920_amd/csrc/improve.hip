@@ -39,6 +39,7 @@ __device__ __forceinline__ void flush_counters(IterCounters* ctr, int p, bool le
                                                unsigned long long edges, int changed) {
   __shared__ int block_p, mixed;
   __shared__ unsigned long long red[4];
+  __syncthreads();  // a previous call of this workgroup may still read red
   if (threadIdx.x == 0) {
     block_p = p;
     mixed = 0;
@@ -99,11 +100,16 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
                                                   const LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                   const float* __restrict__ h, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, uint8_t* __restrict__ stamp,
-                                                  IterCounters* __restrict__ ctr) {
+                                                  IterCounters* __restrict__ ctr, const int32_t* __restrict__ tiles) {
   if (ctl->any_active == 0) return;  // every problem has converged
   const uint8_t ep = (uint8_t)ctl->epoch;
   const int gl = threadIdx.x % GW;
-  const int64_t v = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
+  // a batch loops over the units of its active tiles; a single graph has one unit
+  const int64_t units = kBatched ? tile_units(ctl, n, kThreads / GW) : 1;
+  for (int64_t w = kBatched ? blockIdx.x : 0; w < units; w += kBatched ? gridDim.x : 1) {
+  const int64_t vbase =
+      kBatched ? tile_unit_slot(ctl, tiles, kThreads / GW, w) : (int64_t)blockIdx.x * (kThreads / GW);
+  const int64_t v = vbase + threadIdx.x / GW;
   const int32_t x = v < n ? (int32_t)v : n - 1;
   const int p = kBatched ? prob[x] : 0;
   const float G = ps[p].thr;
@@ -130,6 +136,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
     }
   }
   flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0);
+  }
 }
 
 // Compacted Improve domain: the slots stamped with this iteration's epoch.  Each
@@ -139,13 +146,23 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
 // stamp is cleared here after being read.
 constexpr int kListPer = 16;
 
+// In a batch only the active tiles are scanned, and a slot of a problem that has
+// stopped never enters the list (its stamps may be stale: tiles of stopped problems
+// are not cleared at the wrap).
 __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __restrict__ ctl,
-                                                         uint8_t* __restrict__ stamp, int32_t* __restrict__ dlist) {
+                                                         uint8_t* __restrict__ stamp, int32_t* __restrict__ dlist,
+                                                         const int32_t* __restrict__ prob,
+                                                         const ProblemState* __restrict__ ps,
+                                                         const int32_t* __restrict__ tiles) {
   if (ctl->any_active == 0) return;  // every problem has converged
   const uint32_t epoch = ctl->epoch;
   const uint8_t ep = (uint8_t)epoch;
   const bool wrap = (epoch & 0xffu) == 0xffu;
-  const int64_t v0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kListPer;
+  const int64_t units = prob ? tile_units(ctl, n, kThreads * kListPer) : 1;
+  for (int64_t wu = prob ? blockIdx.x : 0; wu < units; wu += prob ? gridDim.x : 1) {
+  const int64_t bbase =
+      prob ? tile_unit_slot(ctl, tiles, kThreads * kListPer, wu) : (int64_t)blockIdx.x * kThreads * kListPer;
+  const int64_t v0 = bbase + (int64_t)threadIdx.x * kListPer;
   uint32_t mask = 0;
   if (v0 + kListPer <= n) {
     uint4* p4 = reinterpret_cast<uint4*>(stamp + v0);
@@ -165,10 +182,17 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
       if (wrap && sv != 0) stamp[v0 + i] = 0;
     }
   }
+  if (prob) {
+    for (uint32_t m = mask; m; m &= m - 1) {
+      const int i = __ffs(m) - 1;
+      if (!ps[prob[v0 + i]].active) mask &= ~(1u << i);
+    }
+  }
   // workgroup exclusive scan of the per-thread counts
   __shared__ int wsum[kThreads / kWave];
   __shared__ int base;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();  // the previous unit's readers of wsum / base are done
   const int c = __popc(mask);
   int incl = c;
 #pragma unroll
@@ -194,6 +218,7 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
     mask &= mask - 1;
     dlist[pos++] = (int32_t)(v0 + i);
   }
+  }
 }
 
 // Improve over the compacted domain: group i takes entry i of dlist; workgroups past
@@ -209,8 +234,9 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
                                                      IterCounters* __restrict__ ctr) {
   if (ctl->any_active == 0) return;  // every problem has converged
   const int64_t cnt = ctl->ndomain;
-  const int64_t first = (int64_t)blockIdx.x * (kThreads / GW);
-  if (first >= cnt) return;  // the whole workgroup is past the domain
+  // a batch strides over the domain with a fixed grid; a single graph's grid covers it
+  const int64_t step = kBatched ? (int64_t)gridDim.x * (kThreads / GW) : cnt;
+  for (int64_t first = (int64_t)blockIdx.x * (kThreads / GW); first < cnt; first += step) {
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane / GW, gl = threadIdx.x % GW;
   const int64_t gi = first + threadIdx.x / GW;
@@ -292,6 +318,7 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
     changed = 1;
   }
   flush_counters(ctr, p, valid && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
+  }
 }
 
 inline dim3 grid_for(int64_t n, int gw) {
@@ -299,20 +326,27 @@ inline dim3 grid_for(int64_t n, int gw) {
   return dim3((unsigned)(b > 0 ? b : 1));
 }
 
+// Batches use a fixed grid that strides over the live work.
+inline dim3 batch_grid(int64_t n, int per_block) {
+  const int64_t T = (n + kTileSlots - 1) / kTileSlots;
+  const int64_t units = T * (kTileSlots / per_block);
+  return dim3((unsigned)(units < kBatchBlocks ? (units > 0 ? units : 1) : kBatchBlocks));
+}
+
 template <int GW, int U, bool B>
 void launch_mark_t(const StepArgs& a, hipStream_t s) {
-  const dim3 grid = grid_for(a.n, GW);
+  const dim3 grid = B ? batch_grid(a.n, kThreads / GW) : grid_for(a.n, GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
     hipLaunchKernelGGL((k_mark<GW, U, uint32_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g, a.h,
-                       a.rp, a.col, a.stamp, a.ctr);
+                       a.rp, a.col, a.stamp, a.ctr, a.tiles);
   else
     hipLaunchKernelGGL((k_mark<GW, U, int64_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g, a.h,
-                       a.rp, a.col, a.stamp, a.ctr);
+                       a.rp, a.col, a.stamp, a.ctr, a.tiles);
 }
 
 template <int GW, int U, bool B>
 void launch_improve_t(const StepArgs& a, hipStream_t s) {
-  const dim3 grid = grid_for(a.n, GW);
+  const dim3 grid = B ? batch_grid(a.n, kThreads / GW) : grid_for(a.n, GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
     hipLaunchKernelGGL((k_improve<GW, U, uint32_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
                        a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);
@@ -335,8 +369,10 @@ void launch_improve_b(const StepArgs& a, hipStream_t s) {
 
 void launch_domain_list(const StepArgs& a, hipStream_t s) {
   const int64_t per_block = (int64_t)kThreads * kListPer;
-  hipLaunchKernelGGL(k_domain_list, dim3((unsigned)((a.n + per_block - 1) / per_block)), dim3(kThreads), 0, s, a.n,
-                     a.ctl, a.stamp, a.dlist);
+  static_assert(kThreads * kListPer == kTileSlots, "one domain-list workgroup per tile");
+  const dim3 grid = a.prob ? batch_grid(a.n, (int)per_block) : dim3((unsigned)((a.n + per_block - 1) / per_block));
+  hipLaunchKernelGGL(k_domain_list, grid, dim3(kThreads), 0, s, a.n, a.ctl, a.stamp, a.dlist, a.prob, a.ps,
+                     a.tiles);
 }
 
 // Variants: lanes per row x quads per lane in flight (GW x Q x 4 entries per pass).

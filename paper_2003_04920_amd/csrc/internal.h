@@ -118,7 +118,8 @@ struct WalkArgs {
   float* g;
   unsigned long long* word;  // n {epoch, g bits} stamps
   unsigned long long* hops;  // nullable: total parent links walked
-  int parts;               // launches over consecutive slot ranges
+  int parts;               // launches over consecutive slot ranges (single graphs)
+  const int32_t* tiles;    // batches: active tile list
   bool coherent;           // device-scope stamp accesses
 };
 void launch_eval_walk(const WalkArgs& a, hipStream_t s);
@@ -127,7 +128,10 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
                         LoopCtl* ctl, hipStream_t s);
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s);
-void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, hipStream_t s);
+// prob / tiles: a batch's problem map and the active tile list it rebuilds (NULL
+// for a single graph).
+void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
+                       const int32_t* prob, int32_t* tiles, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
@@ -147,6 +151,7 @@ struct StepArgs {
   float* pcost;
   IterCounters* ctr;         // kCounterSlots copies per problem
   int32_t* dlist;            // compacted Improve domain (n entries of room)
+  const int32_t* tiles;      // batches: active tile list (see LoopCtl::ntiles)
 };
 constexpr int kRowVariants = 4;
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);
