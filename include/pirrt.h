@@ -301,6 +301,50 @@ int pirrt_rrg_heuristic(pirrt_rrg* r, int64_t goal, float* h_out, int mem_kind);
 
 const char* pirrt_rrg_last_error(const pirrt_rrg* r);
 
+/*
+ * Learned sampling proposal (not in the paper: a network that scores candidate
+ * samples by how likely they are to lie near the optimal path; the planner mixes
+ * its picks 50/50 with uniform samples, so Replan stays exact on whatever graph
+ * results).  Network: features (in_dim <= 288 binary32 values per sample, e.g. the
+ * sample's coordinates then the obstacle encoding) -> 256 -> 256 -> 1 logit, ReLU
+ * hidden layers.  Parameters are binary32 masters laid out as one array:
+ *   W1 [288 x 256] row-major (rows >= in_dim stay 0), b1 [256],
+ *   W2 [256 x 256] row-major, b2 [256], w3 [256], b3 [1]
+ * (pirrt_mlp_num_params() floats).  Every product uses bfloat16 (round to nearest
+ * even) copies of the weights and bfloat16 activations with binary32 accumulation:
+ *   X = bf16(features); A1 = bf16(relu(X W1 + b1)); A2 = bf16(relu(A1 W2 + b2));
+ *   logit = A2 bf16(w3) + b3.
+ * Training minimises the mean BCE-with-logits loss with Adam; the backward pass
+ * rounds dZ2 = dz w3^T [Z2 > 0] and dZ1 = dZ2 W2^T [Z1 > 0] to bfloat16 before its
+ * products.  x: float[B * in_dim] row-major; y: float[B] labels in {0, 1}.
+ */
+typedef struct pirrt_mlp pirrt_mlp;
+
+typedef struct {
+  int32_t in_dim;    /* feature width, 1..288 */
+  int32_t max_batch; /* largest B of any call */
+  float lr, beta1, beta2, eps; /* Adam constants (lr > 0, 0 <= beta < 1, eps > 0) */
+  void* hip_stream;  /* hipStream_t; NULL = the null stream */
+  int32_t device;    /* HIP device ordinal; -1 = current */
+} pirrt_mlp_config;
+
+int64_t pirrt_mlp_num_params(void);
+/* Creates a network with all parameters 0 (set them with pirrt_mlp_set_params). */
+int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg);
+int pirrt_mlp_destroy(pirrt_mlp* net);
+/* Replaces the binary32 parameters (finite) and resets the Adam state. */
+int pirrt_mlp_set_params(pirrt_mlp* net, const float* params, int mem_kind);
+int pirrt_mlp_get_params(pirrt_mlp* net, float* params, int mem_kind);
+/* logits: float[B]. */
+int pirrt_mlp_forward(pirrt_mlp* net, int32_t B, const float* x, float* logits, int mem_kind);
+/* Gradient of the mean loss into grads (parameter layout, nullable) and the loss
+   into *loss (host, nullable); parameters unchanged. */
+int pirrt_mlp_gradients(pirrt_mlp* net, int32_t B, const float* x, const float* y, float* grads, float* loss,
+                        int mem_kind);
+/* One Adam step on one batch; *loss (host, nullable) = the batch loss before it. */
+int pirrt_mlp_train_step(pirrt_mlp* net, int32_t B, const float* x, const float* y, float* loss, int mem_kind);
+const char* pirrt_mlp_last_error(const pirrt_mlp* net);
+
 #ifdef __cplusplus
 }
 #endif

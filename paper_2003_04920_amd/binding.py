@@ -32,6 +32,8 @@ EXPORTS = [
     "pirrt_rrg_create", "pirrt_rrg_destroy", "pirrt_rrg_num_points", "pirrt_rrg_add_points", "pirrt_rrg_sample",
     "pirrt_rrg_get_points", "pirrt_rrg_rows", "pirrt_rrg_connect", "pirrt_rrg_connect_problem",
     "pirrt_rrg_heuristic", "pirrt_rrg_last_error",
+    "pirrt_mlp_num_params", "pirrt_mlp_create", "pirrt_mlp_destroy", "pirrt_mlp_set_params", "pirrt_mlp_get_params",
+    "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
 ]
 
 
@@ -43,6 +45,12 @@ class pirrt_config(ctypes.Structure):
 class pirrt_rrg_config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("n_obstacles", ctypes.c_int32), ("kind", ctypes.c_void_p),
                 ("centre", ctypes.c_void_p), ("size", ctypes.c_void_p), ("point_capacity", ctypes.c_int64),
+                ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32)]
+
+
+class pirrt_mlp_config(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32)]
 
 
@@ -116,6 +124,15 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_rrg_connect_problem": (cint, [vp, ctypes.c_double, vp, ctypes.POINTER(i32)]),
         "pirrt_rrg_heuristic": (cint, [vp, i64, vp, cint]),
         "pirrt_rrg_last_error": (ctypes.c_char_p, [vp]),
+        "pirrt_mlp_num_params": (i64, []),
+        "pirrt_mlp_create": (cint, [ctypes.POINTER(vp), ctypes.POINTER(pirrt_mlp_config)]),
+        "pirrt_mlp_destroy": (cint, [vp]),
+        "pirrt_mlp_set_params": (cint, [vp, vp, cint]),
+        "pirrt_mlp_get_params": (cint, [vp, vp, cint]),
+        "pirrt_mlp_forward": (cint, [vp, i32, vp, vp, cint]),
+        "pirrt_mlp_gradients": (cint, [vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
+        "pirrt_mlp_train_step": (cint, [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
+        "pirrt_mlp_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -477,6 +494,82 @@ class Rrg:
         out = np.empty(self.n, np.float32) if out is None else out
         self._check(self._lib.pirrt_rrg_heuristic(self._h, goal, _ptr(out), _mem_kind(out)))
         return out
+
+
+class Mlp:
+    """One pirrt_mlp handle (the learned proposal's network).  Parameters travel as
+    one float32 array in the layout of include/pirrt.h (W1 [288 x 256], b1, W2, b2,
+    w3, b3)."""
+
+    def __init__(self, in_dim: int, max_batch: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, stream: Optional[int] = None, device: int = -1, lib: Optional[ctypes.CDLL] = None):
+        self._lib = lib or load()
+        cfg = pirrt_mlp_config(in_dim, max_batch, lr, beta1, beta2, eps, stream or None, device)
+        h = ctypes.c_void_p()
+        rc = self._lib.pirrt_mlp_create(ctypes.byref(h), ctypes.byref(cfg))
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_mlp_last_error(None).decode())
+        self._h = h
+        self.in_dim = in_dim
+        self.num_params = int(self._lib.pirrt_mlp_num_params())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.pirrt_mlp_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != PIRRT_OK:
+            raise PirrtError(rc, self._lib.pirrt_mlp_last_error(self._h).decode())
+        return rc
+
+    def set_params(self, params) -> int:
+        params = _check_dtype(params, np.float32, "float32")
+        return self._check(self._lib.pirrt_mlp_set_params(self._h, _ptr(params), _mem_kind(params)))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, np.float32)
+        self._check(self._lib.pirrt_mlp_get_params(self._h, _ptr(out), PIRRT_MEM_HOST))
+        return out
+
+    def forward(self, x, out=None):
+        x = _check_dtype(x, np.float32, "float32")
+        B = int(x.shape[0])
+        if out is None:
+            if _is_device(x):
+                import torch
+                out = torch.empty(B, dtype=torch.float32, device=x.device)
+            else:
+                out = np.empty(B, np.float32)
+        self._check(self._lib.pirrt_mlp_forward(self._h, B, _ptr(x), _ptr(out), _mem_kind(x, out)))
+        return out
+
+    def gradients(self, x, y):
+        x = _check_dtype(x, np.float32, "float32")
+        y = _check_dtype(y, np.float32, "float32")
+        g = np.empty(self.num_params, np.float32)
+        loss = ctypes.c_float(0.0)
+        if _is_device(x):
+            import torch
+            gd = torch.empty(self.num_params, dtype=torch.float32, device=x.device)
+            self._check(self._lib.pirrt_mlp_gradients(self._h, int(x.shape[0]), _ptr(x), _ptr(y), _ptr(gd),
+                                                      ctypes.byref(loss), PIRRT_MEM_DEVICE))
+            return float(loss.value), gd.cpu().numpy()
+        self._check(self._lib.pirrt_mlp_gradients(self._h, int(x.shape[0]), _ptr(x), _ptr(y), _ptr(g),
+                                                  ctypes.byref(loss), PIRRT_MEM_HOST))
+        return float(loss.value), g
+
+    def train_step(self, x, y) -> float:
+        x = _check_dtype(x, np.float32, "float32")
+        y = _check_dtype(y, np.float32, "float32")
+        loss = ctypes.c_float(0.0)
+        self._check(self._lib.pirrt_mlp_train_step(self._h, int(x.shape[0]), _ptr(x), _ptr(y), ctypes.byref(loss),
+                                                   _mem_kind(x, y)))
+        return float(loss.value)
 
 
 def pirrt_strerror(code: int) -> str:

@@ -1,0 +1,546 @@
+// The learned sampling proposal's network on the device: features (sample
+// coordinates + obstacle encoding, zero-padded to K = 288) -> 256 -> 256 -> 1 logit,
+// ReLU hidden layers, bfloat16 operands with binary32 accumulation on MFMA, binary32
+// master parameters, BCE-with-logits loss, Adam (Kingma and Ba, 2015).
+//
+// Rounding points (the contract the oracle states): X = bf16(f); A1 = bf16(relu(Z1));
+// A2 = bf16(relu(Z2)); weights used by products are bf16 copies of the binary32
+// masters; dZ2 = bf16(dz w3^T * [Z2 > 0]); dZ1 = bf16(dZ2 W2^T * [Z1 > 0]).
+//
+// Every matrix product is one MFMA kernel: a workgroup of four waves owns a 64 x 64
+// output tile, each wave a 32 x 32 block accumulated by v_mfma_f32_32x32x16_bf16 over
+// K in steps of 16.  Operands are read through strides, so the transposed products of
+// the backward pass (A1^T dZ2, X^T dZ1, dZ2 W2^T) need no transposed copies; a
+// contiguous K run is fetched with one 16-byte load per lane.
+#include <string.h>
+
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+#include "pirrt.h"
+
+using namespace pirrt;
+
+namespace {
+
+constexpr int kIn = 288;      // padded input width (a multiple of 16)
+constexpr int kHidden = 256;  // hidden width
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kIn * kHidden;
+constexpr int64_t kOffW2 = kOffB1 + kHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kHidden * kHidden;
+constexpr int64_t kOffW3 = kOffB2 + kHidden;
+constexpr int64_t kOffB3 = kOffW3 + kHidden;
+constexpr int64_t kNumParams = kOffB3 + 1;
+constexpr int kThreads = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (no NaN reaches here)
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+enum Epi { kEpiFwd = 0, kEpiMaskBf16 = 1, kEpiF32 = 2 };
+
+struct GemmArgs {
+  int32_t M, N, K;
+  const uint16_t* A;  // element (m, k) at A[m * sam + k * sak]
+  int64_t sam, sak;
+  const uint16_t* B;  // element (k, n) at B[k * sbk + n * sbn]
+  int64_t sbk, sbn;
+  const float* bias;  // kEpiFwd: per column
+  const float* zref;  // kEpiMaskBf16: fp32 [M x N] whose sign gates the output
+  float* zout;        // kEpiFwd: fp32 pre-activation [M x N] (nullable); kEpiF32: output
+  uint16_t* bout;     // kEpiFwd / kEpiMaskBf16: bf16 output [M x N]
+};
+
+template <bool kAContig>
+__device__ __forceinline__ bf16x8 load_a(const GemmArgs& g, int64_t m, int64_t k) {
+  if (kAContig) {
+    const uint4 w = *reinterpret_cast<const uint4*>(g.A + m * g.sam + k);
+    return __builtin_bit_cast(bf16x8, w);
+  }
+  uint16_t t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = g.A[m * g.sam + (k + i) * g.sak];
+  return __builtin_bit_cast(bf16x8, t);
+}
+
+template <bool kBContig>
+__device__ __forceinline__ bf16x8 load_b(const GemmArgs& g, int64_t k, int64_t n) {
+  if (kBContig) {
+    const uint4 w = *reinterpret_cast<const uint4*>(g.B + n * g.sbn + k);
+    return __builtin_bit_cast(bf16x8, w);
+  }
+  uint16_t t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = g.B[(k + i) * g.sbk + n * g.sbn];
+  return __builtin_bit_cast(bf16x8, t);
+}
+
+// One 32 x 32 output block per wave.  Lane l supplies A row l % 32 and B column
+// l % 32 with the 8 consecutive K entries starting at 8 * (l / 32); accumulator
+// register r of lane l holds row 8 * (r / 4) + 4 * (l / 32) + r % 4, column l % 32.
+template <bool kAContig, bool kBContig, int kEpi>
+__global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t m0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
+  const int64_t n0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= g.M || n0 >= g.N) return;  // whole wave outside (M, N are multiples of 32)
+  const int64_t am = m0 + (lane & 31), bn = n0 + (lane & 31);
+  const int kq = (lane >> 5) * 8;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int64_t k = 0; k < g.K; k += 16) {
+    const bf16x8 a = load_a<kAContig>(g, am, k + kq);
+    const bf16x8 b = load_b<kBContig>(g, k + kq, bn);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int64_t col = n0 + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int64_t o = row * g.N + col;
+    if (kEpi == kEpiFwd) {
+      const float v = acc[r] + g.bias[col];
+      if (g.zout) g.zout[o] = v;
+      g.bout[o] = to_bf16(v > 0.0f ? v : 0.0f);
+    } else if (kEpi == kEpiMaskBf16) {
+      g.bout[o] = to_bf16(g.zref[o] > 0.0f ? acc[r] : 0.0f);
+    } else {
+      g.zout[o] = acc[r];
+    }
+  }
+}
+
+// X = bf16(features), zero-padded to kIn columns and Bp rows.
+__global__ void k_features(int32_t B, int32_t Bp, int32_t in_dim, const float* __restrict__ x,
+                           uint16_t* __restrict__ X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Bp * kIn) return;
+  const int64_t b = i / kIn, k = i % kIn;
+  X[i] = (b < B && k < in_dim) ? to_bf16(x[b * in_dim + k]) : (uint16_t)0;
+}
+
+// z = A2 w3 + b3 per row (one wave per row); with labels also dz = (sigmoid(z) - y)/B
+// (0 on padding rows) and the mean BCE-with-logits loss.
+__global__ void __launch_bounds__(kThreads) k_layer3(int32_t B, int32_t Bp, const uint16_t* __restrict__ A2,
+                                                     const uint16_t* __restrict__ w3b, const float* __restrict__ P,
+                                                     const float* __restrict__ y, float* __restrict__ z,
+                                                     float* __restrict__ dz, float* __restrict__ loss) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (b >= Bp) return;
+  float s = 0.0f;
+  for (int k = lane; k < kHidden; k += kWave) s += from_bf16(A2[b * kHidden + k]) * from_bf16(w3b[k]);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  if (lane != 0) return;
+  const float zb = s + P[kOffB3];
+  z[b] = zb;
+  if (!y) return;
+  if (b >= B) {
+    dz[b] = 0.0f;
+    return;
+  }
+  const float yb = y[b];
+  dz[b] = (1.0f / (1.0f + expf(-zb)) - yb) / (float)B;
+  const float l = fmaxf(zb, 0.0f) - zb * yb + log1pf(expf(-fabsf(zb)));
+  atomicAdd(loss, l / (float)B);
+}
+
+// dZ2 = bf16(dz w3^T * [Z2 > 0])
+__global__ void k_dz2(int32_t Bp, const float* __restrict__ dz, const uint16_t* __restrict__ w3b,
+                      const float* __restrict__ Z2, uint16_t* __restrict__ dZ2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Bp * kHidden) return;
+  const int64_t b = i / kHidden, k = i % kHidden;
+  dZ2[i] = to_bf16(Z2[i] > 0.0f ? dz[b] * from_bf16(w3b[k]) : 0.0f);
+}
+
+// out[n] = sum over rows of a bf16 [rows x N] matrix (one thread per column).
+__global__ void k_colsum(int32_t rows, int32_t N, const uint16_t* __restrict__ M, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int32_t r = 0; r < rows; ++r) s += from_bf16(M[(int64_t)r * N + n]);
+  out[n] = s;
+}
+
+// gw3[k] = sum_b A2[b][k] dz[b]; gb3 = sum_b dz[b] (thread kHidden).
+__global__ void k_grad3(int32_t Bp, const uint16_t* __restrict__ A2, const float* __restrict__ dz,
+                        float* __restrict__ G) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > kHidden) return;
+  float s = 0.0f;
+  if (k < kHidden)
+    for (int32_t b = 0; b < Bp; ++b) s += from_bf16(A2[(int64_t)b * kHidden + k]) * dz[b];
+  else
+    for (int32_t b = 0; b < Bp; ++b) s += dz[b];
+  G[k < kHidden ? kOffW3 + k : kOffB3] = s;
+}
+
+__global__ void k_adam(int64_t np, float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const float g = G[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_refresh(const float* __restrict__ P, uint16_t* __restrict__ W1b, uint16_t* __restrict__ W2b,
+                          uint16_t* __restrict__ w3b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)kIn * kHidden) W1b[i] = to_bf16(P[kOffW1 + i]);
+  if (i < (int64_t)kHidden * kHidden) W2b[i] = to_bf16(P[kOffW2 + i]);
+  if (i < kHidden) w3b[i] = to_bf16(P[kOffW3 + i]);
+}
+
+inline unsigned nblocks(int64_t n, int per = kThreads) { return (unsigned)((n + per - 1) / per > 0 ? (n + per - 1) / per : 1); }
+
+}  // namespace
+
+struct pirrt_mlp {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t in_dim = 0, max_batch = 0, bcap = 0;
+  float lr = 1e-3f, beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  int64_t t = 0;
+  float* P = nullptr;
+  float* G = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  uint16_t* W1b = nullptr;
+  uint16_t* W2b = nullptr;
+  uint16_t* w3b = nullptr;
+  float* xin = nullptr;   // staging of host features
+  float* yin = nullptr;
+  uint16_t* X = nullptr;
+  float* Z1 = nullptr;
+  uint16_t* A1 = nullptr;
+  float* Z2 = nullptr;
+  uint16_t* A2 = nullptr;
+  float* z = nullptr;
+  float* dz = nullptr;
+  uint16_t* dZ2 = nullptr;
+  uint16_t* dZ1 = nullptr;
+  float* dloss = nullptr;
+  float* hloss = nullptr;  // pinned
+  bool poisoned = false;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_mlp_create_error;
+
+int mfail(pirrt_mlp* N, int code, const std::string& m) {
+  N->err = m;
+  return code;
+}
+
+int mdev(pirrt_mlp* N, hipError_t e, const char* what) {
+  N->poisoned = true;
+  N->err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return PIRRT_EDEVICE;
+}
+
+#define MHIP(N, expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return mdev(N, e_, #expr);  \
+  } while (0)
+
+template <class T>
+bool malloc_dev(T** p, int64_t count) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
+
+template <class T>
+void free_dev(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void release(pirrt_mlp* N) {
+  free_dev(N->P); free_dev(N->G); free_dev(N->m); free_dev(N->v); free_dev(N->W1b); free_dev(N->W2b);
+  free_dev(N->w3b); free_dev(N->xin); free_dev(N->yin); free_dev(N->X); free_dev(N->Z1); free_dev(N->A1);
+  free_dev(N->Z2); free_dev(N->A2); free_dev(N->z); free_dev(N->dz); free_dev(N->dZ2); free_dev(N->dZ1);
+  free_dev(N->dloss);
+  if (N->hloss) (void)hipHostFree(N->hloss);
+  N->hloss = nullptr;
+}
+
+int mguard(pirrt_mlp* N) {
+  if (!N) return PIRRT_EINVAL;
+  if (N->poisoned) return PIRRT_EDEVICE;
+  hipError_t e = hipSetDevice(N->device);
+  if (e != hipSuccess) return mdev(N, e, "hipSetDevice");
+  return PIRRT_OK;
+}
+
+void launch_gemm(const GemmArgs& g, bool a_contig, bool b_contig, int epi, hipStream_t s) {
+  const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+#define GEMM(AC, BC, E) hipLaunchKernelGGL((k_gemm<AC, BC, E>), grid, dim3(kThreads), 0, s, g)
+  if (epi == kEpiFwd) {
+    if (a_contig && b_contig) GEMM(true, true, kEpiFwd); else GEMM(true, false, kEpiFwd);
+  } else if (epi == kEpiMaskBf16) {
+    GEMM(true, true, kEpiMaskBf16);
+  } else {
+    if (a_contig) GEMM(true, false, kEpiF32); else GEMM(false, false, kEpiF32);
+  }
+#undef GEMM
+}
+
+// Features into X (padded rows and columns are zero); B rows, Bp = B rounded up to 64.
+int stage_inputs(pirrt_mlp* N, int32_t B, int32_t Bp, const float* x, const float* y, int mem_kind,
+                 const float** yd) {
+  hipStream_t s = N->stream;
+  const float* xd = x;
+  *yd = y;
+  if (mem_kind == PIRRT_MEM_HOST) {
+    MHIP(N, hipMemcpyAsync(N->xin, x, sizeof(float) * (size_t)B * N->in_dim, hipMemcpyHostToDevice, s));
+    xd = N->xin;
+    if (y) {
+      MHIP(N, hipMemcpyAsync(N->yin, y, sizeof(float) * (size_t)B, hipMemcpyHostToDevice, s));
+      *yd = N->yin;
+    }
+  }
+  hipLaunchKernelGGL(k_features, dim3(nblocks((int64_t)Bp * kIn)), dim3(kThreads), 0, s, B, Bp, N->in_dim, xd, N->X);
+  MHIP(N, hipGetLastError());
+  return PIRRT_OK;
+}
+
+void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z) {
+  hipStream_t s = N->stream;
+  GemmArgs g1{Bp, kHidden, kIn, N->X, kIn, 1, N->W1b, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
+              N->A1};
+  // W1b is stored [kIn x kHidden] row-major: element (k, n) at k * kHidden + n
+  g1.sbk = kHidden;
+  g1.sbn = 1;
+  launch_gemm(g1, true, false, kEpiFwd, s);
+  GemmArgs g2{Bp, kHidden, kHidden, N->A1, kHidden, 1, N->W2b, kHidden, 1, N->P + kOffB2, nullptr,
+              keep_z ? N->Z2 : nullptr, N->A2};
+  launch_gemm(g2, true, false, kEpiFwd, s);
+}
+
+// Forward + loss + gradients into N->G (the loss lands in N->dloss).
+int enqueue_gradients(pirrt_mlp* N, int32_t B, int32_t Bp, const float* yd) {
+  hipStream_t s = N->stream;
+  enqueue_forward(N, Bp, true);
+  MHIP(N, hipMemsetAsync(N->dloss, 0, sizeof(float), s));
+  hipLaunchKernelGGL(k_layer3, dim3(nblocks((int64_t)Bp * kWave)), dim3(kThreads), 0, s, B, Bp, N->A2, N->w3b, N->P,
+                     yd, N->z, N->dz, N->dloss);
+  hipLaunchKernelGGL(k_grad3, dim3(nblocks(kHidden + 1)), dim3(kThreads), 0, s, Bp, N->A2, N->dz, N->G);
+  hipLaunchKernelGGL(k_dz2, dim3(nblocks((int64_t)Bp * kHidden)), dim3(kThreads), 0, s, Bp, N->dz, N->w3b, N->Z2,
+                     N->dZ2);
+  hipLaunchKernelGGL(k_colsum, dim3(nblocks(kHidden)), dim3(kThreads), 0, s, Bp, kHidden, N->dZ2, N->G + kOffB2);
+  // gW2[i][j] = sum_b A1[b][i] dZ2[b][j]
+  GemmArgs gw2{kHidden, kHidden, Bp, N->A1, 1, kHidden, N->dZ2, kHidden, 1, nullptr, nullptr, N->G + kOffW2,
+               nullptr};
+  launch_gemm(gw2, false, false, kEpiF32, s);
+  // dZ1 = bf16(dZ2 W2^T * [Z1 > 0]): element (k = j, n = i) of W2^T is W2b[i][j]
+  GemmArgs gd1{Bp, kHidden, kHidden, N->dZ2, kHidden, 1, N->W2b, 1, kHidden, nullptr, N->Z1, nullptr, N->dZ1};
+  launch_gemm(gd1, true, true, kEpiMaskBf16, s);
+  hipLaunchKernelGGL(k_colsum, dim3(nblocks(kHidden)), dim3(kThreads), 0, s, Bp, kHidden, N->dZ1, N->G + kOffB1);
+  // gW1[i][j] = sum_b X[b][i] dZ1[b][j]
+  GemmArgs gw1{kIn, kHidden, Bp, N->X, 1, kIn, N->dZ1, kHidden, 1, nullptr, nullptr, N->G + kOffW1, nullptr};
+  launch_gemm(gw1, false, false, kEpiF32, s);
+  MHIP(N, hipGetLastError());
+  return PIRRT_OK;
+}
+
+int check_batch(pirrt_mlp* N, int32_t B, const float* x, int mem_kind) {
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return mfail(N, PIRRT_EINVAL, "bad mem_kind");
+  if (B < 1 || B > N->max_batch) return mfail(N, PIRRT_EINVAL, "batch size outside 1..max_batch");
+  if (!x) return mfail(N, PIRRT_EINVAL, "x is NULL");
+  return PIRRT_OK;
+}
+
+inline int32_t padded(int32_t B) { return (B + 63) / 64 * 64; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t pirrt_mlp_num_params(void) { return kNumParams; }
+
+int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
+  if (!out || !cfg) return PIRRT_EINVAL;
+  *out = nullptr;
+  if (cfg->in_dim < 1 || cfg->in_dim > kIn || cfg->max_batch < 1 || cfg->max_batch > (1 << 24) ||
+      !(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f)) {
+    g_mlp_create_error = "in_dim outside 1..288, max_batch outside 1..2^24, or bad Adam constants";
+    return PIRRT_EINVAL;
+  }
+  pirrt_mlp* N = new (std::nothrow) pirrt_mlp();
+  if (!N) return PIRRT_ENOMEM;
+  int dev = cfg->device;
+  if ((dev < 0 && hipGetDevice(&dev) != hipSuccess) || hipSetDevice(dev) != hipSuccess) {
+    (void)hipGetLastError();
+    delete N;
+    g_mlp_create_error = "no HIP device";
+    return PIRRT_EDEVICE;
+  }
+  N->device = dev;
+  N->stream = (hipStream_t)cfg->hip_stream;
+  N->in_dim = cfg->in_dim;
+  N->max_batch = cfg->max_batch;
+  N->bcap = padded(cfg->max_batch);
+  N->lr = cfg->lr;
+  N->beta1 = cfg->beta1;
+  N->beta2 = cfg->beta2;
+  N->eps = cfg->eps;
+  const int64_t bc = N->bcap;
+  bool ok = malloc_dev(&N->P, kNumParams) && malloc_dev(&N->G, kNumParams) && malloc_dev(&N->m, kNumParams) &&
+            malloc_dev(&N->v, kNumParams) && malloc_dev(&N->W1b, (int64_t)kIn * kHidden) &&
+            malloc_dev(&N->W2b, (int64_t)kHidden * kHidden) && malloc_dev(&N->w3b, kHidden) &&
+            malloc_dev(&N->xin, (int64_t)N->max_batch * N->in_dim) && malloc_dev(&N->yin, N->max_batch) &&
+            malloc_dev(&N->X, bc * kIn) && malloc_dev(&N->Z1, bc * kHidden) && malloc_dev(&N->A1, bc * kHidden) &&
+            malloc_dev(&N->Z2, bc * kHidden) && malloc_dev(&N->A2, bc * kHidden) && malloc_dev(&N->z, bc) &&
+            malloc_dev(&N->dz, bc) && malloc_dev(&N->dZ2, bc * kHidden) && malloc_dev(&N->dZ1, bc * kHidden) &&
+            malloc_dev(&N->dloss, 1);
+  if (ok && hipHostMalloc((void**)&N->hloss, sizeof(float), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    N->hloss = nullptr;
+    ok = false;
+  }
+  if (ok)
+    ok = hipMemset(N->P, 0, sizeof(float) * kNumParams) == hipSuccess &&
+         hipMemset(N->m, 0, sizeof(float) * kNumParams) == hipSuccess &&
+         hipMemset(N->v, 0, sizeof(float) * kNumParams) == hipSuccess &&
+         hipMemset(N->W1b, 0, sizeof(uint16_t) * kIn * kHidden) == hipSuccess &&
+         hipMemset(N->W2b, 0, sizeof(uint16_t) * kHidden * kHidden) == hipSuccess &&
+         hipMemset(N->w3b, 0, sizeof(uint16_t) * kHidden) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    release(N);
+    delete N;
+    g_mlp_create_error = "device allocation failed at create";
+    return PIRRT_ENOMEM;
+  }
+  *out = N;
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_destroy(pirrt_mlp* N) {
+  if (!N) return PIRRT_OK;
+  (void)hipSetDevice(N->device);
+  if (!N->poisoned) (void)hipStreamSynchronize(N->stream);
+  release(N);
+  delete N;
+  return PIRRT_OK;
+}
+
+const char* pirrt_mlp_last_error(const pirrt_mlp* N) { return N ? N->err.c_str() : g_mlp_create_error.c_str(); }
+
+int pirrt_mlp_set_params(pirrt_mlp* N, const float* params, int mem_kind) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return mfail(N, PIRRT_EINVAL, "bad mem_kind");
+  if (!params) return mfail(N, PIRRT_EINVAL, "params is NULL");
+  if (mem_kind == PIRRT_MEM_HOST)
+    for (int64_t i = 0; i < kNumParams; ++i)
+      if (!std::isfinite(params[i])) return mfail(N, PIRRT_EINVAL, "parameter not finite");
+  hipStream_t s = N->stream;
+  MHIP(N, hipMemcpyAsync(N->P, params, sizeof(float) * kNumParams,
+                         mem_kind == PIRRT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+  MHIP(N, hipMemsetAsync(N->m, 0, sizeof(float) * kNumParams, s));
+  MHIP(N, hipMemsetAsync(N->v, 0, sizeof(float) * kNumParams, s));
+  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, s, N->P, N->W1b, N->W2b,
+                     N->w3b);
+  MHIP(N, hipGetLastError());
+  MHIP(N, hipStreamSynchronize(s));
+  N->t = 0;
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_get_params(pirrt_mlp* N, float* params, int mem_kind) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return mfail(N, PIRRT_EINVAL, "bad mem_kind");
+  if (!params) return mfail(N, PIRRT_EINVAL, "params is NULL");
+  MHIP(N, hipMemcpyAsync(params, N->P, sizeof(float) * kNumParams,
+                         mem_kind == PIRRT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, N->stream));
+  MHIP(N, hipStreamSynchronize(N->stream));
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_forward(pirrt_mlp* N, int32_t B, const float* x, float* logits, int mem_kind) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if ((rc = check_batch(N, B, x, mem_kind))) return rc;
+  if (!logits) return mfail(N, PIRRT_EINVAL, "logits is NULL");
+  const int32_t Bp = padded(B);
+  const float* yd = nullptr;
+  if ((rc = stage_inputs(N, B, Bp, x, nullptr, mem_kind, &yd))) return rc;
+  enqueue_forward(N, Bp, false);
+  hipLaunchKernelGGL(k_layer3, dim3(nblocks((int64_t)Bp * kWave)), dim3(kThreads), 0, N->stream, B, Bp, N->A2,
+                     N->w3b, N->P, nullptr, N->z, nullptr, nullptr);
+  MHIP(N, hipGetLastError());
+  MHIP(N, hipMemcpyAsync(logits, N->z, sizeof(float) * (size_t)B,
+                         mem_kind == PIRRT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, N->stream));
+  MHIP(N, hipStreamSynchronize(N->stream));
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_gradients(pirrt_mlp* N, int32_t B, const float* x, const float* y, float* grads, float* loss,
+                        int mem_kind) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if ((rc = check_batch(N, B, x, mem_kind))) return rc;
+  if (!y) return mfail(N, PIRRT_EINVAL, "y is NULL");
+  const int32_t Bp = padded(B);
+  const float* yd = nullptr;
+  if ((rc = stage_inputs(N, B, Bp, x, y, mem_kind, &yd))) return rc;
+  if ((rc = enqueue_gradients(N, B, Bp, yd))) return rc;
+  if (grads)
+    MHIP(N, hipMemcpyAsync(grads, N->G, sizeof(float) * kNumParams,
+                           mem_kind == PIRRT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, N->stream));
+  MHIP(N, hipMemcpyAsync(N->hloss, N->dloss, sizeof(float), hipMemcpyDeviceToHost, N->stream));
+  MHIP(N, hipStreamSynchronize(N->stream));
+  if (loss) *loss = *N->hloss;
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_train_step(pirrt_mlp* N, int32_t B, const float* x, const float* y, float* loss, int mem_kind) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if ((rc = check_batch(N, B, x, mem_kind))) return rc;
+  if (!y) return mfail(N, PIRRT_EINVAL, "y is NULL");
+  const int32_t Bp = padded(B);
+  const float* yd = nullptr;
+  if ((rc = stage_inputs(N, B, Bp, x, y, mem_kind, &yd))) return rc;
+  if ((rc = enqueue_gradients(N, B, Bp, yd))) return rc;
+  N->t += 1;
+  const float c1 = 1.0f - powf(N->beta1, (float)N->t), c2 = 1.0f - powf(N->beta2, (float)N->t);
+  hipLaunchKernelGGL(k_adam, dim3(nblocks(kNumParams)), dim3(kThreads), 0, N->stream, kNumParams, N->P, N->G, N->m,
+                     N->v, N->lr, N->beta1, N->beta2, N->eps, c1, c2);
+  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, N->stream, N->P, N->W1b,
+                     N->W2b, N->w3b);
+  MHIP(N, hipGetLastError());
+  MHIP(N, hipMemcpyAsync(N->hloss, N->dloss, sizeof(float), hipMemcpyDeviceToHost, N->stream));
+  MHIP(N, hipStreamSynchronize(N->stream));
+  if (loss) *loss = *N->hloss;
+  return PIRRT_OK;
+}
+
+}  // extern "C"
