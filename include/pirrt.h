@@ -329,6 +329,7 @@ typedef struct {
 } pirrt_mlp_config;
 
 int64_t pirrt_mlp_num_params(void);
+int32_t pirrt_mlp_in_dim(const pirrt_mlp* net); /* -1 for NULL */
 /* Creates a network with all parameters 0 (set them with pirrt_mlp_set_params). */
 int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg);
 int pirrt_mlp_destroy(pirrt_mlp* net);
@@ -344,6 +345,18 @@ int pirrt_mlp_gradients(pirrt_mlp* net, int32_t B, const float* x, const float* 
 /* One Adam step on one batch; *loss (host, nullable) = the batch loss before it. */
 int pirrt_mlp_train_step(pirrt_mlp* net, int32_t B, const float* x, const float* y, float* loss, int mem_kind);
 const char* pirrt_mlp_last_error(const pirrt_mlp* net);
+
+/*
+ * Learned proposal sampling: appends to r the `count` best of n_candidates free
+ * uniform candidates (<= 8192) of stream `stream` under `seed` from *counter on
+ * (advanced past them), scored by net on features = the candidate's coordinates
+ * (binary32), then enc[enc_len] (host, e.g. the obstacle encoding); d + enc_len must
+ * equal the network's in_dim and n_candidates may not exceed its max_batch.  Higher
+ * logit wins, the earlier candidate among equal logits; the chosen ones are appended
+ * in candidate order.  The planner mixes these with pirrt_rrg_sample draws.
+ */
+int pirrt_rrg_sample_learned(pirrt_rrg* r, pirrt_mlp* net, const float* enc, int32_t enc_len, uint64_t seed,
+                             uint32_t stream, uint64_t* counter, int32_t n_candidates, int32_t count);
 
 #ifdef __cplusplus
 }

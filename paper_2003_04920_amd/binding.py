@@ -34,6 +34,7 @@ EXPORTS = [
     "pirrt_rrg_heuristic", "pirrt_rrg_last_error",
     "pirrt_mlp_num_params", "pirrt_mlp_create", "pirrt_mlp_destroy", "pirrt_mlp_set_params", "pirrt_mlp_get_params",
     "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
+    "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned",
 ]
 
 
@@ -133,6 +134,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_mlp_gradients": (cint, [vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
         "pirrt_mlp_train_step": (cint, [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
         "pirrt_mlp_last_error": (ctypes.c_char_p, [vp]),
+        "pirrt_mlp_in_dim": (i32, [vp]),
+        "pirrt_rrg_sample_learned": (cint, [vp, vp, vp, i32, ctypes.c_uint64, u32, ctypes.POINTER(ctypes.c_uint64),
+                                            i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -459,6 +463,17 @@ class Rrg:
         """Appends `count` free samples; returns the next counter."""
         c = ctypes.c_uint64(counter)
         self._check(self._lib.pirrt_rrg_sample(self._h, int(seed), int(stream), ctypes.byref(c), int(count)))
+        return int(c.value)
+
+    def sample_learned(self, net: "Mlp", enc, seed: int, stream: int, counter: int, n_candidates: int,
+                       count: int) -> int:
+        """Appends the `count` best-scored of n_candidates free candidates; returns
+        the next counter."""
+        enc = np.ascontiguousarray(enc, np.float32)
+        c = ctypes.c_uint64(counter)
+        self._check(self._lib.pirrt_rrg_sample_learned(self._h, net._h, enc.ctypes.data if len(enc) else None,
+                                                       len(enc), int(seed), int(stream), ctypes.byref(c),
+                                                       int(n_candidates), int(count)))
         return int(c.value)
 
     def points(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:

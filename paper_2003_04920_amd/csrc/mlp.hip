@@ -382,6 +382,8 @@ extern "C" {
 
 int64_t pirrt_mlp_num_params(void) { return kNumParams; }
 
+int32_t pirrt_mlp_in_dim(const pirrt_mlp* N) { return N ? N->in_dim : -1; }
+
 int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
   if (!out || !cfg) return PIRRT_EINVAL;
   *out = nullptr;

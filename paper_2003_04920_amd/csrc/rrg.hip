@@ -278,6 +278,87 @@ __global__ void __launch_bounds__(kThreads) k_heuristic(int64_t n, const double*
   h[v] = __double2float_rn(__dsqrt_rn(dist2<D>(x, gx)));
 }
 
+// Features of candidate samples: coordinates (as binary32), then the encoding.
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_features(int32_t m, const double* __restrict__ pts,
+                                                       const float* __restrict__ enc, int32_t in_dim,
+                                                       float* __restrict__ feat) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)m * in_dim) return;
+  const int64_t r = i / in_dim, k = i % in_dim;
+  feat[i] = k < D ? (float)pts[r * D + k] : enc[k - D];
+}
+
+// The c best of m logits (m <= kSelMax): one workgroup sorts 64-bit keys {logit in
+// a sign-ordered encoding, complement of the index} in LDS with a bitonic network
+// (descending: highest logit first, the earlier candidate first among equal
+// logits), flags the first c, then lists the flagged indices in ascending order.
+constexpr int kSelThreads = 1024;
+constexpr int kSelMax = 8192;
+
+__global__ void __launch_bounds__(kSelThreads) k_select_top(int32_t m, int32_t c, const float* __restrict__ logits,
+                                                            int32_t* __restrict__ flag, int32_t* __restrict__ sel) {
+  __shared__ unsigned long long key[kSelMax];
+  __shared__ int32_t part[kSelThreads];
+  int N = 1;
+  while (N < m) N <<= 1;
+  for (int i = threadIdx.x; i < N; i += kSelThreads) {
+    unsigned long long kk = 0ull;  // padding sorts last
+    if (i < m) {
+      uint32_t u = __float_as_uint(logits[i]);
+      u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+      kk = ((unsigned long long)u << 32) | (unsigned long long)(~(uint32_t)i);
+      flag[i] = 0;
+    }
+    key[i] = kk;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += kSelThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const unsigned long long a = key[i], b = key[l];
+          if (((i & k) == 0) ? (a < b) : (a > b)) {
+            key[i] = b;
+            key[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < c; i += kSelThreads) flag[~(uint32_t)key[i]] = 1;
+  __syncthreads();
+  const int chunk = (m + kSelThreads - 1) / kSelThreads;
+  const int lo = threadIdx.x * chunk, hi = lo + chunk < m ? lo + chunk : m;
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += flag[i];
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kSelThreads; ++w) {
+      const int x = part[w];
+      part[w] = t;
+      t += x;
+    }
+  }
+  __syncthreads();
+  int pos = part[threadIdx.x];
+  for (int i = lo; i < hi; ++i)
+    if (flag[i]) sel[pos++] = i;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_gather_points(int32_t c, const int32_t* __restrict__ sel,
+                                                            const double* __restrict__ cand, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)c * D) return;
+  const int64_t j = i / D, k = i % D;
+  dst[i] = cand[(int64_t)sel[j] * D + k];
+}
+
 __global__ void k_check_points(int64_t m, const double* __restrict__ x, int* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < m && !isfinite(x[i])) atomicOr(bad, 1);
@@ -316,6 +397,13 @@ struct pirrt_rrg {
   float* cost = nullptr;
   float* hbuf = nullptr;
   int64_t hcap = 0;
+  // learned sampler scratch (at most kSelMax candidates)
+  double* lpts = nullptr;
+  float* lfeat = nullptr;
+  float* llogit = nullptr;
+  float* lenc = nullptr;
+  int32_t* lflag = nullptr;
+  int32_t* lsel = nullptr;
   void* scan = nullptr;
   size_t scan_bytes = 0;
   int64_t* dword = nullptr;
@@ -411,9 +499,9 @@ void launch_candidates(pirrt_rrg* R, int64_t T, uint64_t k0, uint64_t seed, uint
 }
 
 template <int D>
-void launch_take(pirrt_rrg* R, int64_t T, int64_t need) {
-  hipLaunchKernelGGL(k_take<D>, dim3(blocks(T)), dim3(kThreads), 0, R->stream, T, need, R->cbuf, R->flag, R->pos,
-                     R->pts + R->n * D, R->dword);
+void launch_take(pirrt_rrg* R, int64_t T, int64_t need, double* dst) {
+  hipLaunchKernelGGL(k_take<D>, dim3(blocks(T)), dim3(kThreads), 0, R->stream, T, need, R->cbuf, R->flag, R->pos, dst,
+                     R->dword);
 }
 
 template <int D>
@@ -518,10 +606,61 @@ int build_rows(pirrt_rrg* R, int64_t n_old, double radius, int64_t* nnz) {
   return PIRRT_OK;
 }
 
+// `count` free candidates of (seed, stream) from *counter on, in counter order, into
+// dst (device, count * d doubles); *counter ends one past the last one taken.
+int draw_free(pirrt_rrg* R, uint64_t seed, uint32_t stream_id, uint64_t* counter, int64_t count, double* dst) {
+  const int d = R->d;
+  int rc;
+  uint64_t k = *counter;
+  int64_t need = count, got_all = 0, tried = 0;
+  while (need > 0) {
+    const int64_t T = need + need / 2 + 4096;
+    if (T > R->cand_cap_s) {
+      rfree(R->cbuf); rfree(R->flag); rfree(R->pos);
+      R->cand_cap_s = 0;
+      if (!ralloc(&R->cbuf, T * d) || !ralloc(&R->flag, T) || !ralloc(&R->pos, T + 1))
+        return rfail(R, PIRRT_ENOMEM, "device allocation of sampler candidates failed");
+      R->cand_cap_s = T;
+    }
+    if ((rc = ensure_scan(R, T + 1))) return rc;
+#define CANDS(D) launch_candidates<D>(R, T, k, seed, stream_id)
+    PIRRT_BY_DIM(d, CANDS);
+#undef CANDS
+    RHIP(R, hipGetLastError());
+    scan_i32_to_i64(R->flag, T, R->pos, R->scan, R->stream);
+    RHIP(R, hipGetLastError());
+    RHIP(R, hipMemsetAsync(R->dword, 0, sizeof(int64_t), R->stream));
+    double* out = dst + got_all * d;
+#define TAKE(D) launch_take<D>(R, T, need, out)
+    PIRRT_BY_DIM(d, TAKE);
+#undef TAKE
+    RHIP(R, hipGetLastError());
+    RHIP(R, hipMemcpyAsync(R->host, R->pos + T, sizeof(int64_t), hipMemcpyDeviceToHost, R->stream));
+    RHIP(R, hipMemcpyAsync(R->host + 1, R->dword, sizeof(int64_t), hipMemcpyDeviceToHost, R->stream));
+    RHIP(R, hipStreamSynchronize(R->stream));
+    const int64_t got = R->host[0];
+    if (got >= need) {
+      k += (uint64_t)R->host[1];
+      got_all += need;
+      need = 0;
+    } else {
+      k += (uint64_t)T;
+      got_all += got;
+      need -= got;
+    }
+    tried += T;
+    if (need > 0 && tried > count * 4096 + (1 << 24))
+      return rfail(R, PIRRT_EINVAL, "the free space is too small: no free sample found");
+  }
+  *counter = k;
+  return PIRRT_OK;
+}
+
 void release(pirrt_rrg* R) {
   rfree(R->okind); rfree(R->ocentre); rfree(R->osize); rfree(R->pts); rfree(R->cbuf); rfree(R->flag); rfree(R->pos);
   rfree(R->cnt); rfree(R->cptr); rfree(R->cand_u); rfree(R->cand_v); rfree(R->keep); rfree(R->kpos); rfree(R->ccost);
   rfree(R->rp); rfree(R->col); rfree(R->cost); rfree(R->hbuf); rfree(R->dword); rfree(R->dflag);
+  rfree(R->lpts); rfree(R->lfeat); rfree(R->llogit); rfree(R->lenc); rfree(R->lflag); rfree(R->lsel);
   if (R->scan) (void)hipFree(R->scan);
   R->scan = nullptr;
   if (R->host) (void)hipHostFree(R->host);
@@ -648,48 +787,58 @@ int pirrt_rrg_sample(pirrt_rrg* R, uint64_t seed, uint32_t stream_id, uint64_t* 
   if (count < 0) return rfail(R, PIRRT_EINVAL, "count < 0");
   if (R->n + count > (int64_t)INT32_MAX - 1) return rfail(R, PIRRT_EINVAL, "point ids beyond INT32_MAX");
   if (count == 0) return PIRRT_OK;
+  if ((rc = grow(R, &R->pts, &R->cap, (R->n + count) * R->d, R->n * R->d))) return rc;
+  if ((rc = draw_free(R, seed, stream_id, counter, count, R->pts + R->n * R->d))) return rc;
+  R->n += count;
+  return PIRRT_OK;
+}
+
+int pirrt_rrg_sample_learned(pirrt_rrg* R, pirrt_mlp* net, const float* enc, int32_t enc_len, uint64_t seed,
+                             uint32_t stream_id, uint64_t* counter, int32_t n_candidates, int32_t count) {
+  int rc = rguard(R);
+  if (rc) return rc;
+  if (!net || !counter) return rfail(R, PIRRT_EINVAL, "net or counter is NULL");
+  if (n_candidates < 1 || n_candidates > kSelMax) return rfail(R, PIRRT_EINVAL, "n_candidates outside 1..8192");
+  if (count < 0 || count > n_candidates) return rfail(R, PIRRT_EINVAL, "count outside 0..n_candidates");
+  if (enc_len < 0 || (enc_len > 0 && !enc)) return rfail(R, PIRRT_EINVAL, "bad encoding");
   const int d = R->d;
+  const int32_t in_dim = d + enc_len;
+  if (pirrt_mlp_in_dim(net) != in_dim) return rfail(R, PIRRT_EINVAL, "d + enc_len differs from the network's in_dim");
+  if (R->n + count > (int64_t)INT32_MAX - 1) return rfail(R, PIRRT_EINVAL, "point ids beyond INT32_MAX");
+  if (count == 0) return PIRRT_OK;
+  if (!R->lpts) {
+    if (!ralloc(&R->lpts, (int64_t)kSelMax * kMaxDim) || !ralloc(&R->lfeat, (int64_t)kSelMax * 288) ||
+        !ralloc(&R->llogit, kSelMax) || !ralloc(&R->lenc, 288) || !ralloc(&R->lflag, kSelMax) ||
+        !ralloc(&R->lsel, kSelMax))
+      return rfail(R, PIRRT_ENOMEM, "device allocation of the learned sampler failed");
+  }
   if ((rc = grow(R, &R->pts, &R->cap, (R->n + count) * d, R->n * d))) return rc;
   uint64_t k = *counter;
-  int64_t need = count, tried = 0;
-  while (need > 0) {
-    const int64_t T = need + need / 2 + 4096;
-    if (T > R->cand_cap_s) {
-      rfree(R->cbuf); rfree(R->flag); rfree(R->pos);
-      R->cand_cap_s = 0;
-      if (!ralloc(&R->cbuf, T * d) || !ralloc(&R->flag, T) || !ralloc(&R->pos, T + 1))
-        return rfail(R, PIRRT_ENOMEM, "device allocation of sampler candidates failed");
-      R->cand_cap_s = T;
-    }
-    if ((rc = ensure_scan(R, T + 1))) return rc;
-#define CANDS(D) launch_candidates<D>(R, T, k, seed, stream_id)
-    PIRRT_BY_DIM(d, CANDS);
-#undef CANDS
-    RHIP(R, hipGetLastError());
-    scan_i32_to_i64(R->flag, T, R->pos, R->scan, R->stream);
-    RHIP(R, hipGetLastError());
-    RHIP(R, hipMemsetAsync(R->dword, 0, sizeof(int64_t), R->stream));
-#define TAKE(D) launch_take<D>(R, T, need)
-    PIRRT_BY_DIM(d, TAKE);
-#undef TAKE
-    RHIP(R, hipGetLastError());
-    RHIP(R, hipMemcpyAsync(R->host, R->pos + T, sizeof(int64_t), hipMemcpyDeviceToHost, R->stream));
-    RHIP(R, hipMemcpyAsync(R->host + 1, R->dword, sizeof(int64_t), hipMemcpyDeviceToHost, R->stream));
-    RHIP(R, hipStreamSynchronize(R->stream));
-    const int64_t got = R->host[0];
-    if (got >= need) {
-      k += (uint64_t)R->host[1];
-      R->n += need;
-      need = 0;
-    } else {
-      k += (uint64_t)T;
-      R->n += got;
-      need -= got;
-    }
-    tried += T;
-    if (need > 0 && tried > (int64_t)count * 4096 + (1 << 24))
-      return rfail(R, PIRRT_EINVAL, "the free space is too small: no free sample found");
-  }
+  if ((rc = draw_free(R, seed, stream_id, &k, n_candidates, R->lpts))) return rc;
+  hipStream_t s = R->stream;
+  if (enc_len > 0)
+    RHIP(R, hipMemcpyAsync(R->lenc, enc, sizeof(float) * (size_t)enc_len, hipMemcpyHostToDevice, s));
+#define FEAT(D)                                                                                               \
+  hipLaunchKernelGGL(k_features<D>, dim3(blocks((int64_t)n_candidates * in_dim)), dim3(kThreads), 0, s, n_candidates, \
+                     R->lpts, R->lenc, in_dim, R->lfeat)
+  PIRRT_BY_DIM(d, FEAT);
+#undef FEAT
+  RHIP(R, hipGetLastError());
+  RHIP(R, hipStreamSynchronize(s));
+  rc = pirrt_mlp_forward(net, n_candidates, R->lfeat, R->llogit, PIRRT_MEM_DEVICE);
+  if (rc) return rfail(R, rc, std::string("pirrt_mlp_forward: ") + pirrt_mlp_last_error(net));
+  hipLaunchKernelGGL(k_select_top, dim3(1), dim3(kSelThreads), 0, s, n_candidates, count, R->llogit, R->lflag,
+                     R->lsel);
+  RHIP(R, hipGetLastError());
+  double* dst = R->pts + R->n * d;
+#define GATHER(D)                                                                                                \
+  hipLaunchKernelGGL(k_gather_points<D>, dim3(blocks((int64_t)count * D)), dim3(kThreads), 0, s, count, R->lsel, \
+                     R->lpts, dst)
+  PIRRT_BY_DIM(d, GATHER);
+#undef GATHER
+  RHIP(R, hipGetLastError());
+  RHIP(R, hipStreamSynchronize(s));
+  R->n += count;
   *counter = k;
   return PIRRT_OK;
 }

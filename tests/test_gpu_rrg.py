@@ -133,3 +133,30 @@ def test_rrg_invalid_arguments(P):
         G.connect(1, 0.3, graph)  # the graph holds 0 points, not 1
     G.connect(0, 0.3, graph)
     assert graph.n == 2
+
+
+@pytest.mark.parametrize("n_cand,count", [(8192, 500), (1000, 1000), (777, 13)])
+def test_sample_learned(P, n_cand, count):
+    """The learned sampler appends exactly the `count` best-scored of the oracle's
+    n_cand free candidates (the network's own logits, ties to the earlier
+    candidate), in candidate order, and advances the counter past them."""
+    from oracle import mlp as ML
+    d = 6
+    obs = W.make_obstacles(d, 40, "sphere", 77)
+    enc = ML.obstacle_encoding(obs).astype(np.float32)
+    net = P.Mlp(d + len(enc), 8192)
+    p = ML.init_params(np.random.default_rng(3), d + len(enc))
+    net.set_params(np.concatenate([np.asarray(getattr(p, k), np.float32).ravel() for k in ML.PARAM_NAMES]))
+    G = P.Rrg(d, obs, stream=stream())
+    G.add_points(ROOT_GOAL(d))
+    c = G.sample_learned(net, enc, seed=5, stream=9, counter=0, n_candidates=n_cand, count=count)
+    cand, want_c = R.sample(d, 5, 9, 0, n_cand, obs)
+    assert c == want_c
+    feats = np.concatenate([cand.astype(np.float32), np.broadcast_to(enc, (n_cand, len(enc)))], axis=1)
+    logits = net.forward(np.ascontiguousarray(feats, np.float32))
+    order = np.lexsort((np.arange(n_cand), -logits.astype(np.float64)))
+    chosen = np.sort(order[:count])
+    got = G.points(2)
+    assert np.array_equal(got, cand[chosen])
+    with pytest.raises(P.PirrtError):
+        G.sample_learned(net, enc[:-1], seed=5, stream=9, counter=0, n_candidates=10, count=5)
