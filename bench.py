@@ -225,6 +225,172 @@ def bench_multi(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args):
+    """Learned sampling proposal on the 6D generator (40 spheres): training data from
+    converged Replans on `args.layouts` layouts at 200k vertices (label: a path
+    through the vertex within 5% of the best, from a root-rooted and a goal-rooted
+    Replan without pruning), the network trained on the device, then the planner
+    grown to `args.plan_n` vertices in batches of `args.batch` on held-out layouts,
+    uniform sampling against half learned / half uniform sampling, with Replan
+    after every batch."""
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    d, n_train = 6, 200_000
+    root_goal = np.stack([np.full(d, 0.05), np.full(d, 0.95)])
+
+    def build(seed, n):
+        obs = W.make_obstacles(d, 40, "sphere", seed)
+        R = P.Rrg(d, obs, stream=stream, point_capacity=n)
+        R.add_points(root_goal)
+        R.sample(seed + 1, 0, 0, n - 2)
+        G = P.Graph(stream=stream, vertex_capacity=n)
+        R.connect(0, W.radius(n, d), G)
+        return obs, R, G
+
+    # ---- training data
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    rng = np.random.default_rng(7)
+    pos_total = 0
+    for i in range(args.layouts):
+        obs, R, G = build(20_000 + 10 * i, n_train)
+        g_r, _, _ = G.replan(0, 1, None, False)
+        g_t, _, _ = G.replan(1, 0, None, False)
+        best = float(g_r[1])
+        tot = g_r.astype(np.float64) + g_t.astype(np.float64)
+        lab = (np.isfinite(tot) & (tot <= 1.05 * best)).astype(np.float32)
+        pos = np.nonzero(lab > 0)[0]
+        neg = np.nonzero(lab == 0)[0]
+        k_pos = min(len(pos), args.per_layout // 2)
+        pick = np.concatenate([rng.choice(pos, k_pos, replace=False),
+                               rng.choice(neg, args.per_layout - k_pos, replace=False)])
+        pts = R.points()[pick].astype(np.float32)
+        enc = W.sphere_encoding(obs)
+        xs.append(np.concatenate([pts, np.broadcast_to(enc, (len(pick), len(enc)))], axis=1))
+        ys.append(lab[pick])
+        pos_total += int(lab.sum())
+        del R, G
+    X = torch.from_numpy(np.ascontiguousarray(np.concatenate(xs), np.float32)).to(dev)
+    Y = torch.from_numpy(np.concatenate(ys)).to(dev)
+    data_s = time.perf_counter() - t0
+    log("training data: %d layouts, %d samples (%.1f%% positive), %.1f s; positives per layout %.0f" %
+        (args.layouts, len(Y), 100.0 * float(Y.mean()), data_s, pos_total / max(1, args.layouts)))
+
+    # ---- training on the device
+    in_dim = X.shape[1]
+    net = P.Mlp(in_dim, 8192, lr=1e-3, stream=stream)
+    init = np.zeros(net.num_params, np.float32)
+    r2 = np.random.default_rng(11)
+    o = 0
+    init[o:o + in_dim * 256] = (r2.standard_normal((in_dim, 256)) * np.sqrt(2.0 / in_dim)).ravel()
+    o = 288 * 256 + 256
+    init[o:o + 256 * 256] = (r2.standard_normal(256 * 256) * np.sqrt(2.0 / 256))
+    o += 256 * 256 + 256
+    init[o:o + 256] = r2.standard_normal(256) * np.sqrt(1.0 / 256)
+    net.set_params(init)
+    nval = len(Y) // 10
+    perm = torch.from_numpy(np.random.default_rng(3).permutation(len(Y))).to(dev)
+    Xv, Yv, Xt, Yt = X[perm[:nval]], Y[perm[:nval]], X[perm[nval:]].contiguous(), Y[perm[nval:]].contiguous()
+    bs = 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses, steps = [], 0
+    for ep in range(args.epochs):
+        order = torch.randperm(len(Yt), device=dev)
+        for i in range(0, len(Yt) - bs + 1, bs):
+            idx = order[i:i + bs]
+            losses.append(net.train_step(Xt[idx].contiguous(), Yt[idx].contiguous()))
+            steps += 1
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    zv = torch.cat([net.forward(Xv[i:i + 8192].contiguous()) for i in range(0, nval, 8192)])
+    pred = zv > 0
+    acc = float((pred == (Yv > 0)).float().mean())
+    recall = float((pred & (Yv > 0)).float().sum() / (Yv > 0).float().sum().clamp(min=1))
+    precision = float((pred & (Yv > 0)).float().sum() / pred.float().sum().clamp(min=1))
+    log("training: %d steps of %d in %.2f s (%.0f samples/s); loss %.4f -> %.4f; held-out accuracy %.3f, "
+        "recall %.3f, precision %.3f" % (steps, bs, train_s, steps * bs / max(train_s, 1e-9),
+                                         np.mean(losses[:20]), np.mean(losses[-20:]), acc, recall, precision))
+    xb = Xt[:8192].contiguous()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        net.forward(xb)
+    torch.cuda.synchronize()
+    infer_us = 1e6 * (time.perf_counter() - t1) / 20
+
+    # ---- planner comparison on held-out layouts
+    def plan(seed, learned):
+        obs = W.make_obstacles(d, 40, "sphere", seed)
+        enc = W.sphere_encoding(obs)
+        R = P.Rrg(d, obs, stream=stream, point_capacity=args.plan_n + args.batch)
+        R.add_points(root_goal)
+        G = P.Graph(stream=stream, vertex_capacity=args.plan_n + args.batch)
+        R.connect(0, W.radius(2, d), G)
+        cu, cl, n_old, hist = 0, 0, 2, []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        while R.n < args.plan_n:
+            if learned:
+                cl = R.sample_learned(net, enc, seed + 1, 1, cl, 8192, args.batch // 2)
+                cu = R.sample(seed + 1, 0, cu, args.batch - args.batch // 2)
+            else:
+                cu = R.sample(seed + 1, 0, cu, args.batch)
+            n = R.n
+            R.connect(n_old, W.radius(n, d), G)
+            h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
+            gout = torch.empty(n, dtype=torch.float32, device=dev)
+            pout = torch.empty(n, dtype=torch.int32, device=dev)
+            G.replan(0, 1, h, True, g_out=gout, parent_out=pout)
+            hist.append((time.perf_counter() - t_start, n, float(gout[1].item())))
+            n_old = n
+        return hist
+
+    rows = []
+    for j in range(args.heldout):
+        seed = 30_000 + 10 * j
+        hp = plan(seed, False)
+        hl = plan(seed, True)
+        cost_p, t_p = hp[-1][2], hp[-1][0]
+        reach = [t for t, _, c in hl if c <= 1.01 * cost_p]
+        t_reach = reach[0] if reach else None
+        rows.append({"layout": seed, "plain_cost": round(cost_p, 5), "plain_s": round(t_p, 3),
+                     "learned_cost": round(hl[-1][2], 5), "learned_s": round(hl[-1][0], 3),
+                     "learned_s_to_1pct_of_plain": None if t_reach is None else round(t_reach, 3),
+                     "time_ratio": None if t_reach is None else round(t_reach / t_p, 3),
+                     "plain_cost_at_10pct_time": round(min(c for t, _, c in hp if t <= 0.1 * t_p + 1e-9)
+                                                       if any(t <= 0.1 * t_p for t, _, _ in hp) else hp[0][2], 5),
+                     "learned_cost_at_10pct_time": round(min(c for t, _, c in hl if t <= 0.1 * t_p + 1e-9)
+                                                         if any(t <= 0.1 * t_p for t, _, _ in hl) else hl[0][2], 5)})
+        log("layout %d: %s" % (seed, json.dumps(rows[-1])))
+    ratios = [r["time_ratio"] for r in rows if r["time_ratio"] is not None]
+    out = {
+        "metric": "Learned-proposal planner: wall time to within 1%% of the plain planner's %d-vertex path cost, "
+                  "as a fraction of the plain planner's time" % args.plan_n,
+        "value": round(float(np.median(ratios)), 4) if ratios else None, "unit": "fraction",
+        "higher_is_better": False, "n_gpus": 1, "dtype": "bf16 network / f32 Replan", "data": "synthetic",
+        "config": {"workload": "6D unit cube, 40 spheres; %d training layouts at %d vertices (%d samples each, "
+                               "positive-balanced); planner to %d vertices in batches of %d, Replan after each; "
+                               "learned = half of each batch the best of 8192 scored candidates" %
+                               (args.layouts, n_train, args.per_layout, args.plan_n, args.batch)},
+        "training": {"steps": steps, "batch": bs, "seconds": round(train_s, 3),
+                     "samples_per_s": round(steps * bs / max(train_s, 1e-9)), "loss_first": round(float(np.mean(losses[:20])), 4),
+                     "loss_last": round(float(np.mean(losses[-20:])), 4), "heldout_accuracy": round(acc, 4),
+                     "heldout_recall": round(recall, 4), "heldout_precision": round(precision, 4),
+                     "data_seconds": round(data_s, 2)},
+        "inference_us_per_8192": round(infer_us, 1),
+        "layouts": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,9 +404,16 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
-    ap.add_argument("--workload", choices=["plain6d", "multi"], default="plain6d",
-                    help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan")
+    ap.add_argument("--workload", choices=["plain6d", "multi", "learned"], default="plain6d",
+                    help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan; "
+                         "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
+    ap.add_argument("--layouts", type=int, default=100, help="learned: training layouts")
+    ap.add_argument("--per-layout", type=int, default=8192, help="learned: samples kept per layout")
+    ap.add_argument("--epochs", type=int, default=4, help="learned: training epochs")
+    ap.add_argument("--heldout", type=int, default=3, help="learned: held-out layouts for the planner")
+    ap.add_argument("--plan-n", type=int, default=1_000_000, help="learned: planner vertex count")
+    ap.add_argument("--batch", type=int, default=1000, help="learned: samples per planner batch")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary)
@@ -251,6 +424,9 @@ def main():
         sys.exit(2)
     if args.workload == "multi":
         bench_multi(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
 
     import numpy as np

@@ -185,12 +185,16 @@ __global__ void __launch_bounds__(kThreads) k_take(int64_t T, int64_t need, cons
   if (p == need - 1) *last = t + 1;
 }
 
-// Pass 1 (WRITE = false): count of earlier points within r of each new vertex.
-// Pass 2 (WRITE = true): their ids, ascending, at cptr[v - n_old].
+// Radius search over a grid of (256 new vertices) x (kChunk earlier points).
+// Pass 1 (WRITE = false): cc[row * nch + chunk] = candidates of that row in that
+// chunk.  Pass 2 (WRITE = true): their ids, ascending, from off[row * nch + chunk]
+// (the exclusive scan of cc in row-major order, so every row stays ascending in u).
+constexpr int64_t kChunk = 8192;
+
 template <int D, bool WRITE>
 __global__ void __launch_bounds__(kThreads) k_radius(int64_t n_old, int64_t n, const double* __restrict__ pts,
-                                                     double r2, int32_t* __restrict__ cnt,
-                                                     const int64_t* __restrict__ cptr, int32_t* __restrict__ cand_u,
+                                                     double r2, int32_t nch, int32_t* __restrict__ cc,
+                                                     const int64_t* __restrict__ off, int32_t* __restrict__ cand_u,
                                                      int32_t* __restrict__ cand_v) {
   __shared__ double tile[kTile * D];
   const int64_t vb = n_old + (int64_t)blockIdx.x * kThreads;
@@ -200,10 +204,13 @@ __global__ void __launch_bounds__(kThreads) k_radius(int64_t n_old, int64_t n, c
 #pragma unroll
   for (int k = 0; k < D; ++k) xv[k] = live ? pts[v * D + k] : 0.0;
   const int64_t vmax = (vb + kThreads < n ? vb + kThreads : n);  // u < vmax covers every thread
+  const int64_t c0 = (int64_t)blockIdx.y * kChunk;
+  const int64_t c1 = (c0 + kChunk < vmax ? c0 + kChunk : vmax);
+  const int64_t slot = (v - n_old) * nch + blockIdx.y;
   int32_t c = 0;
-  int64_t out = WRITE && live ? cptr[v - n_old] : 0;
-  for (int64_t u0 = 0; u0 < vmax; u0 += kTile) {
-    const int64_t m = (vmax - u0 < kTile ? vmax - u0 : kTile);
+  int64_t out = WRITE && live ? off[slot] : 0;
+  for (int64_t u0 = c0; u0 < c1; u0 += kTile) {
+    const int64_t m = (c1 - u0 < kTile ? c1 - u0 : kTile);
     __syncthreads();
     for (int64_t i = threadIdx.x; i < m * D; i += kThreads) tile[i] = pts[u0 * D + i];
     __syncthreads();
@@ -223,7 +230,7 @@ __global__ void __launch_bounds__(kThreads) k_radius(int64_t n_old, int64_t n, c
       }
     }
   }
-  if (!WRITE && live) cnt[v - n_old] = c;
+  if (!WRITE && live) cc[slot] = c;
 }
 
 // Segment test and cost of every candidate edge.
@@ -258,10 +265,10 @@ __global__ void __launch_bounds__(kThreads) k_compact(int64_t m, const int32_t* 
   cost[kpos[j]] = ccost[j];
 }
 
-__global__ void __launch_bounds__(kThreads) k_row_ptr(int64_t rows, const int64_t* __restrict__ cptr,
+__global__ void __launch_bounds__(kThreads) k_row_ptr(int64_t rows, int32_t nch, const int64_t* __restrict__ off,
                                                       const int64_t* __restrict__ kpos, int64_t* __restrict__ rp) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i <= rows) rp[i] = kpos[cptr[i]];
+  if (i <= rows) rp[i] = kpos[off[i * nch]];
 }
 
 template <int D>
@@ -386,6 +393,7 @@ struct pirrt_rrg {
   int32_t* cnt = nullptr;
   int64_t* cptr = nullptr;
   int64_t rows_cap = 0;
+  int64_t rp_cap = 0;
   int32_t* cand_u = nullptr;
   int32_t* cand_v = nullptr;
   int32_t* keep = nullptr;
@@ -505,14 +513,15 @@ void launch_take(pirrt_rrg* R, int64_t T, int64_t need, double* dst) {
 }
 
 template <int D>
-void launch_radius(pirrt_rrg* R, int64_t n_old, double r2, bool write) {
+void launch_radius(pirrt_rrg* R, int64_t n_old, double r2, int32_t nch, bool write) {
   const int64_t rows = R->n - n_old;
+  const dim3 grid(blocks(rows), (unsigned)nch);
   if (write)
-    hipLaunchKernelGGL((k_radius<D, true>), dim3(blocks(rows)), dim3(kThreads), 0, R->stream, n_old, R->n, R->pts,
-                       r2, R->cnt, R->cptr, R->cand_u, R->cand_v);
+    hipLaunchKernelGGL((k_radius<D, true>), grid, dim3(kThreads), 0, R->stream, n_old, R->n, R->pts, r2, nch, R->cnt,
+                       R->cptr, R->cand_u, R->cand_v);
   else
-    hipLaunchKernelGGL((k_radius<D, false>), dim3(blocks(rows)), dim3(kThreads), 0, R->stream, n_old, R->n, R->pts,
-                       r2, R->cnt, R->cptr, R->cand_u, R->cand_v);
+    hipLaunchKernelGGL((k_radius<D, false>), grid, dim3(kThreads), 0, R->stream, n_old, R->n, R->pts, r2, nch,
+                       R->cnt, R->cptr, R->cand_u, R->cand_v);
 }
 
 template <int D>
@@ -544,30 +553,38 @@ int build_rows(pirrt_rrg* R, int64_t n_old, double radius, int64_t* nnz) {
   hipStream_t s = R->stream;
   int rc;
   *nnz = 0;
-  if (rows + 1 > R->rows_cap) {
+  // per-(row, chunk) counts and their scan: cnt / cptr hold rows * nch (+1) entries
+  const int32_t nch = (int32_t)((R->n + kChunk - 1) / kChunk);
+  const int64_t cells = rows * nch;
+  if (cells + 1 > R->rows_cap) {
     rfree(R->cnt);
     rfree(R->cptr);
-    rfree(R->rp);
     R->rows_cap = 0;
-    const int64_t c = rows + 1 + (rows + 1) / 2;
-    if (!ralloc(&R->cnt, c) || !ralloc(&R->cptr, c) || !ralloc(&R->rp, c))
+    const int64_t c = cells + 1 + (cells + 1) / 2;
+    if (!ralloc(&R->cnt, c) || !ralloc(&R->cptr, c))
       return rfail(R, PIRRT_ENOMEM, "device allocation of row offsets failed");
     R->rows_cap = c;
+  }
+  if (rows + 1 > R->rp_cap) {
+    rfree(R->rp);
+    R->rp_cap = 0;
+    if (!ralloc(&R->rp, rows + 1 + (rows + 1) / 2)) return rfail(R, PIRRT_ENOMEM, "device allocation of rows failed");
+    R->rp_cap = rows + 1 + (rows + 1) / 2;
   }
   if (rows == 0) {
     RHIP(R, hipMemsetAsync(R->rp, 0, sizeof(int64_t), s));
     RHIP(R, hipStreamSynchronize(s));
     return PIRRT_OK;
   }
-  if ((rc = ensure_scan(R, rows + 1))) return rc;
+  if ((rc = ensure_scan(R, cells + 1))) return rc;
   const double r2 = radius * radius;
-#define RAD_COUNT(D) launch_radius<D>(R, n_old, r2, false)
+#define RAD_COUNT(D) launch_radius<D>(R, n_old, r2, nch, false)
   PIRRT_BY_DIM(R->d, RAD_COUNT);
 #undef RAD_COUNT
   RHIP(R, hipGetLastError());
-  scan_i32_to_i64(R->cnt, rows, R->cptr, R->scan, s);
+  scan_i32_to_i64(R->cnt, cells, R->cptr, R->scan, s);
   RHIP(R, hipGetLastError());
-  RHIP(R, hipMemcpyAsync(R->host, R->cptr + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RHIP(R, hipMemcpyAsync(R->host, R->cptr + cells, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RHIP(R, hipStreamSynchronize(s));
   const int64_t m = R->host[0];
   if (m > ((int64_t)1 << 40)) return rdev(R, hipErrorUnknown, "candidate count out of range");
@@ -582,7 +599,7 @@ int build_rows(pirrt_rrg* R, int64_t n_old, double radius, int64_t* nnz) {
   }
   if ((rc = ensure_scan(R, m + 1))) return rc;
   if (m > 0) {
-#define RAD_WRITE(D) launch_radius<D>(R, n_old, r2, true)
+#define RAD_WRITE(D) launch_radius<D>(R, n_old, r2, nch, true)
     PIRRT_BY_DIM(R->d, RAD_WRITE);
 #undef RAD_WRITE
     RHIP(R, hipGetLastError());
@@ -598,7 +615,7 @@ int build_rows(pirrt_rrg* R, int64_t n_old, double radius, int64_t* nnz) {
                        R->col, R->cost);
     RHIP(R, hipGetLastError());
   }
-  hipLaunchKernelGGL(k_row_ptr, dim3(blocks(rows + 1)), dim3(kThreads), 0, s, rows, R->cptr, R->kpos, R->rp);
+  hipLaunchKernelGGL(k_row_ptr, dim3(blocks(rows + 1)), dim3(kThreads), 0, s, rows, nch, R->cptr, R->kpos, R->rp);
   RHIP(R, hipGetLastError());
   RHIP(R, hipMemcpyAsync(R->host, R->kpos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RHIP(R, hipStreamSynchronize(s));

@@ -298,6 +298,20 @@ def multi_problem_spec(index: int, base_seed: int = 1000, n_min: int = 5000,
     return ProblemSpec(index, d, max(n, 3), obs, base_seed + 200_000 + index)
 
 
+def sphere_encoding(obs: Obstacles, slots: int = 40) -> np.ndarray:
+    """Input format of the learned proposal: the spheres' (centre, radius) in order,
+    zero-padded to `slots` entries of d + 1 values (binary32)."""
+    d = obs.d
+    enc = np.zeros(slots * (d + 1), np.float32)
+    k = 0
+    for o in range(len(obs.kind)):
+        if obs.kind[o] == 0 and k < slots:
+            enc[k * (d + 1):k * (d + 1) + d] = obs.centre[o]
+            enc[k * (d + 1) + d] = obs.size[o, 0]
+            k += 1
+    return enc
+
+
 def path_graph(n: int, costs: np.ndarray) -> Batch:
     """A path 0-1-2-...-(n-1); costs[i] is the cost of edge (i, i+1)."""
     row_ptr = np.zeros(n + 1, np.int64)
