@@ -141,6 +141,18 @@ int pirrt_insert_batch(pirrt_graph* g, int32_t n_new, const int64_t* row_ptr, co
 int pirrt_replan(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uint32_t flags,
                  float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
 
+/*
+ * Autotuner: runs the Replan this call describes (arguments as pirrt_replan) once
+ * per kernel configuration -- the Improve / promising-set row split (lanes per row
+ * x 16-byte quads in flight: 16x1, 8x2, 4x4, 8x1) and the scope of the walk
+ * Evaluate's stamps (device, workgroup) -- each from the current policy, keeps the
+ * fastest for later calls on this handle and restores the policy (results never
+ * depend on the configuration).  *config (nullable) receives the index chosen,
+ * row split + 4 x (workgroup-scope stamps).
+ */
+int pirrt_tune(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uint32_t flags, int mem_kind,
+               int32_t* config);
+
 /* Copies the stored policy out: g, parent and parent-edge cost (each may be NULL). */
 int pirrt_get_policy(pirrt_graph* g, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind);
 
@@ -216,6 +228,10 @@ int64_t pirrt_batch_problem_offset(const pirrt_batch* b, int32_t problem);
  */
 int pirrt_batch_replan(pirrt_batch* b, const int32_t* roots, const int32_t* goals, const float* h,
                        uint32_t flags, float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
+
+/* As pirrt_tune for the batch's Replan of every problem. */
+int pirrt_batch_tune(pirrt_batch* b, const int32_t* roots, const int32_t* goals, const float* h, uint32_t flags,
+                     int mem_kind, int32_t* config);
 
 /* Policy of every problem (concatenated, local parent ids). */
 int pirrt_batch_get_policy(pirrt_batch* b, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind);

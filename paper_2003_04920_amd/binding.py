@@ -34,7 +34,7 @@ EXPORTS = [
     "pirrt_rrg_heuristic", "pirrt_rrg_last_error",
     "pirrt_mlp_num_params", "pirrt_mlp_create", "pirrt_mlp_destroy", "pirrt_mlp_set_params", "pirrt_mlp_get_params",
     "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
-    "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned",
+    "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned", "pirrt_tune", "pirrt_batch_tune",
 ]
 
 
@@ -137,6 +137,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_mlp_in_dim": (i32, [vp]),
         "pirrt_rrg_sample_learned": (cint, [vp, vp, vp, i32, ctypes.c_uint64, u32, ctypes.POINTER(ctypes.c_uint64),
                                             i32, i32]),
+        "pirrt_tune": (cint, [vp, i32, i32, vp, u32, cint, ctypes.POINTER(i32)]),
+        "pirrt_batch_tune": (cint, [vp, vp, vp, vp, u32, cint, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -266,6 +268,14 @@ class Graph:
         d["rc"] = rc
         return g_out, parent_out, d
 
+    def tune(self, root: int, goal: int, h=None, prune: bool = True) -> int:
+        """Autotunes the kernel configuration on this Replan; returns its index."""
+        h = _check_dtype(h, np.float32, "float32")
+        cfg = ctypes.c_int32(-1)
+        self._check(self._lib.pirrt_tune(self._h, int(root), int(goal), _ptr(h), 0 if prune else PIRRT_NO_PRUNE,
+                                         _mem_kind(h), ctypes.byref(cfg)))
+        return int(cfg.value)
+
     def get_policy(self, device=None):
         n = self.n
         if device is not None:
@@ -388,6 +398,16 @@ class Batch:
         self._check(rc, allow=(PIRRT_ENOTCONVERGED,) if allow_not_converged else ())
         stats = [dict(st[i].as_dict(), rc=rc) for i in range(P)]
         return g_out, parent_out, stats
+
+    def tune(self, roots, goals, h=None, prune: bool = True) -> int:
+        """Autotunes the kernel configuration on this batch Replan; returns its index."""
+        roots = np.ascontiguousarray(roots, np.int32)
+        goals = np.ascontiguousarray(goals, np.int32)
+        h = _check_dtype(h, np.float32, "float32")
+        cfg = ctypes.c_int32(-1)
+        self._check(self._lib.pirrt_batch_tune(self._h, _ptr(roots), _ptr(goals), _ptr(h),
+                                               0 if prune else PIRRT_NO_PRUNE, _mem_kind(h), ctypes.byref(cfg)))
+        return int(cfg.value)
 
     def get_policy(self, device=None):
         n = self.n

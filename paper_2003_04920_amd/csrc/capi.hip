@@ -1002,6 +1002,59 @@ int stage_h(pirrt_graph* G, const float* h, int mem_kind, const float** out) {
   return PIRRT_OK;
 }
 
+// Autotuner: the Replan of the call is run once per kernel configuration -- the
+// Improve / mark row split (lanes per row x quads in flight) and the scope of the
+// walk's Evaluate stamps (device or workgroup) -- each from the same policy, the
+// fastest kept.  A first pass over the configurations captures their loop graphs;
+// the second is timed.  The policy and the root marks are restored at the end.
+constexpr int kTuneConfigs = kRowVariants * 2;
+
+int tune(pirrt_graph* G, int32_t P, const int32_t* rid, const int32_t* rs, const int32_t* gs, const float* hdev,
+         bool prune, int32_t* config) {
+  hipStream_t s = G->stream;
+  const size_t n = (size_t)G->n;
+  // the policy goes to the spare copies (free here: h is staged in hbuf already)
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->g2, G->g, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->parent2, G->parent, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost2, G->pcost, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  const std::vector<int32_t> roots0 = G->hroots;
+  int rc;
+  auto restore = [&]() -> int {
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->g, G->g2, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->parent, G->parent2, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost, G->pcost2, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    G->hroots = roots0;
+    G->nroots = (int32_t)roots0.size();
+    if (G->nroots > 0)
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, roots0.data(), sizeof(int32_t) * roots0.size(), hipMemcpyHostToDevice,
+                                    s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    return PIRRT_OK;
+  };
+  double best = 1e300;
+  int bestc = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = 0; c < kTuneConfigs; ++c) {
+      G->row_variant = c % kRowVariants;
+      G->walk_coherent = c / kRowVariants == 0;
+      if ((rc = restore())) return rc;
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = run_replan(G, P, rid, rs, gs, hdev, prune, false, nullptr);
+      if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (pass == 1 && ms < best) {
+        best = ms;
+        bestc = c;
+      }
+    }
+  }
+  G->row_variant = bestc % kRowVariants;
+  G->walk_coherent = bestc / kRowVariants == 0;
+  if ((rc = restore())) return rc;
+  if (config) *config = bestc;
+  return PIRRT_OK;
+}
+
 pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   *rc_out = PIRRT_OK;
   pirrt_config c;
@@ -1187,6 +1240,20 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   if (stats) *stats = st;
   return keep;
+}
+
+int pirrt_tune(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uint32_t flags, int mem_kind,
+               int32_t* config) {
+  int rc = guard(G);
+  if (rc) return rc;
+  if (G->batched) return fail(G, PIRRT_EINVAL, "this handle holds a batch of problems");
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if (G->n <= 0) return fail(G, PIRRT_EINVAL, "empty graph");
+  if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
+  const float* hdev = nullptr;
+  if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
+  return tune(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 
 int pirrt_get_policy(pirrt_graph* G, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {
@@ -1424,6 +1491,35 @@ int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goal
   }
   HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   return keep;
+}
+
+int pirrt_batch_tune(pirrt_batch* B, const int32_t* roots, const int32_t* goals, const float* h, uint32_t flags,
+                     int mem_kind, int32_t* config) {
+  if (!B) return PIRRT_EINVAL;
+  pirrt_graph* G = B->G;
+  int rc = guard(G);
+  if (rc) return rc;
+  const int32_t P = (int32_t)G->pbase.size() - 1;
+  if (P <= 0) return fail(G, PIRRT_EINVAL, "empty batch");
+  if (!roots || !goals) return fail(G, PIRRT_EINVAL, "roots or goals is NULL");
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  for (int32_t i = 0; i < P; ++i) {
+    const int64_t b = G->pbase[(size_t)i], len = G->pbase[(size_t)i + 1] - b;
+    if (roots[i] < 0 || roots[i] >= len || goals[i] < 0 || goals[i] >= len)
+      return fail(G, PIRRT_EINVAL, "root or goal out of range in problem " + std::to_string(i));
+  }
+  if (G->renumber_pending && (rc = renumber(G))) return rc;
+  if ((rc = upload_bases(G))) return rc;
+  std::vector<int32_t> rid((size_t)P), rs((size_t)P), gs((size_t)P);
+  for (int32_t i = 0; i < P; ++i) {
+    const int64_t b = G->pbase[(size_t)i];
+    rid[(size_t)i] = (int32_t)(b + roots[i]);
+    rs[(size_t)i] = G->hslot[(size_t)(b + roots[i])];
+    gs[(size_t)i] = G->hslot[(size_t)(b + goals[i])];
+  }
+  const float* hdev = nullptr;
+  if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  return tune(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 
 int pirrt_batch_get_policy(pirrt_batch* B, float* g_out, int32_t* parent_out, float* pcost_out, int mem_kind) {

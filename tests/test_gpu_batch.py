@@ -245,3 +245,17 @@ def test_batch_invalid_arguments(P):
     for i, pr in enumerate(probs):
         _, rc, st, fin = oracle_run(pr)
         check_problem("after errors", g, parent, B.offsets[i], pr, fin.g, fin.parent)
+
+
+def test_batch_tune(P):
+    probs = problem_set()[:6]
+    B = build(P, probs)
+    cfg = B.tune([p.root for p in probs], [p.goal for p in probs], full_h(probs))
+    assert 0 <= cfg < 8
+    g, parent, stats = B.replan([p.root for p in probs], [p.goal for p in probs], full_h(probs))
+    off = B.offsets
+    for i, pr in enumerate(probs):
+        _, rc, st, fin = oracle_run(pr)
+        check_problem("tuned", g, parent, off[i], pr, fin.g, fin.parent)
+        for k in STAT_KEYS:
+            assert stats[i][k] == st[k], (pr.name, k)

@@ -325,3 +325,34 @@ def test_level_synchronous_evaluator_agrees(P, monkeypatch):
     run_both(P, wl.batches, {i: (0, 1) for i in range(4)}, wl.heuristic, True)
     b = lattice_batch(40, 0.9, 5)
     run_both(P, [b], {0: (0, 1)}, None, False)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("coherent", [0, 1])
+def test_every_kernel_configuration(P, monkeypatch, variant, coherent):
+    """The autotuner may choose any row split and stamp scope: each gives the
+    oracle's results."""
+    monkeypatch.setenv("PIRRT_ROW_VARIANT", str(variant))
+    monkeypatch.setenv("PIRRT_WALK_COHERENT", str(coherent))
+    wl = W.batched_6d(batches=3, batch=800, seed=101)
+    run_both(P, wl.batches, {0: (0, 1), 2: (0, 1)}, wl.heuristic, True, check_insert=False)
+
+
+def test_tune_restores_policy_and_keeps_results(P):
+    wl = W.plain_2d()
+    G = gpu_graph(P)
+    G.insert_rows(wl.batches[0])
+    g0, p0, c0 = G.get_policy()
+    h = wl.heuristic(G.n)
+    cfg = G.tune(0, 1, h, True)
+    assert 0 <= cfg < 8
+    g1, p1, c1 = G.get_policy()
+    assert np.array_equal(g0.view(np.uint32), g1.view(np.uint32)) and np.array_equal(p0, p1)
+    assert np.array_equal(c0.view(np.uint32), c1.view(np.uint32))
+    R = O.Graph()
+    assert R.insert_batch(wl.batches[0]) == 0
+    gg, pp, sg = G.replan(0, 1, h, True)
+    rc, so = R.replan(0, 1, h, True)
+    st = R.state()
+    assert_same_policy("after tune", gg, pp, st.g, st.parent)
+    assert_same_stats("after tune", sg, so)
