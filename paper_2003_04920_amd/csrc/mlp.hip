@@ -199,11 +199,22 @@ __global__ void k_adam(int64_t np, float* __restrict__ P, const float* __restric
   P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-__global__ void k_refresh(const float* __restrict__ P, uint16_t* __restrict__ W1b, uint16_t* __restrict__ W2b,
-                          uint16_t* __restrict__ w3b) {
+// bf16 copies of the weights: W2b row-major (the backward product dZ2 W2^T reads its
+// rows contiguously), W1t / W2t transposed (the forward products read their columns
+// contiguously).
+__global__ void k_refresh(const float* __restrict__ P, uint16_t* __restrict__ W1t, uint16_t* __restrict__ W2b,
+                          uint16_t* __restrict__ W2t, uint16_t* __restrict__ w3b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (int64_t)kIn * kHidden) W1b[i] = to_bf16(P[kOffW1 + i]);
-  if (i < (int64_t)kHidden * kHidden) W2b[i] = to_bf16(P[kOffW2 + i]);
+  if (i < (int64_t)kIn * kHidden) {
+    const int64_t k = i / kHidden, n = i % kHidden;
+    W1t[n * kIn + k] = to_bf16(P[kOffW1 + i]);
+  }
+  if (i < (int64_t)kHidden * kHidden) {
+    const int64_t k = i / kHidden, n = i % kHidden;
+    const uint16_t b = to_bf16(P[kOffW2 + i]);
+    W2b[i] = b;
+    W2t[n * kHidden + k] = b;
+  }
   if (i < kHidden) w3b[i] = to_bf16(P[kOffW3 + i]);
 }
 
@@ -221,8 +232,9 @@ struct pirrt_mlp {
   float* G = nullptr;
   float* m = nullptr;
   float* v = nullptr;
-  uint16_t* W1b = nullptr;
-  uint16_t* W2b = nullptr;
+  uint16_t* W1t = nullptr;  // bf16 W1 transposed [kHidden x kIn]
+  uint16_t* W2b = nullptr;  // bf16 W2 [kHidden x kHidden]
+  uint16_t* W2t = nullptr;  // bf16 W2 transposed
   uint16_t* w3b = nullptr;
   float* xin = nullptr;   // staging of host features
   float* yin = nullptr;
@@ -280,7 +292,8 @@ void free_dev(T*& p) {
 }
 
 void release(pirrt_mlp* N) {
-  free_dev(N->P); free_dev(N->G); free_dev(N->m); free_dev(N->v); free_dev(N->W1b); free_dev(N->W2b);
+  free_dev(N->P); free_dev(N->G); free_dev(N->m); free_dev(N->v); free_dev(N->W1t); free_dev(N->W2b);
+  free_dev(N->W2t);
   free_dev(N->w3b); free_dev(N->xin); free_dev(N->yin); free_dev(N->X); free_dev(N->Z1); free_dev(N->A1);
   free_dev(N->Z2); free_dev(N->A2); free_dev(N->z); free_dev(N->dz); free_dev(N->dZ2); free_dev(N->dZ1);
   free_dev(N->dloss);
@@ -330,15 +343,13 @@ int stage_inputs(pirrt_mlp* N, int32_t B, int32_t Bp, const float* x, const floa
 
 void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z) {
   hipStream_t s = N->stream;
-  GemmArgs g1{Bp, kHidden, kIn, N->X, kIn, 1, N->W1b, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
+  // element (k, n) of W1 is W1t[n * kIn + k]: contiguous in k
+  GemmArgs g1{Bp, kHidden, kIn, N->X, kIn, 1, N->W1t, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
               N->A1};
-  // W1b is stored [kIn x kHidden] row-major: element (k, n) at k * kHidden + n
-  g1.sbk = kHidden;
-  g1.sbn = 1;
-  launch_gemm(g1, true, false, kEpiFwd, s);
-  GemmArgs g2{Bp, kHidden, kHidden, N->A1, kHidden, 1, N->W2b, kHidden, 1, N->P + kOffB2, nullptr,
+  launch_gemm(g1, true, true, kEpiFwd, s);
+  GemmArgs g2{Bp, kHidden, kHidden, N->A1, kHidden, 1, N->W2t, 1, kHidden, N->P + kOffB2, nullptr,
               keep_z ? N->Z2 : nullptr, N->A2};
-  launch_gemm(g2, true, false, kEpiFwd, s);
+  launch_gemm(g2, true, true, kEpiFwd, s);
 }
 
 // Forward + loss + gradients into N->G (the loss lands in N->dloss).
@@ -413,8 +424,9 @@ int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
   N->eps = cfg->eps;
   const int64_t bc = N->bcap;
   bool ok = malloc_dev(&N->P, kNumParams) && malloc_dev(&N->G, kNumParams) && malloc_dev(&N->m, kNumParams) &&
-            malloc_dev(&N->v, kNumParams) && malloc_dev(&N->W1b, (int64_t)kIn * kHidden) &&
-            malloc_dev(&N->W2b, (int64_t)kHidden * kHidden) && malloc_dev(&N->w3b, kHidden) &&
+            malloc_dev(&N->v, kNumParams) && malloc_dev(&N->W1t, (int64_t)kIn * kHidden) &&
+            malloc_dev(&N->W2b, (int64_t)kHidden * kHidden) && malloc_dev(&N->W2t, (int64_t)kHidden * kHidden) &&
+            malloc_dev(&N->w3b, kHidden) &&
             malloc_dev(&N->xin, (int64_t)N->max_batch * N->in_dim) && malloc_dev(&N->yin, N->max_batch) &&
             malloc_dev(&N->X, bc * kIn) && malloc_dev(&N->Z1, bc * kHidden) && malloc_dev(&N->A1, bc * kHidden) &&
             malloc_dev(&N->Z2, bc * kHidden) && malloc_dev(&N->A2, bc * kHidden) && malloc_dev(&N->z, bc) &&
@@ -429,8 +441,9 @@ int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
     ok = hipMemset(N->P, 0, sizeof(float) * kNumParams) == hipSuccess &&
          hipMemset(N->m, 0, sizeof(float) * kNumParams) == hipSuccess &&
          hipMemset(N->v, 0, sizeof(float) * kNumParams) == hipSuccess &&
-         hipMemset(N->W1b, 0, sizeof(uint16_t) * kIn * kHidden) == hipSuccess &&
+         hipMemset(N->W1t, 0, sizeof(uint16_t) * kIn * kHidden) == hipSuccess &&
          hipMemset(N->W2b, 0, sizeof(uint16_t) * kHidden * kHidden) == hipSuccess &&
+         hipMemset(N->W2t, 0, sizeof(uint16_t) * kHidden * kHidden) == hipSuccess &&
          hipMemset(N->w3b, 0, sizeof(uint16_t) * kHidden) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -467,8 +480,8 @@ int pirrt_mlp_set_params(pirrt_mlp* N, const float* params, int mem_kind) {
                          mem_kind == PIRRT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
   MHIP(N, hipMemsetAsync(N->m, 0, sizeof(float) * kNumParams, s));
   MHIP(N, hipMemsetAsync(N->v, 0, sizeof(float) * kNumParams, s));
-  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, s, N->P, N->W1b, N->W2b,
-                     N->w3b);
+  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, s, N->P, N->W1t, N->W2b,
+                     N->W2t, N->w3b);
   MHIP(N, hipGetLastError());
   MHIP(N, hipStreamSynchronize(s));
   N->t = 0;
@@ -536,8 +549,8 @@ int pirrt_mlp_train_step(pirrt_mlp* N, int32_t B, const float* x, const float* y
   const float c1 = 1.0f - powf(N->beta1, (float)N->t), c2 = 1.0f - powf(N->beta2, (float)N->t);
   hipLaunchKernelGGL(k_adam, dim3(nblocks(kNumParams)), dim3(kThreads), 0, N->stream, kNumParams, N->P, N->G, N->m,
                      N->v, N->lr, N->beta1, N->beta2, N->eps, c1, c2);
-  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, N->stream, N->P, N->W1b,
-                     N->W2b, N->w3b);
+  hipLaunchKernelGGL(k_refresh, dim3(nblocks((int64_t)kIn * kHidden)), dim3(kThreads), 0, N->stream, N->P, N->W1t,
+                     N->W2b, N->W2t, N->w3b);
   MHIP(N, hipGetLastError());
   MHIP(N, hipMemcpyAsync(N->hloss, N->dloss, sizeof(float), hipMemcpyDeviceToHost, N->stream));
   MHIP(N, hipStreamSynchronize(N->stream));
