@@ -840,6 +840,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.pcost = G->pcost;
   sa.ctr = G->ctr;
   sa.dlist = G->dlist;
+  sa.plist = G->fr1;  // free during a Replan (the level evaluator's frontiers run only between marks)
   sa.tiles = G->tiles;
   WalkArgs& wa = L.wa;
   wa.n = n;

@@ -45,7 +45,8 @@ struct LoopCtl {
   int32_t any_eval;     // some problem needs an Evaluate after this iteration
   int32_t ndomain;      // entries of the compacted Improve domain of this iteration
   int32_t ntiles;       // batches: entries of the active tile list; -1 = every tile
-  int32_t pad[2];
+  int32_t npromising;   // single graphs: entries of the compacted promising set
+  int32_t pad;
 };
 
 // Batches run their per-slot kernels over tiles of kTileSlots consecutive slots;

@@ -121,6 +121,7 @@ __global__ void k_after_eval(int32_t P, ProblemState* __restrict__ ps, const flo
     ctl->any_active = any;
     ctl->any_eval = 0;
     ctl->ndomain = 0;
+    ctl->npromising = 0;
     ctl->ntiles = prob ? count : -1;
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
   }

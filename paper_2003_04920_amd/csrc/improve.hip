@@ -223,6 +223,99 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
 
 // Improve over the compacted domain: group i takes entry i of dlist; workgroups past
 // the domain's end leave at once.
+// Single graphs mark in two steps.  k_promising_list tests kListPer consecutive
+// vertices per thread (16-byte loads of g and h), stamps the promising ones and lists
+// them (one atomic per workgroup); k_mark_rows then stamps the neighbours of the
+// listed vertices only, so the row work follows |P| rather than n.
+__global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, const ProblemState* __restrict__ ps,
+                                                            LoopCtl* __restrict__ ctl, const float* __restrict__ g,
+                                                            const float* __restrict__ h,
+                                                            uint8_t* __restrict__ stamp, int32_t* __restrict__ plist,
+                                                            IterCounters* __restrict__ ctr) {
+  if (ctl->any_active == 0) return;  // the problem has converged
+  const uint8_t ep = (uint8_t)ctl->epoch;
+  const float G = ps[0].thr;
+  const int64_t v0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kListPer;
+  uint32_t mask = 0;
+  if (v0 + kListPer <= n) {
+    const float4* g4 = reinterpret_cast<const float4*>(g + v0);
+    const float4* h4 = reinterpret_cast<const float4*>(h ? h + v0 : g);
+#pragma unroll
+    for (int q = 0; q < kListPer / 4; ++q) {
+      const float4 a = g4[q];
+      const float4 b = h ? h4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (add_rn(a.x, b.x) < G) mask |= 1u << (4 * q);
+      if (add_rn(a.y, b.y) < G) mask |= 1u << (4 * q + 1);
+      if (add_rn(a.z, b.z) < G) mask |= 1u << (4 * q + 2);
+      if (add_rn(a.w, b.w) < G) mask |= 1u << (4 * q + 3);
+    }
+  } else {
+    for (int i = 0; i < kListPer && v0 + i < n; ++i)
+      if (add_rn(g[v0 + i], h ? h[v0 + i] : 0.0f) < G) mask |= 1u << i;
+  }
+  __shared__ int wsum[kThreads / kWave];
+  __shared__ int base;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int c = __popc(mask);
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      const int x = wsum[w];
+      wsum[w] = t;
+      t += x;
+    }
+    base = t ? atomicAdd(&ctl->npromising, t) : 0;
+    if (t) atomicAdd(&ctr[blockIdx.x % kCounterSlots].nP, t);
+  }
+  __syncthreads();
+  int pos = base + wsum[wid] + incl - c;
+  while (mask) {
+    const int i = __ffs(mask) - 1;
+    mask &= mask - 1;
+    stamp[v0 + i] = ep;
+    plist[pos++] = (int32_t)(v0 + i);
+  }
+}
+
+template <int GW, int Q, typename Idx>
+__global__ void __launch_bounds__(kThreads) k_mark_rows(const LoopCtl* __restrict__ ctl,
+                                                       const int32_t* __restrict__ plist,
+                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       uint8_t* __restrict__ stamp) {
+  if (ctl->any_active == 0) return;
+  const int64_t cnt = ctl->npromising;
+  const int64_t gi = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
+  if (gi >= cnt) return;  // no barrier below: groups leave independently
+  const uint8_t ep = (uint8_t)ctl->epoch;
+  const int gl = threadIdx.x % GW;
+  const int32_t x = plist[gi];
+  const Idx ra = (Idx)rp[x], rb = (Idx)rp[x + 1];
+  const int4* col4 = reinterpret_cast<const int4*>(col);
+  const Idx qa = ra >> 2, qb = (rb + 3) >> 2;
+  for (Idx k = qa + gl; k < qb; k += GW * Q) {
+    int4 w[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) w[q] = col4[k + q * GW < qb ? k + q * GW : qa];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (k + q * GW >= qb) continue;
+      const Idx j0 = (k + q * GW) * 4;
+      const int32_t u[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (j0 + e >= ra && j0 + e < rb) stamp[u[e]] = ep;
+    }
+  }
+}
+
 template <int GW, int Q, typename Idx, bool kBatched>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* __restrict__ prob,
                                                      const ProblemState* __restrict__ ps,
@@ -335,7 +428,19 @@ inline dim3 batch_grid(int64_t n, int per_block) {
 
 template <int GW, int U, bool B>
 void launch_mark_t(const StepArgs& a, hipStream_t s) {
-  const dim3 grid = B ? batch_grid(a.n, kThreads / GW) : grid_for(a.n, GW);
+  if (!B) {  // single graph: promising list, then the rows of the listed vertices
+    const int64_t per_block = (int64_t)kThreads * kListPer;
+    hipLaunchKernelGGL(k_promising_list, dim3((unsigned)((a.n + per_block - 1) / per_block)), dim3(kThreads), 0, s,
+                       a.n, a.ps, a.ctl, a.g, a.h, a.stamp, a.plist, a.ctr);
+    if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
+      hipLaunchKernelGGL((k_mark_rows<GW, U, uint32_t>), grid_for(a.n, GW), dim3(kThreads), 0, s, a.ctl, a.plist,
+                         a.rp, a.col, a.stamp);
+    else
+      hipLaunchKernelGGL((k_mark_rows<GW, U, int64_t>), grid_for(a.n, GW), dim3(kThreads), 0, s, a.ctl, a.plist, a.rp,
+                         a.col, a.stamp);
+    return;
+  }
+  const dim3 grid = batch_grid(a.n, kThreads / GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
     hipLaunchKernelGGL((k_mark<GW, U, uint32_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g, a.h,
                        a.rp, a.col, a.stamp, a.ctr, a.tiles);

@@ -151,6 +151,7 @@ struct StepArgs {
   float* pcost;
   IterCounters* ctr;         // kCounterSlots copies per problem
   int32_t* dlist;            // compacted Improve domain (n entries of room)
+  int32_t* plist;            // single graphs: compacted promising set (n entries of room)
   const int32_t* tiles;      // batches: active tile list (see LoopCtl::ntiles)
 };
 constexpr int kRowVariants = 4;
