@@ -113,6 +113,7 @@ struct pirrt_graph {
   std::vector<int32_t> hslot;
   int64_t reorder_n = 0;          // vertex count at the last renumbering
   double reorder_growth = 1.25;   // renumber when n grows by this factor (0 = never)
+  bool clustered_order = true;    // seed clusters on top of the breadth-first order
   bool renumber_pending = false;  // batch problems added since the last renumbering
   // problems: problem i holds caller ids [pbase[i], pbase[i+1]) and the same slots
   bool batched = false;
@@ -560,6 +561,25 @@ int renumber(pirrt_graph* G) {
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   for (int32_t i = 0; i < P; ++i)
     if (cnt[(size_t)i] != G->pbase[(size_t)i + 1]) return fail_device(G, hipErrorUnknown, "renumbering lost vertices");
+  if (G->clustered_order) {
+    // seeds by Luby rounds, then clusters in the breadth-first order of their seeds
+    int32_t* state = G->pending;
+    int32_t* win = G->add;
+    HIP_OR_FAIL(G, hipMemsetAsync(state, 0, sizeof(int32_t) * (size_t)n, s));
+    for (int round = 0;; ++round) {
+      HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[1], 0, sizeof(int32_t), s));
+      launch_mis_round(n, G->rp, G->col, state, win, &G->dcount[1], s);
+      HIP_OR_FAIL(G, hipGetLastError());
+      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[1], &G->dcount[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(G, hipStreamSynchronize(s));
+      if (G->host->count[1] == 0) break;
+      if (round > n) return fail_device(G, hipErrorUnknown, "independent-set rounds did not finish");
+    }
+    launch_cluster_order(n, G->rp, G->col, state, order, G->fr1, G->fr0, G->deg, G->rp2, G->child_ptr, G->lvl,
+                         G->scan_scratch, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    order = G->lvl;
+  }
   PermuteArgs a;
   a.n = n;
   a.order = order;
@@ -1144,6 +1164,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   }
   const char* growth = getenv("PIRRT_REORDER_GROWTH");
   if (growth) G->reorder_growth = atof(growth);
+  const char* ord = getenv("PIRRT_ORDER");
+  if (ord) G->clustered_order = strcmp(ord, "bfs") != 0;
   const char* tr = getenv("PIRRT_TRACE");
   G->trace = tr && atoi(tr) > 0;
   const char* ev = getenv("PIRRT_EVALUATE");

@@ -73,6 +73,14 @@ void launch_bfs_discover(int32_t fsize, const int32_t* frontier, int32_t tag, co
 void launch_bfs_order_level(int32_t fsize, int32_t m, const int32_t* cand, const int32_t* key, int32_t* hist,
                             int64_t* off, int32_t* cursor, int32_t* next, const int32_t* prob, int32_t* pstart,
                             int32_t* pcnt, int32_t* order, void* scan_scratch, hipStream_t s);
+// Clustered order: Luby rounds (state 0 undecided / 1 seed / 2 covered; *undecided
+// counts the vertices left), then out = the vertices grouped by their seed's rank in
+// `order`.
+void launch_mis_round(int32_t n, const int64_t* rp, const int32_t* col, int32_t* state, int32_t* win,
+                      int32_t* undecided, hipStream_t s);
+void launch_cluster_order(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* state, const int32_t* order,
+                          int32_t* rank, int32_t* key, int32_t* hist, int64_t* off, int32_t* cursor, int32_t* out,
+                          void* scan_scratch, hipStream_t s);
 void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,
                              hipStream_t s);
 void launch_permute(const PermuteArgs& a, hipStream_t s);

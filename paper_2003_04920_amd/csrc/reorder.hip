@@ -155,6 +155,106 @@ __global__ void __launch_bounds__(kThreads) k_bfs_advance(int32_t m, const int32
   if (i == m - 1 || (prob ? prob[next[i + 1]] : 0) != p) pcnt[p] += (int32_t)i - pstart[p] + 1;
 }
 
+// Clustered order (optional): a maximal independent set of "seeds" by Luby's rounds
+// on hashed priorities, every other vertex joins its highest-priority neighbouring
+// seed, and clusters follow their seed's breadth-first rank.  Vertices of one cluster
+// are within one hop of a common seed, so a wave's rows share more lines of g.
+__device__ __forceinline__ uint32_t mis_prio(uint32_t v) {  // a bijection of 32-bit values
+  v ^= v >> 16;
+  v *= 0x85ebca6bu;
+  v ^= v >> 13;
+  v *= 0xc2b2ae35u;
+  v ^= v >> 16;
+  return v;
+}
+
+// state: 0 undecided, 1 seed, 2 covered.  win[v] = 1 if v beats every undecided
+// neighbour this round.
+__global__ void __launch_bounds__(kThreads) k_mis_select(int32_t n, const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const int32_t* __restrict__ state, int32_t* __restrict__ win) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t w = 0;
+  if (state[v] == 0) {
+    w = 1;
+    const uint32_t pv = mis_prio((uint32_t)v);
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) {
+      const int32_t u = col[j];
+      if (u != v && state[u] == 0 && mis_prio((uint32_t)u) > pv) {
+        w = 0;
+        break;
+      }
+    }
+  }
+  win[v] = w;
+}
+
+__global__ void __launch_bounds__(kThreads) k_mis_apply(int32_t n, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ win, int32_t* __restrict__ state,
+                                                       int32_t* __restrict__ undecided) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || state[v] != 0) return;
+  if (win[v]) {
+    state[v] = 1;
+    return;
+  }
+  for (int64_t j = rp[v]; j < rp[v + 1]; ++j) {
+    const int32_t u = col[j];
+    if (win[u] || state[u] == 1) {  // old seeds are stable; this round's come through win
+      state[v] = 2;
+      return;
+    }
+  }
+  atomicAdd(undecided, 1);
+}
+
+// key[v] = breadth-first rank of v's cluster seed; hist[key]++.
+__global__ void __launch_bounds__(kThreads) k_mis_key(int32_t n, const int64_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ state,
+                                                     const int32_t* __restrict__ rank, int32_t* __restrict__ key,
+                                                     int32_t* __restrict__ hist) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t seed = (int32_t)v;
+  if (state[v] != 1) {
+    uint32_t best = 0;
+    bool found = false;
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) {
+      const int32_t u = col[j];
+      if (state[u] != 1) continue;
+      const uint32_t pu = mis_prio((uint32_t)u);
+      if (!found || pu > best) {
+        best = pu;
+        seed = u;
+        found = true;
+      }
+    }
+  }
+  const int32_t k = rank[seed];
+  key[v] = k;
+  atomicAdd(&hist[k], 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_mis_scatter(int32_t n, const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ key,
+                                                         const int64_t* __restrict__ off,
+                                                         int32_t* __restrict__ cursor, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = order[i];  // breadth-first order: members keep roughly that order
+  const int32_t k = key[v];
+  out[off[k] + atomicAdd(&cursor[k], 1)] = v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_rank_of(int32_t n, const int32_t* __restrict__ order,
+                                                     int32_t* __restrict__ rank) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rank[order[i]] = (int32_t)i;
+}
+
 // Vertices the BFS did not reach follow in their problem's range.
 __global__ void __launch_bounds__(kThreads) k_append_unvisited(int32_t n, const int32_t* __restrict__ visited,
                                                               int32_t* __restrict__ order,
@@ -328,6 +428,23 @@ void launch_bfs_order_level(int32_t fsize, int32_t m, const int32_t* cand, const
   hipLaunchKernelGGL(k_bfs_starts, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart);
   hipLaunchKernelGGL(k_bfs_place, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart, pcnt, order);
   hipLaunchKernelGGL(k_bfs_advance, dim3(blocks_for(m)), dim3(kThreads), 0, s, m, next, prob, pstart, pcnt);
+}
+
+void launch_mis_round(int32_t n, const int64_t* rp, const int32_t* col, int32_t* state, int32_t* win,
+                      int32_t* undecided, hipStream_t s) {
+  hipLaunchKernelGGL(k_mis_select, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, rp, col, state, win);
+  hipLaunchKernelGGL(k_mis_apply, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, rp, col, win, state, undecided);
+}
+
+void launch_cluster_order(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* state, const int32_t* order,
+                          int32_t* rank, int32_t* key, int32_t* hist, int64_t* off, int32_t* cursor, int32_t* out,
+                          void* scan_scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_rank_of, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, order, rank);
+  hipMemsetAsync(hist, 0, sizeof(int32_t) * (size_t)n, s);
+  hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)n, s);
+  hipLaunchKernelGGL(k_mis_key, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, rp, col, state, rank, key, hist);
+  scan_i32_to_i64(hist, n, off, scan_scratch, s);
+  hipLaunchKernelGGL(k_mis_scatter, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, order, key, off, cursor, out);
 }
 
 void launch_append_unvisited(int32_t n, const int32_t* visited, int32_t* order, const int32_t* prob, int32_t* pcnt,

@@ -356,3 +356,10 @@ def test_tune_restores_policy_and_keeps_results(P):
     st = R.state()
     assert_same_policy("after tune", gg, pp, st.g, st.parent)
     assert_same_stats("after tune", sg, so)
+
+
+def test_breadth_first_order_agrees(P, monkeypatch):
+    """Both storage orders (clustered, plain breadth-first) give the oracle's results."""
+    monkeypatch.setenv("PIRRT_ORDER", "bfs")
+    wl = W.batched_6d(batches=4, batch=700, seed=103)
+    run_both(P, wl.batches, {i: (0, 1) for i in range(4)}, wl.heuristic, True)
