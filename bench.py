@@ -108,7 +108,13 @@ def profile_summary(paths):
             v = [x for (k, c), xs in per.items() if c == counter and pred(k) for x in xs]
             return sum(v) / len(v) if v else None
         calib = lambda k: "native::neg" in k
-        imp = lambda k: k.startswith("k_improve")
+        # the Improve variant the run used most (the autotuner also runs the others once)
+        imp_names = {}
+        for (k, c), v in per.items():
+            if k.startswith("k_improve") and c == "FETCH_SIZE":
+                imp_names[k] = len(v)
+        imp_main = max(imp_names, key=imp_names.get) if imp_names else None
+        imp = lambda k: k == imp_main
         cf, cw = mean(calib, "FETCH_SIZE"), mean(calib, "WRITE_SIZE")
         f_imp, w_imp = mean(imp, "FETCH_SIZE"), mean(imp, "WRITE_SIZE")
         if cf and cw and f_imp is not None and w_imp is not None:
@@ -116,6 +122,7 @@ def profile_summary(paths):
             traffic = int(round(f_imp * 1024 * sf + w_imp * 1024 * sw))
             out.append("calibration: FETCH_SIZE reads %.1f KiB and WRITE_SIZE %.1f KiB for 1 GiB each: "
                        "scale %.4f (fetch), %.4f (write)" % (cf, cw, sf, sw))
+            out.append("k_improve_kernel: %s" % imp_main)
             out.append("k_improve_fetch_bytes_per_launch: %d" % int(round(f_imp * 1024 * sf)))
             out.append("k_improve_write_bytes_per_launch: %d" % int(round(w_imp * 1024 * sw)))
             out.append("k_improve_traffic_bytes_per_launch: %d" % traffic)
@@ -416,6 +423,9 @@ def main():
                          "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
     ap.add_argument("--tune-each", action="store_true", help="multi: autotune every sequential graph too")
+    ap.add_argument("--config", type=int, default=-1,
+                    help="plain6d: fixed kernel configuration 0-7 (row split + 4 x workgroup-scope stamps) instead "
+                         "of the autotuner")
     ap.add_argument("--layouts", type=int, default=100, help="learned: training layouts")
     ap.add_argument("--per-layout", type=int, default=8192, help="learned: samples kept per layout")
     ap.add_argument("--epochs", type=int, default=4, help="learned: training epochs")
@@ -453,6 +463,9 @@ def main():
     log("workload %s: n=%d, batches=%d, directed edges=%d (%.1fs)" %
         (wl.name, wl.n, len(wl.batches), 2 * wl.nnz, time.time() - t0))
     b0 = wl.batches[0]
+    if args.config >= 0:  # a fixed kernel configuration instead of the autotuner's choice
+        os.environ["PIRRT_ROW_VARIANT"] = str(args.config % 4)
+        os.environ["PIRRT_WALK_COHERENT"] = "0" if args.config >= 4 else "1"
     G = P.Graph(stream=stream.cuda_stream, device=0)
     t0 = time.time()
     G.insert_rows(b0)
@@ -470,8 +483,9 @@ def main():
         _, _, st = G.replan(0, 1, h, True, timing=timing, g_out=g_out, parent_out=p_out)
         return st
 
-    # the library's autotuner picks the kernel configuration (outside the timed region)
-    tuned = G.tune(0, 1, h, True)
+    # the library's autotuner picks the kernel configuration (outside the timed region),
+    # unless --config fixed it when the graph was created
+    tuned = G.tune(0, 1, h, True) if args.config < 0 else args.config
     log("autotuner: configuration %d (row split %d, %s-scope Evaluate stamps)" %
         (tuned, tuned % 4, "workgroup" if tuned >= 4 else "device"))
 
