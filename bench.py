@@ -519,6 +519,23 @@ def main():
                 "avg_launch_us": round(1e3 * tst["ms_improve"] / max(1, tst["improve_launches"]), 2),
                 "bytes_per_launch": int(nbytes / max(1, tst["improve_launches"]))}
 
+    # the same Replan with pruning off (G = +inf: every reachable vertex is promising)
+    noprune = None
+    if not args.no_extra:
+        G.snapshot_restore()
+        G.replan(0, 1, h, False, g_out=g_out, parent_out=p_out)
+        reps = 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G.snapshot_restore()
+            _, _, s3 = G.replan(0, 1, h, False, g_out=g_out, parent_out=p_out)
+        torch.cuda.synchronize()
+        t_np = (time.perf_counter() - t0) / reps
+        noprune = {"replan_ms": round(1e3 * t_np, 3), "iterations": s3["iterations"],
+                   "edges_examined": s3["edges_examined"], "gteps": round(s3["edges_examined"] / t_np / 1e9, 2)}
+        log("pruning off: %s" % json.dumps(noprune))
+
     extra = None
     if not args.no_extra and len(wl.batches) > 1:
         # a further 10,000-vertex batch on the converged 1M-vertex policy
@@ -590,6 +607,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra_batch": extra,
+        "pruning_off": noprune,
     }
     print(json.dumps(out), flush=True)
 

@@ -285,36 +285,6 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, const Pr
   }
 }
 
-template <int GW, int Q, typename Idx>
-__global__ void __launch_bounds__(kThreads) k_mark_rows(const LoopCtl* __restrict__ ctl,
-                                                       const int32_t* __restrict__ plist,
-                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                       uint8_t* __restrict__ stamp) {
-  if (ctl->any_active == 0) return;
-  const int64_t cnt = ctl->npromising;
-  const int64_t gi = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / GW;
-  if (gi >= cnt) return;  // no barrier below: groups leave independently
-  const uint8_t ep = (uint8_t)ctl->epoch;
-  const int gl = threadIdx.x % GW;
-  const int32_t x = plist[gi];
-  const Idx ra = (Idx)rp[x], rb = (Idx)rp[x + 1];
-  const int4* col4 = reinterpret_cast<const int4*>(col);
-  const Idx qa = ra >> 2, qb = (rb + 3) >> 2;
-  for (Idx k = qa + gl; k < qb; k += GW * Q) {
-    int4 w[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) w[q] = col4[k + q * GW < qb ? k + q * GW : qa];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if (k + q * GW >= qb) continue;
-      const Idx j0 = (k + q * GW) * 4;
-      const int32_t u[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (j0 + e >= ra && j0 + e < rb) stamp[u[e]] = ep;
-    }
-  }
-}
 
 template <int GW, int Q, typename Idx, bool kBatched>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* __restrict__ prob,
@@ -411,6 +381,75 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
     changed = 1;
   }
   flush_counters(ctr, p, valid && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
+  }
+}
+
+// Neighbour stamping of the listed promising vertices (single graphs).  The rows one
+// workgroup takes are neighbours in the storage order, so they share most of their
+// neighbours: the 32 rows of a 6D workgroup list each distinct neighbour about twice.
+// Each pass writes every entry's slot id into a direct-mapped table in LDS (the last
+// writer keeps a position), then stamps once per table position in use; an entry
+// whose id lost its position is stamped directly.  Slot u sits at position
+// (mix(u / 32) + u % 32) mod the table size, so the ids of one 128-byte line of stamps
+// occupy neighbouring positions and their stores leave from neighbouring lanes, which
+// lets the memory pipeline merge them: about half the L2 write requests of one store
+// per entry.
+constexpr int32_t kTabEmpty = -1;
+
+__device__ __forceinline__ uint32_t tab_pos(int32_t u) {
+  return (((uint32_t)u >> 5) * 0x9E3779B1u >> 16) + ((uint32_t)u & 31u);
+}
+
+// 64 table positions per row of the workgroup (a 6D row has ~54 entries).
+template <int GW>
+constexpr int tab_slots() { return (kThreads / GW) * 64; }
+
+template <int GW, int Q, typename Idx>
+__global__ void __launch_bounds__(kThreads) k_mark_rows(const LoopCtl* __restrict__ ctl,
+                                                       const int32_t* __restrict__ plist,
+                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       uint8_t* __restrict__ stamp) {
+  constexpr int kSlots = tab_slots<GW>();
+  __shared__ int32_t keys[kSlots];
+  if (ctl->any_active == 0) return;
+  const int64_t cnt = ctl->npromising;
+  const int64_t first = (int64_t)blockIdx.x * (kThreads / GW);
+  if (first >= cnt) return;  // the whole workgroup
+  const uint8_t ep = (uint8_t)ctl->epoch;
+  const int gl = threadIdx.x % GW;
+  const int64_t gi = first + threadIdx.x / GW;
+  const bool valid = gi < cnt;
+  const int32_t x = plist[valid ? gi : cnt - 1];
+  const Idx ra = valid ? (Idx)rp[x] : 0, rb = valid ? (Idx)rp[x + 1] : 0;
+  const int4* col4 = reinterpret_cast<const int4*>(col);
+  const Idx qa = ra >> 2, qb = (rb + 3) >> 2;
+  Idx k = qa + gl;
+  for (;;) {
+    for (int i = threadIdx.x; i < kSlots; i += kThreads) keys[i] = kTabEmpty;
+    if (!__syncthreads_or(k < qb)) break;  // also: the clears are done
+    int32_t u[4 * Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int4 w = col4[k + q * GW < qb ? k + q * GW : qa];
+      const Idx j0 = (k + q * GW) * 4;
+      const bool live = k + q * GW < qb;
+      const int32_t uu[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) u[4 * q + e] = live && j0 + e >= ra && j0 + e < rb ? uu[e] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i)
+      if (u[i] >= 0) keys[tab_pos(u[i]) & (kSlots - 1)] = u[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i)
+      if (u[i] >= 0 && keys[tab_pos(u[i]) & (kSlots - 1)] != u[i]) stamp[u[i]] = ep;
+    for (int i = threadIdx.x; i < kSlots; i += kThreads) {
+      const int32_t y = keys[i];
+      if (y != kTabEmpty) stamp[y] = ep;
+    }
+    k += GW * Q;
+    __syncthreads();  // every read of the table is done before it is cleared
   }
 }
 
