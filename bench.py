@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of the MI355X
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 IMPROVE_SRC = os.path.join(ROOT, "paper_2003_04920_amd", "csrc", "improve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_6d_1m_traffic.txt")
@@ -191,6 +192,20 @@ def bench_multi(args):
     iters = [x["iterations"] for x in st]
     log("batched: %.3f ms per Replan of all problems, %.1f GTEPS, iterations max %d mean %.1f" %
         (ms_batch, edges / ms_batch / 1e6, max(iters), sum(iters) / len(iters)))
+    # phase timing (HIP events around every launch) for the Improve roofline
+    B.snapshot_restore()
+    tst = B.replan(roots, goals, h, True, timing=True, g_out=g_out, parent_out=p_out)[2]
+    t0s = tst[0]
+    sum_d = sum(x["sum_D"] for x in tst)
+    nbytes = improve_bytes(edges, sum_d, n, t0s["improve_launches"])
+    achieved = nbytes / (t0s["ms_improve"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_improve (batched)",
+                "launches": t0s["improve_launches"],
+                "avg_launch_us": round(1e3 * t0s["ms_improve"] / max(1, t0s["improve_launches"]), 2),
+                "bytes_per_launch": int(nbytes / max(1, t0s["improve_launches"]))}
+    log("timing pass: improve %.3f ms over %d launches, %.1f GB/s algorithmic" %
+        (t0s["ms_improve"], t0s["improve_launches"], achieved))
     # the same problems, one graph handle and one pirrt_replan call each
     graphs = []
     off = B.offsets
@@ -220,6 +235,29 @@ def bench_multi(args):
     ms_seq = 1e3 * (time.perf_counter() - t0) / reps
     assert seq_edges == edges, (seq_edges, edges)
     log("sequential: %.3f ms for %d pirrt_replan calls" % (ms_seq, len(graphs)))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the serial oracle on the first problems, up to about 15 s of host time
+        import oracle
+        spent = cpu_edges = 0
+        used = 0
+        for i, (R, sp) in enumerate(zip(rrgs, specs)):
+            rp_, col_, cost_ = R.rows(0, sp.radius)
+            O = oracle.Graph()
+            assert O.insert(rp_, col_, cost_) == 0
+            hh = h[off[i]:off[i + 1]].cpu().numpy()
+            t0 = time.perf_counter()
+            rc, so = O.replan(0, 1, hh, True)
+            spent += time.perf_counter() - t0
+            assert rc == 0 and so["edges_examined"] == st[i]["edges_examined"], (i, so, st[i])
+            cpu_edges += so["edges_examined"]
+            used += 1
+            if spent > 15.0:
+                break
+        cpu = {"value": round(cpu_edges / spent / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "one full Replan of each of the first %d problems (%d examined edges, serial C oracle, "
+                         "one thread, %.2f s)" % (used, cpu_edges, spent)}
+        log("cpu baseline: %s" % json.dumps(cpu))
     out = {
         "metric": "Batched multi-graph Replan GTEPS (%d problems, one pirrt_batch_replan per step)" % len(specs),
         "value": round(edges / ms_batch / 1e6, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -231,6 +269,8 @@ def bench_multi(args):
                    "problems": len(specs), "vertices": n, "directed_edges": nnz,
                    "edges_examined_per_step": edges, "iterations_max": max(iters),
                    "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "sequential_ms": round(ms_seq, 3), "speedup_vs_sequential": round(ms_seq / ms_batch, 2),
         "sequential_gteps": round(edges / ms_seq / 1e6, 3),
         "device_build_s": round(build_s, 3),
@@ -340,6 +380,51 @@ def bench_learned(args):
     torch.cuda.synchronize()
     infer_us = 1e6 * (time.perf_counter() - t1) / 20
 
+    # the network's training step against the bf16 matrix-core peak (multiply-adds per
+    # sample: forward 288x256 + 256x256 + 256, backward the two weight gradients, the
+    # hidden-layer input gradient and the output layer)
+    macs = (288 * 256 + 256 * 256 + 256) + (288 * 256 + 2 * 256 * 256 + 2 * 256)
+    # steps on one resident batch (the training loop above also gathers its batches)
+    xr, yr = Xt[:bs].contiguous(), Yt[:bs].contiguous()
+    probe = P.Mlp(in_dim, bs, lr=1e-3, stream=stream)
+    probe.set_params(init)
+    for _ in range(5):
+        probe.train_step(xr, yr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(100):
+        probe.train_step(xr, yr)
+    torch.cuda.synchronize()
+    step_us = 1e6 * (time.perf_counter() - t1) / 100
+    tflops = 2.0 * macs * bs / (step_us * 1e-6) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(tflops, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / BF16_PEAK_TFLOPS, 6), "traffic": None,
+                "kernel": "network training step (bf16 MFMA GEMMs + epilogues, batch %d)" % bs,
+                "avg_step_us": round(step_us, 1),
+                "note": "one train_step call (features, 2 forward GEMMs, loss, backward GEMMs and column sums, "
+                        "Adam, bf16 weight refresh, loss read back) on a resident batch"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's training step (numpy, one BLAS thread) on the same batch size
+        from threadpoolctl import threadpool_limits
+        from oracle import mlp as M
+        xh = Xt[:bs].cpu().numpy()
+        yh = Yt[:bs].cpu().numpy()
+        prm = M.init_params(np.random.default_rng(11), in_dim)
+        opt = M.Adam(lr=1e-3)
+        reps = 0
+        with threadpool_limits(limits=1):
+            t2 = time.perf_counter()
+            while time.perf_counter() - t2 < 10.0:
+                _, grads, _ = M.loss_and_grads(prm, xh, yh)
+                prm = opt.step(prm, grads)
+                reps += 1
+            cpu_s = time.perf_counter() - t2
+        cpu = {"value": round(reps * bs / cpu_s, 1), "unit": "training samples/s", "cores": 1, "kind": "oracle",
+               "sample": "%d training steps of %d samples with the numpy oracle (forward, backward, Adam; "
+                         "one BLAS thread, %.1f s)" % (reps, bs, cpu_s)}
+        log("cpu baseline: %s" % json.dumps(cpu))
+
     # ---- planner comparison on held-out layouts
     def plan(seed, learned):
         obs = W.make_obstacles(d, 40, "sphere", seed)
@@ -400,6 +485,8 @@ def bench_learned(args):
                      "heldout_recall": round(recall, 4), "heldout_precision": round(precision, 4),
                      "data_seconds": round(data_s, 2)},
         "inference_us_per_8192": round(infer_us, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "layouts": rows,
     }
     print(json.dumps(out), flush=True)

@@ -80,7 +80,9 @@ typedef struct {
   int64_t sum_P;          /* sum over iterations of |promising set| */
   int64_t sum_D;          /* sum over iterations of |Improve domain| */
   int64_t changed_total;  /* sum over iterations of parents switched */
-  /* wall time of the call and, with PIRRT_TIMING, of its phases (milliseconds) */
+  /* wall time of the call and, with PIRRT_TIMING, of its phases (milliseconds); the
+     phases of a batch run for all of its problems at once, so every problem's entry
+     holds the batch's phase times and launch counts */
   double ms_total;
   double ms_evaluate;
   double ms_mark;

@@ -982,13 +982,12 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
       st.changed_total = (int64_t)q.changed_total;
       st.ms_total = ms;
       st.evaluate_calls = timing ? agg.evaluate_calls : q.iterations;
-      if (P == 1) {
-        st.ms_evaluate = agg.ms_evaluate;
-        st.ms_mark = agg.ms_mark;
-        st.ms_improve = agg.ms_improve;
-        st.improve_launches = agg.improve_launches;
-        st.mark_launches = agg.mark_launches;
-      }
+      // the phases of a batch serve all of its problems at once
+      st.ms_evaluate = agg.ms_evaluate;
+      st.ms_mark = agg.ms_mark;
+      st.ms_improve = agg.ms_improve;
+      st.improve_launches = agg.improve_launches;
+      st.mark_launches = agg.mark_launches;
     }
   }
   G->last_iterations = most;

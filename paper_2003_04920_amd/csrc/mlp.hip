@@ -58,6 +58,8 @@ struct GemmArgs {
   const float* zref;  // kEpiMaskBf16: fp32 [M x N] whose sign gates the output
   float* zout;        // kEpiFwd: fp32 pre-activation [M x N] (nullable); kEpiF32: output
   uint16_t* bout;     // kEpiFwd / kEpiMaskBf16: bf16 output [M x N]
+  int64_t kchunk;     // split K: workgroup z sums k in [z * kchunk, (z + 1) * kchunk) and
+                      // kEpiF32 writes its partial product to zout + z * M * N
 };
 
 template <bool kAContig>
@@ -98,7 +100,9 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int64_t k = 0; k < g.K; k += 16) {
+  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t k1 = k0 + g.kchunk < g.K ? k0 + g.kchunk : g.K;
+  for (int64_t k = k0; k < k1; k += 16) {
     const bf16x8 a = load_a<kAContig>(g, am, k + kq);
     const bf16x8 b = load_b<kBContig>(g, k + kq, bn);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
     } else if (kEpi == kEpiMaskBf16) {
       g.bout[o] = to_bf16(g.zref[o] > 0.0f ? acc[r] : 0.0f);
     } else {
-      g.zout[o] = acc[r];
+      g.zout[(int64_t)blockIdx.z * g.M * g.N + o] = acc[r];
     }
   }
 }
@@ -129,31 +133,50 @@ __global__ void k_features(int32_t B, int32_t Bp, int32_t in_dim, const float* _
   X[i] = (b < B && k < in_dim) ? to_bf16(x[b * in_dim + k]) : (uint16_t)0;
 }
 
-// z = A2 w3 + b3 per row (one wave per row); with labels also dz = (sigmoid(z) - y)/B
-// (0 on padding rows) and the mean BCE-with-logits loss.
+// z = A2 w3 + b3 per row (one thread per row, k ascending); with labels also
+// dz = (sigmoid(z) - y) / B and the workgroup's loss sum (rows in order) in lpart.
 __global__ void __launch_bounds__(kThreads) k_layer3(int32_t B, int32_t Bp, const uint16_t* __restrict__ A2,
                                                      const uint16_t* __restrict__ w3b, const float* __restrict__ P,
                                                      const float* __restrict__ y, float* __restrict__ z,
-                                                     float* __restrict__ dz, float* __restrict__ loss) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  if (b >= Bp) return;
-  float s = 0.0f;
-  for (int k = lane; k < kHidden; k += kWave) s += from_bf16(A2[b * kHidden + k]) * from_bf16(w3b[k]);
+                                                     float* __restrict__ dz, float* __restrict__ lpart) {
+  __shared__ float wl[kHidden];
+  __shared__ float red[kThreads];
+  for (int k = threadIdx.x; k < kHidden; k += kThreads) wl[k] = from_bf16(w3b[k]);
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (b < Bp) {
+    const uint4* row = reinterpret_cast<const uint4*>(A2 + b * kHidden);
+    float s = 0.0f;
+    for (int q = 0; q < kHidden / 8; ++q) {
+      const uint4 w = row[q];
+      const uint32_t h[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-  if (lane != 0) return;
-  const float zb = s + P[kOffB3];
-  z[b] = zb;
-  if (!y) return;
-  if (b >= B) {
-    dz[b] = 0.0f;
-    return;
+      for (int e = 0; e < 4; ++e) {
+        s += __uint_as_float(h[e] << 16) * wl[8 * q + 2 * e];
+        s += __uint_as_float(h[e] & 0xffff0000u) * wl[8 * q + 2 * e + 1];
+      }
+    }
+    const float zb = s + P[kOffB3];
+    z[b] = zb;
+    if (y) {
+      if (b < B) {
+        const float yb = y[b];
+        dz[b] = (1.0f / (1.0f + expf(-zb)) - yb) / (float)B;
+        l = (fmaxf(zb, 0.0f) - zb * yb + log1pf(expf(-fabsf(zb)))) / (float)B;
+      } else {
+        dz[b] = 0.0f;
+      }
+    }
   }
-  const float yb = y[b];
-  dz[b] = (1.0f / (1.0f + expf(-zb)) - yb) / (float)B;
-  const float l = fmaxf(zb, 0.0f) - zb * yb + log1pf(expf(-fabsf(zb)));
-  atomicAdd(loss, l / (float)B);
+  if (!y) return;
+  red[threadIdx.x] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int i = 0; i < kThreads; ++i) t += red[i];
+    lpart[blockIdx.x] = t;
+  }
 }
 
 // dZ2 = bf16(dz w3^T * [Z2 > 0])
@@ -166,25 +189,58 @@ __global__ void k_dz2(int32_t Bp, const float* __restrict__ dz, const uint16_t* 
 }
 
 // out[n] = sum over rows of a bf16 [rows x N] matrix (one thread per column).
-__global__ void k_colsum(int32_t rows, int32_t N, const uint16_t* __restrict__ M, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// Column sums over the batch in two fixed-order stages (the same bits on every run):
+// workgroup (c, j) sums rows [j * rows_per, (j + 1) * rows_per) of 64 columns, four
+// row phases per column then the phases in order, into part[j][col]; k_sum_parts then
+// adds the kColParts partials of each column in order.  Column N (when `ones`) is the
+// all-ones column, and `w` (nullable) weights the rows: sum_b w[b] M[b][col].
+constexpr int kColParts = 64;
+constexpr int kSplitK = 32;  // K splits of the weight-gradient products
+
+__global__ void __launch_bounds__(kThreads) k_colsum_part(int32_t rows, int32_t rows_per, int32_t N, bool ones,
+                                                         const uint16_t* __restrict__ M,
+                                                         const float* __restrict__ w, float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + c;
+  const int ncol = N + (ones ? 1 : 0);
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
   float s = 0.0f;
-  for (int32_t r = 0; r < rows; ++r) s += from_bf16(M[(int64_t)r * N + n]);
-  out[n] = s;
+  if (col < ncol) {
+    for (int64_t r = r0 + ph; r < r1; r += 4) {
+      const float x = col < N ? from_bf16(M[r * N + col]) : 1.0f;
+      s += w ? x * w[r] : x;
+    }
+  }
+  red[ph][c] = s;
+  __syncthreads();
+  if (ph == 0 && col < ncol) part[(int64_t)blockIdx.y * ncol + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-// gw3[k] = sum_b A2[b][k] dz[b]; gb3 = sum_b dz[b] (thread kHidden).
-__global__ void k_grad3(int32_t Bp, const uint16_t* __restrict__ A2, const float* __restrict__ dz,
-                        float* __restrict__ G) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > kHidden) return;
-  float s = 0.0f;
-  if (k < kHidden)
-    for (int32_t b = 0; b < Bp; ++b) s += from_bf16(A2[(int64_t)b * kHidden + k]) * dz[b];
-  else
-    for (int32_t b = 0; b < Bp; ++b) s += dz[b];
-  G[k < kHidden ? kOffW3 + k : kOffB3] = s;
+// out[i] = sum over z < parts of part[z * count + i], in order of z (four outputs per
+// thread, eight partials in flight).
+__global__ void k_sum_parts(int64_t count, int32_t parts, const float* __restrict__ part, float* __restrict__ out) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= count) return;
+  const int nv = count - i0 < 4 ? (int)(count - i0) : 4;
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  int32_t z = 0;
+  for (; z + 8 <= parts; z += 8) {
+    float v[8][4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[u][j] = j < nv ? part[(int64_t)(z + u) * count + i0 + j] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[j] += v[u][j];
+  }
+  for (; z < parts; ++z)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] += j < nv ? part[(int64_t)z * count + i0 + j] : 0.0f;
+  for (int j = 0; j < nv; ++j) out[i0 + j] = s[j];
 }
 
 __global__ void k_adam(int64_t np, float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m,
@@ -248,6 +304,7 @@ struct pirrt_mlp {
   uint16_t* dZ2 = nullptr;
   uint16_t* dZ1 = nullptr;
   float* dloss = nullptr;
+  float* part = nullptr;   // partial sums of the split reductions
   float* hloss = nullptr;  // pinned
   bool poisoned = false;
   std::string err;
@@ -297,6 +354,7 @@ void release(pirrt_mlp* N) {
   free_dev(N->w3b); free_dev(N->xin); free_dev(N->yin); free_dev(N->X); free_dev(N->Z1); free_dev(N->A1);
   free_dev(N->Z2); free_dev(N->A2); free_dev(N->z); free_dev(N->dz); free_dev(N->dZ2); free_dev(N->dZ1);
   free_dev(N->dloss);
+  free_dev(N->part);
   if (N->hloss) (void)hipHostFree(N->hloss);
   N->hloss = nullptr;
 }
@@ -309,8 +367,8 @@ int mguard(pirrt_mlp* N) {
   return PIRRT_OK;
 }
 
-void launch_gemm(const GemmArgs& g, bool a_contig, bool b_contig, int epi, hipStream_t s) {
-  const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+void launch_gemm(const GemmArgs& g, bool a_contig, bool b_contig, int epi, hipStream_t s, int splits = 1) {
+  const dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)splits);
 #define GEMM(AC, BC, E) hipLaunchKernelGGL((k_gemm<AC, BC, E>), grid, dim3(kThreads), 0, s, g)
   if (epi == kEpiFwd) {
     if (a_contig && b_contig) GEMM(true, true, kEpiFwd); else GEMM(true, false, kEpiFwd);
@@ -320,6 +378,30 @@ void launch_gemm(const GemmArgs& g, bool a_contig, bool b_contig, int epi, hipSt
     if (a_contig) GEMM(true, false, kEpiF32); else GEMM(false, false, kEpiF32);
   }
 #undef GEMM
+}
+
+// Deterministic column sums of a bf16 [rows x cols] matrix (see k_colsum_part) into out.
+void launch_colsum(pirrt_mlp* N, int32_t rows, int32_t cols, bool ones, const uint16_t* M, const float* w,
+                   float* out) {
+  const int32_t ncol = cols + (ones ? 1 : 0);
+  const int32_t per = (rows + kColParts - 1) / kColParts;
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((ncol + 63) / 64), kColParts), dim3(kThreads), 0, N->stream, rows,
+                     per, cols, ones, M, w, N->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks((ncol + 3) / 4)), dim3(kThreads), 0, N->stream, (int64_t)ncol,
+                     kColParts, N->part, out);
+}
+
+// A weight gradient (M x N, K = the batch): the K range is split over kSplitK
+// workgroup layers (an output tile alone would leave most of the chip idle), the
+// partial products go to N->part and are added in split order.
+void launch_weight_grad(pirrt_mlp* N, GemmArgs g, float* out) {
+  const int64_t kc = ((g.K + kSplitK - 1) / kSplitK + 15) / 16 * 16;
+  const int splits = (int)((g.K + kc - 1) / kc);
+  g.kchunk = kc;
+  g.zout = N->part;
+  launch_gemm(g, false, false, kEpiF32, N->stream, splits);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(((int64_t)g.M * g.N + 3) / 4)), dim3(kThreads), 0, N->stream,
+                     (int64_t)g.M * g.N, splits, N->part, out);
 }
 
 // Features into X (padded rows and columns are zero); B rows, Bp = B rounded up to 64.
@@ -345,10 +427,10 @@ void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z) {
   hipStream_t s = N->stream;
   // element (k, n) of W1 is W1t[n * kIn + k]: contiguous in k
   GemmArgs g1{Bp, kHidden, kIn, N->X, kIn, 1, N->W1t, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
-              N->A1};
+              N->A1, kIn};
   launch_gemm(g1, true, true, kEpiFwd, s);
   GemmArgs g2{Bp, kHidden, kHidden, N->A1, kHidden, 1, N->W2t, 1, kHidden, N->P + kOffB2, nullptr,
-              keep_z ? N->Z2 : nullptr, N->A2};
+              keep_z ? N->Z2 : nullptr, N->A2, kHidden};
   launch_gemm(g2, true, true, kEpiFwd, s);
 }
 
@@ -356,24 +438,25 @@ void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z) {
 int enqueue_gradients(pirrt_mlp* N, int32_t B, int32_t Bp, const float* yd) {
   hipStream_t s = N->stream;
   enqueue_forward(N, Bp, true);
-  MHIP(N, hipMemsetAsync(N->dloss, 0, sizeof(float), s));
-  hipLaunchKernelGGL(k_layer3, dim3(nblocks((int64_t)Bp * kWave)), dim3(kThreads), 0, s, B, Bp, N->A2, N->w3b, N->P,
-                     yd, N->z, N->dz, N->dloss);
-  hipLaunchKernelGGL(k_grad3, dim3(nblocks(kHidden + 1)), dim3(kThreads), 0, s, Bp, N->A2, N->dz, N->G);
+  const unsigned nb3 = nblocks(Bp);
+  hipLaunchKernelGGL(k_layer3, dim3(nb3), dim3(kThreads), 0, s, B, Bp, N->A2, N->w3b, N->P, yd, N->z, N->dz,
+                     N->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kThreads), 0, s, (int64_t)1, (int32_t)nb3, N->part, N->dloss);
+  // gw3 = A2^T dz and gb3 = sum dz: the weighted column sums of [A2 | 1]
+  launch_colsum(N, Bp, kHidden, true, N->A2, N->dz, N->G + kOffW3);
   hipLaunchKernelGGL(k_dz2, dim3(nblocks((int64_t)Bp * kHidden)), dim3(kThreads), 0, s, Bp, N->dz, N->w3b, N->Z2,
                      N->dZ2);
-  hipLaunchKernelGGL(k_colsum, dim3(nblocks(kHidden)), dim3(kThreads), 0, s, Bp, kHidden, N->dZ2, N->G + kOffB2);
+  launch_colsum(N, Bp, kHidden, false, N->dZ2, nullptr, N->G + kOffB2);
   // gW2[i][j] = sum_b A1[b][i] dZ2[b][j]
-  GemmArgs gw2{kHidden, kHidden, Bp, N->A1, 1, kHidden, N->dZ2, kHidden, 1, nullptr, nullptr, N->G + kOffW2,
-               nullptr};
-  launch_gemm(gw2, false, false, kEpiF32, s);
+  GemmArgs gw2{kHidden, kHidden, Bp, N->A1, 1, kHidden, N->dZ2, kHidden, 1, nullptr, nullptr, nullptr, nullptr, 0};
+  launch_weight_grad(N, gw2, N->G + kOffW2);
   // dZ1 = bf16(dZ2 W2^T * [Z1 > 0]): element (k = j, n = i) of W2^T is W2b[i][j]
-  GemmArgs gd1{Bp, kHidden, kHidden, N->dZ2, kHidden, 1, N->W2b, 1, kHidden, nullptr, N->Z1, nullptr, N->dZ1};
+  GemmArgs gd1{Bp, kHidden, kHidden, N->dZ2, kHidden, 1, N->W2b, 1, kHidden, nullptr, N->Z1, nullptr, N->dZ1, kHidden};
   launch_gemm(gd1, true, true, kEpiMaskBf16, s);
-  hipLaunchKernelGGL(k_colsum, dim3(nblocks(kHidden)), dim3(kThreads), 0, s, Bp, kHidden, N->dZ1, N->G + kOffB1);
+  launch_colsum(N, Bp, kHidden, false, N->dZ1, nullptr, N->G + kOffB1);
   // gW1[i][j] = sum_b X[b][i] dZ1[b][j]
-  GemmArgs gw1{kIn, kHidden, Bp, N->X, 1, kIn, N->dZ1, kHidden, 1, nullptr, nullptr, N->G + kOffW1, nullptr};
-  launch_gemm(gw1, false, false, kEpiF32, s);
+  GemmArgs gw1{kIn, kHidden, Bp, N->X, 1, kIn, N->dZ1, kHidden, 1, nullptr, nullptr, nullptr, nullptr, 0};
+  launch_weight_grad(N, gw1, N->G + kOffW1);
   MHIP(N, hipGetLastError());
   return PIRRT_OK;
 }
@@ -431,7 +514,8 @@ int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
             malloc_dev(&N->X, bc * kIn) && malloc_dev(&N->Z1, bc * kHidden) && malloc_dev(&N->A1, bc * kHidden) &&
             malloc_dev(&N->Z2, bc * kHidden) && malloc_dev(&N->A2, bc * kHidden) && malloc_dev(&N->z, bc) &&
             malloc_dev(&N->dz, bc) && malloc_dev(&N->dZ2, bc * kHidden) && malloc_dev(&N->dZ1, bc * kHidden) &&
-            malloc_dev(&N->dloss, 1);
+            malloc_dev(&N->dloss, 1) &&
+            malloc_dev(&N->part, std::max<int64_t>((int64_t)kSplitK * kIn * kHidden, (int64_t)kColParts * (kHidden + 1)));
   if (ok && hipHostMalloc((void**)&N->hloss, sizeof(float), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     N->hloss = nullptr;
@@ -508,8 +592,8 @@ int pirrt_mlp_forward(pirrt_mlp* N, int32_t B, const float* x, float* logits, in
   const float* yd = nullptr;
   if ((rc = stage_inputs(N, B, Bp, x, nullptr, mem_kind, &yd))) return rc;
   enqueue_forward(N, Bp, false);
-  hipLaunchKernelGGL(k_layer3, dim3(nblocks((int64_t)Bp * kWave)), dim3(kThreads), 0, N->stream, B, Bp, N->A2,
-                     N->w3b, N->P, nullptr, N->z, nullptr, nullptr);
+  hipLaunchKernelGGL(k_layer3, dim3(nblocks(Bp)), dim3(kThreads), 0, N->stream, B, Bp, N->A2, N->w3b, N->P, nullptr,
+                     N->z, nullptr, nullptr);
   MHIP(N, hipGetLastError());
   MHIP(N, hipMemcpyAsync(logits, N->z, sizeof(float) * (size_t)B,
                          mem_kind == PIRRT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, N->stream));

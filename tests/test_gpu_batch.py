@@ -259,3 +259,24 @@ def test_batch_tune(P):
         check_problem("tuned", g, parent, off[i], pr, fin.g, fin.parent)
         for k in STAT_KEYS:
             assert stats[i][k] == st[k], (pr.name, k)
+
+
+def test_batch_phase_timing(P):
+    """With timing on, every problem's entry holds the batch's phase times; the
+    results stay those of the oracle."""
+    probs = problem_set()
+    B = build(P, probs)
+    off = B.offsets
+    B.snapshot_save()
+    roots, goals = [p.root for p in probs], [p.goal for p in probs]
+    g, parent, stats = B.replan(roots, goals, full_h(probs), timing=True)
+    want = [oracle_run(pr) for pr in probs]
+    for i, pr in enumerate(probs):
+        check_problem("timed", g, parent, off[i], pr, want[i][3].g, want[i][3].parent)
+    first = stats[0]
+    assert first["ms_improve"] > 0 and first["ms_evaluate"] > 0 and first["ms_mark"] > 0
+    # one Improve launch per loop iteration of the batch: the longest problem's count
+    assert first["improve_launches"] == max(s["iterations"] for s in stats)
+    for s in stats[1:]:
+        for k in ("ms_evaluate", "ms_mark", "ms_improve", "improve_launches", "mark_launches", "evaluate_calls"):
+            assert s[k] == first[k], k
