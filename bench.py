@@ -50,8 +50,12 @@ def improve_bytes(edges: int, sum_d: int, n: int, launches: int) -> int:
 
 
 def source_digest() -> str:
-    with open(IMPROVE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the Improve kernel's sources (its file and the shared row-pass header)."""
+    h = hashlib.sha256()
+    for path in (IMPROVE_SRC, os.path.join(os.path.dirname(IMPROVE_SRC), "rowpass.h")):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -65,7 +69,7 @@ def measured_traffic():
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("improve_hip_sha256_16") != source_digest():
+    if vals.get("improve_src_sha256_16") != source_digest():
         return None
     try:
         return int(vals["k_improve_traffic_bytes_per_launch"])
@@ -127,7 +131,7 @@ def profile_summary(paths):
             out.append("k_improve_fetch_bytes_per_launch: %d" % int(round(f_imp * 1024 * sf)))
             out.append("k_improve_write_bytes_per_launch: %d" % int(round(w_imp * 1024 * sw)))
             out.append("k_improve_traffic_bytes_per_launch: %d" % traffic)
-            out.append("improve_hip_sha256_16: %s" % source_digest())
+            out.append("improve_src_sha256_16: %s" % source_digest())
     print("\n".join(out))
 
 
@@ -606,6 +610,27 @@ def main():
                 "avg_launch_us": round(1e3 * tst["ms_improve"] / max(1, tst["improve_launches"]), 2),
                 "bytes_per_launch": int(nbytes / max(1, tst["improve_launches"]))}
 
+    goal_exact = float(g_out[1].item())
+    # the narrowed Improve domain (PIRRT_LOOKAHEAD) on the same graph and policy
+    look = None
+    if not args.no_extra:
+        G.snapshot_restore()
+        G.replan(0, 1, h, True, g_out=g_out, parent_out=p_out, lookahead=True)
+        reps = 5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G.snapshot_restore()
+            _, _, s4 = G.replan(0, 1, h, True, g_out=g_out, parent_out=p_out, lookahead=True)
+        torch.cuda.synchronize()
+        t_lk = (time.perf_counter() - t0) / reps
+        goal_look = float(g_out[1].item())
+        look = {"replan_ms": round(1e3 * t_lk, 3), "speedup_vs_full_domain": round(ms_per_step / (1e3 * t_lk), 3),
+                "iterations": s4["iterations"], "edges_examined": s4["edges_examined"], "sum_D": s4["sum_D"],
+                "goal_cost": goal_look, "goal_cost_full_domain": goal_exact,
+                "goal_cost_rel_diff": abs(goal_look - goal_exact) / goal_exact}
+        log("narrowed domain: %s" % json.dumps(look))
+
     # the same Replan with pruning off (G = +inf: every reachable vertex is promising)
     noprune = None
     if not args.no_extra:
@@ -695,6 +720,7 @@ def main():
         "cpu_baseline": cpu,
         "extra_batch": extra,
         "pruning_off": noprune,
+        "lookahead_domain": look,
     }
     print(json.dumps(out), flush=True)
 

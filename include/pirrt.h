@@ -58,8 +58,17 @@ enum { PIRRT_MEM_HOST = 0, PIRRT_MEM_DEVICE = 1 };
 enum {
   PIRRT_NO_PRUNE = 1u << 0, /* threshold G = +inf instead of g(goal): every reachable
                                vertex is promising */
-  PIRRT_TIMING = 1u << 1    /* time each phase with HIP events (fills the ms_* and
+  PIRRT_TIMING = 1u << 1,   /* time each phase with HIP events (fills the ms_* and
                                per-kernel fields of pirrt_stats; adds event overhead) */
+  PIRRT_LOOKAHEAD = 1u << 2 /* narrowed Improve domain, a work-reduction variant of the
+                               "promising vertices and their neighbours" rule of Sec.
+                               IV-C: a neighbour w of a promising u joins the domain only
+                               if fl(fl(g(u) + c(u,w)) + h(w)) < G, i.e. if the candidate u
+                               offers could be promising; promising vertices stay in.
+                               Improve itself is unchanged.  The fixed point differs from
+                               the default's in general; g(goal) keeps the default's
+                               optimality argument under a consistent h.  Without
+                               pruning both rules coincide. */
 };
 
 typedef struct pirrt_graph pirrt_graph;

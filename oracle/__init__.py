@@ -75,6 +75,8 @@ def load(path: Optional[str] = None):
     lib.orc_get_adjacency.argtypes = [vp, vp, vp, vp]
     lib.orc_replan.restype = ctypes.c_int
     lib.orc_replan.argtypes = [vp, i32, i32, vp, ctypes.c_int, i32, ctypes.POINTER(Stats)]
+    lib.orc_replan_mode.restype = ctypes.c_int
+    lib.orc_replan_mode.argtypes = [vp, i32, i32, vp, ctypes.c_int, ctypes.c_int, i32, ctypes.POINTER(Stats)]
     lib.orc_evaluate.restype = i64
     lib.orc_evaluate.argtypes = [vp, i32]
     if path is None:
@@ -151,12 +153,14 @@ class Graph:
         self._lib.orc_get_adjacency(self._h, _ptr(ptr), _ptr(nbr), _ptr(cst))
         return ptr, nbr[: self.nnz], cst[: self.nnz]
 
-    def replan(self, root: int, goal: int, h=None, prune: bool = True, max_iters: int = 0):
-        """Returns (rc, stats dict).  The policy is updated in place."""
+    def replan(self, root: int, goal: int, h=None, prune: bool = True, max_iters: int = 0,
+               lookahead: bool = False):
+        """Returns (rc, stats dict).  The policy is updated in place.  lookahead selects
+        the narrowed Improve domain (see orc_replan_mode)."""
         st = Stats()
         hh = None if h is None else np.ascontiguousarray(h, np.float32)
-        rc = self._lib.orc_replan(self._h, int(root), int(goal), _ptr(hh), int(bool(prune)),
-                                  int(max_iters), ctypes.byref(st))
+        rc = self._lib.orc_replan_mode(self._h, int(root), int(goal), _ptr(hh), int(bool(prune)),
+                                       int(bool(lookahead)), int(max_iters), ctypes.byref(st))
         return int(rc), st.as_dict()
 
     def evaluate(self, root: int) -> int:

@@ -260,9 +260,24 @@ static int64_t evaluate(orc_graph* G, int32_t root, int32_t* child_ptr, int32_t*
  *   Improve over D (Jacobi, strict improvement, lowest index on ties)
  * until no parent changes, re-evaluating after every step that changed one.
  * h may be NULL (h = 0).  max_iters <= 0 selects 4n + 8.
+ *
+ * lookahead != 0 narrows the domain (a work-reduction variant of Sec. IV-C, not the
+ * paper's own rule): a neighbour w of a promising u joins D only when the candidate
+ * that u offers it could itself be promising, (g(u) + c(u,w)) + h(w) < G, each sum
+ * one binary32 addition.  Promising vertices stay in D.  Improve over D is unchanged
+ * (every neighbour is a candidate).  With pruning off (G = +inf) the filter keeps
+ * every neighbour of a finite-g vertex, so the two modes coincide.
  */
+int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int lookahead,
+                    int32_t max_iters, orc_stats* st);
+
 int orc_replan(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int32_t max_iters,
                orc_stats* st) {
+  return orc_replan_mode(G, root, goal, h, prune, 0, max_iters, st);
+}
+
+int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int lookahead,
+                    int32_t max_iters, orc_stats* st) {
   int64_t n = G->n;
   orc_stats local;
   if (!st) st = &local;
@@ -302,7 +317,15 @@ int orc_replan(orc_graph* G, int32_t root, int32_t goal, const float* h, int pru
     for (int64_t v = 0; v < n; ++v) {
       if (!inP[v]) continue;
       inD[v] = 1;
-      for (int32_t j = 0; j < G->deg[v]; ++j) inD[G->nbr[v][j]] = 1;
+      for (int32_t j = 0; j < G->deg[v]; ++j) {
+        int32_t w = G->nbr[v][j];
+        if (lookahead) {
+          float offer = G->g[v] + G->cst[v][j];
+          float f = offer + (h ? h[w] : 0.0f);
+          if (!(f < thr)) continue;
+        }
+        inD[w] = 1;
+      }
     }
     inD[root] = 0;
     for (int64_t v = 0; v < n; ++v) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libpirrt.so")
 
 PIRRT_OK, PIRRT_EINVAL, PIRRT_ENOMEM, PIRRT_EDEVICE, PIRRT_ENOTCONVERGED = 0, -1, -2, -3, -4
 PIRRT_MEM_HOST, PIRRT_MEM_DEVICE = 0, 1
-PIRRT_NO_PRUNE, PIRRT_TIMING = 1, 2
+PIRRT_NO_PRUNE, PIRRT_TIMING, PIRRT_LOOKAHEAD = 1, 2, 4
 
 EXPORTS = [
     "pirrt_config_init", "pirrt_graph_create", "pirrt_graph_destroy", "pirrt_insert_batch", "pirrt_replan",
@@ -246,9 +246,10 @@ class Graph:
         return self.insert_batch(batch.row_ptr, batch.col, batch.cost)
 
     def replan(self, root: int, goal: int, h=None, prune: bool = True, timing: bool = False,
-               g_out=None, parent_out=None, allow_not_converged: bool = False):
+               g_out=None, parent_out=None, allow_not_converged: bool = False, lookahead: bool = False):
         """Runs Replan.  Outputs are numpy arrays unless device buffers are given
-        (torch tensors on the GPU) or h is a device tensor."""
+        (torch tensors on the GPU) or h is a device tensor.  lookahead selects the
+        narrowed Improve domain (PIRRT_LOOKAHEAD)."""
         h = _check_dtype(h, np.float32, "float32")
         n = self.n
         if g_out is None and parent_out is None and _is_device(h):
@@ -259,7 +260,7 @@ class Graph:
             g_out = np.empty(n, np.float32)
             parent_out = np.empty(n, np.int32)
         kind = _mem_kind(h, g_out, parent_out)
-        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0)
+        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0) | (PIRRT_LOOKAHEAD if lookahead else 0)
         st = pirrt_stats()
         rc = self._lib.pirrt_replan(self._h, int(root), int(goal), _ptr(h), flags, _ptr(g_out), _ptr(parent_out),
                                     kind, ctypes.byref(st))
@@ -268,12 +269,13 @@ class Graph:
         d["rc"] = rc
         return g_out, parent_out, d
 
-    def tune(self, root: int, goal: int, h=None, prune: bool = True) -> int:
+    def tune(self, root: int, goal: int, h=None, prune: bool = True, lookahead: bool = False) -> int:
         """Autotunes the kernel configuration on this Replan; returns its index."""
         h = _check_dtype(h, np.float32, "float32")
         cfg = ctypes.c_int32(-1)
-        self._check(self._lib.pirrt_tune(self._h, int(root), int(goal), _ptr(h), 0 if prune else PIRRT_NO_PRUNE,
-                                         _mem_kind(h), ctypes.byref(cfg)))
+        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_LOOKAHEAD if lookahead else 0)
+        self._check(self._lib.pirrt_tune(self._h, int(root), int(goal), _ptr(h), flags, _mem_kind(h),
+                                         ctypes.byref(cfg)))
         return int(cfg.value)
 
     def get_policy(self, device=None):
@@ -374,7 +376,7 @@ class Batch:
         return int(idx.value)
 
     def replan(self, roots, goals, h=None, prune: bool = True, timing: bool = False, g_out=None,
-               parent_out=None, allow_not_converged: bool = False):
+               parent_out=None, allow_not_converged: bool = False, lookahead: bool = False):
         """Replans every problem.  Returns (g, parent, per-problem stats dicts)."""
         P = self.num_problems
         roots = np.ascontiguousarray(roots, np.int32)
@@ -391,7 +393,7 @@ class Batch:
             g_out = np.empty(n, np.float32)
             parent_out = np.empty(n, np.int32)
         kind = _mem_kind(h, g_out, parent_out)
-        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0)
+        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0) | (PIRRT_LOOKAHEAD if lookahead else 0)
         st = (pirrt_stats * max(P, 1))()
         rc = self._lib.pirrt_batch_replan(self._h, _ptr(roots), _ptr(goals), _ptr(h), flags, _ptr(g_out),
                                           _ptr(parent_out), kind, ctypes.cast(st, ctypes.c_void_p))
@@ -399,14 +401,15 @@ class Batch:
         stats = [dict(st[i].as_dict(), rc=rc) for i in range(P)]
         return g_out, parent_out, stats
 
-    def tune(self, roots, goals, h=None, prune: bool = True) -> int:
+    def tune(self, roots, goals, h=None, prune: bool = True, lookahead: bool = False) -> int:
         """Autotunes the kernel configuration on this batch Replan; returns its index."""
         roots = np.ascontiguousarray(roots, np.int32)
         goals = np.ascontiguousarray(goals, np.int32)
         h = _check_dtype(h, np.float32, "float32")
         cfg = ctypes.c_int32(-1)
         self._check(self._lib.pirrt_batch_tune(self._h, _ptr(roots), _ptr(goals), _ptr(h),
-                                               0 if prune else PIRRT_NO_PRUNE, _mem_kind(h), ctypes.byref(cfg)))
+                                               (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_LOOKAHEAD if lookahead else 0),
+                                               _mem_kind(h), ctypes.byref(cfg)))
         return int(cfg.value)
 
     def get_policy(self, device=None):

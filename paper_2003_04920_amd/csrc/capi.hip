@@ -62,7 +62,7 @@ thread_local std::string g_create_error;
 struct LoopKey {
   const void* ptrs[16];
   int64_t n, nnz;
-  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, pad;
+  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead;
   bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
 };
 
@@ -166,6 +166,7 @@ struct pirrt_graph {
   // tuning
   int32_t mid_hint = 64;
   int row_variant = 2;
+  bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
   bool poisoned = false;
   std::string err;
 };
@@ -779,6 +780,7 @@ LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   k.has_h = L.sa.h != nullptr;
   k.iters = iters;
   k.mid = L.ea.mid_launches;
+  k.lookahead = L.sa.lookahead;
   return k;
 }
 
@@ -862,6 +864,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.dlist = G->dlist;
   sa.plist = G->fr1;  // free during a Replan (the level evaluator's frontiers run only between marks)
   sa.tiles = G->tiles;
+  sa.lookahead = G->lookahead;
   WalkArgs& wa = L.wa;
   wa.n = n;
   wa.prob = problem_map(G);
@@ -1252,6 +1255,7 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   pirrt_stats st;
+  G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   rc = run_replan(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, (flags & PIRRT_TIMING) != 0,
                   &st);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
@@ -1275,6 +1279,7 @@ int pirrt_tune(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uint3
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
+  G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   return tune(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 
@@ -1504,6 +1509,7 @@ int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goal
   }
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   rc = run_replan(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0,
                   (flags & PIRRT_TIMING) != 0, stats);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
@@ -1541,6 +1547,7 @@ int pirrt_batch_tune(pirrt_batch* B, const int32_t* roots, const int32_t* goals,
   }
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
+  G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   return tune(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 

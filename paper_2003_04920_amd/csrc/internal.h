@@ -161,6 +161,7 @@ struct StepArgs {
   int32_t* dlist;            // compacted Improve domain (n entries of room)
   int32_t* plist;            // single graphs: compacted promising set (n entries of room)
   const int32_t* tiles;      // batches: active tile list (see LoopCtl::ntiles)
+  bool lookahead;            // narrowed domain: stamp a neighbour only for a promising offer
 };
 constexpr int kRowVariants = 4;
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);

@@ -456,6 +456,78 @@ def pin_errors(lib):
     assert G.replan(0, 1, np.array([0.0, -1.0], np.float32))[0] == O.EINVAL
 
 
+def lookahead_example():
+    """A five-vertex graph worked by hand for the narrowed Improve domain.
+
+    Edges 0-2 (1), 2-1 (1), 0-3 (0.5), 3-1 (3), 2-4 (0.5); root 0, goal 1;
+    h = (1, 0, 0.5, 1.2, 1); starting policy 2<-0, 1<-2, 3<-1, 4<-2, so
+    g = (0, 2, 1, 5, 1.5) and G = g(1) = 2, f = g + h = (1, 2, 1.5, 6.2, 2.5).
+    Iteration 1: P = {0, 2}.  Full domain: P and its neighbours minus the root
+    = {1, 2, 3, 4} (degrees 2 + 3 + 2 + 1 = 8 entries).  Narrowed: from 0 the
+    offers are 1 + 0.5 = 1.5 to 2 and 0.5 + 1.2 = 1.7 to 3 (both < 2); from 2 they
+    are 2 + 1 = 3 to 0, 2 + 0 = 2 to 1, 1.5 + 1 = 2.5 to 4 (none < 2): D = {2, 3}
+    (5 entries).  Improve moves 3 under 0 (0.5 < 5).  Iteration 2: g(3) = 0.5,
+    P = {0, 2, 3}; the full domain is again {1, 2, 3, 4}; from 3 the offers are
+    1 + 1 = 2 to 0 and 3.5 to 1, so the narrowed domain stays {2, 3}; nothing
+    changes.  Totals (iterations, sum_P, sum_D, edges, changed): full mode
+    (2, 5, 8, 16, 1), narrowed (2, 5, 4, 10, 1); final g = (0, 2, 1, 0.5, 1.5)."""
+    edges = [(0, 2, 1.0), (2, 1, 1.0), (0, 3, 0.5), (3, 1, 3.0), (2, 4, 0.5)]
+    h = np.array([1.0, 0.0, 0.5, 1.2, 1.0], np.float32)
+    parent = np.array([-1, 2, 0, 1, 2], np.int32)
+    pcost = np.array([0.0, 1.0, 1.0, 3.0, 0.5], np.float32)
+    return edges, h, parent, pcost
+
+
+def pin_lookahead_worked_example(lib):
+    edges, h, parent, pcost = lookahead_example()
+    want = {False: (2, 5, 8, 16, 1), True: (2, 5, 4, 10, 1)}
+    for look in (False, True):
+        G = build_graph(lib, [W.from_edges(5, edges)])
+        assert G.set_state(np.zeros(5, np.float32), parent, pcost) == 0
+        rc, st = G.replan(0, 1, h, True, lookahead=look)
+        assert rc == 0
+        got = (st["iterations"], st["sum_P"], st["sum_D"], st["edges_examined"], st["changed_total"])
+        assert got == want[look], (look, got)
+        fin = G.state()
+        assert np.array_equal(fin.g, np.array([0, 2, 1, 0.5, 1.5], np.float32))
+        assert np.array_equal(fin.parent, np.array([-1, 2, 0, 0, 2], np.int32))
+
+
+def pin_lookahead_properties(lib):
+    """Narrowed domain: without pruning it is the full domain (G = +inf passes every
+    finite offer), so results and counters coincide; with pruning and a consistent h
+    the exactness argument still holds (the next vertex of an optimal path is offered
+    its optimal value by a promising predecessor), so g(goal) and every vertex with
+    d(v) + h(v) < d(goal) are optimal; it never takes more entries than the full
+    domain in the first iteration; and the fixed point satisfies the invariants."""
+    for wl in (W.plain_2d(samples=800, seed=0), W.batched_6d(batches=3, batch=400, seed=100)):
+        G = build_graph(lib, wl.batches)
+        H = build_graph(lib, wl.batches)
+        h = wl.heuristic(G.n)
+        rc1, s1 = G.replan(0, 1, h, False, lookahead=True)
+        rc2, s2 = H.replan(0, 1, h, False, lookahead=False)
+        assert rc1 == rc2 == 0 and s1 == s2, (s1, s2)
+        a, b = G.state(), H.state()
+        assert np.array_equal(a.g.view(np.uint32), b.g.view(np.uint32)) and np.array_equal(a.parent, b.parent)
+        # first iteration from the same policy: the narrowed domain is a subset
+        G = build_graph(lib, wl.batches)
+        H = build_graph(lib, wl.batches)
+        _, f1 = G.replan(0, 1, h, True, max_iters=1, lookahead=True)
+        _, f2 = H.replan(0, 1, h, True, max_iters=1, lookahead=False)
+        assert f1["sum_P"] == f2["sum_P"] and f1["sum_D"] <= f2["sum_D"]
+        assert f1["edges_examined"] <= f2["edges_examined"]
+        G = build_graph(lib, wl.batches)
+        rc, st = G.replan(0, 1, h, True, lookahead=True)
+        assert rc == 0
+        d = fp64_dist(G, 0)
+        g = G.state().g
+        if np.isfinite(d[1]):
+            mask = (np.arange(G.n) == 1) | (d + h.astype(np.float64) < d[1] * (1 - 1e-4))
+            assert_close_fp64(g, d, mask, "%s narrowed" % wl.name)
+        fold = fold_root_path(G.state().parent, G.state().pcost, 0)
+        assert np.array_equal(fold.view(np.uint32), g.view(np.uint32))
+
+
 PINS = [pin_golden, pin_path_fold, pin_errors, pin_lattice, pin_complete_graph, pin_insertion_local,
         pin_monotone, pin_invariants, pin_dijkstra, pin_pruned_exactness, pin_any_initial_policy,
-        pin_bruteforce_small]
+        pin_bruteforce_small, pin_lookahead_worked_example, pin_lookahead_properties]

@@ -280,3 +280,22 @@ def test_batch_phase_timing(P):
     for s in stats[1:]:
         for k in ("ms_evaluate", "ms_mark", "ms_improve", "improve_launches", "mark_launches", "evaluate_calls"):
             assert s[k] == first[k], k
+
+
+def test_batch_lookahead_matches_single_problems(P):
+    """The narrowed Improve domain on a batch: every problem ends where the oracle's
+    narrowed mode ends on that problem alone."""
+    probs = problem_set()
+    B = build(P, probs)
+    off = B.offsets
+    g, parent, stats = B.replan([p.root for p in probs], [p.goal for p in probs], full_h(probs), lookahead=True)
+    for i, pr in enumerate(probs):
+        R = O.Graph()
+        rp, col, cst = pr.rows
+        assert R.insert_batch(W.Batch(0, pr.n, rp, col, cst, 0.0)) == 0
+        rc, st = R.replan(pr.root, pr.goal, pr.h, pr.prune, lookahead=True)
+        fin = R.state()
+        assert rc == 0 and stats[i]["rc"] == 0
+        check_problem("lookahead", g, parent, off[i], pr, fin.g, fin.parent)
+        for k in STAT_KEYS:
+            assert stats[i][k] == st[k], (pr.name, k, stats[i][k], st[k])

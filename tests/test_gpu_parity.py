@@ -47,7 +47,7 @@ def assert_same_stats(tag, sg, so):
         assert sg[k] == so[k], "%s: %s gpu %d oracle %d" % (tag, k, sg[k], so[k])
 
 
-def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True):
+def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True, lookahead=False):
     """Inserts `batches` into both and, after each batch i in `plan`, replans
     (root, goal) = plan[i] on both and compares everything."""
     G = gpu_graph(P)
@@ -63,8 +63,8 @@ def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True):
         if i in plan:
             root, goal = plan[i]
             h = None if h_of is None else h_of(G.n)
-            gg, pp, sg = G.replan(root, goal, h, prune)
-            rc, so = R.replan(root, goal, h, prune)
+            gg, pp, sg = G.replan(root, goal, h, prune, lookahead=lookahead)
+            rc, so = R.replan(root, goal, h, prune, lookahead=lookahead)
             assert rc == 0 and sg["rc"] == 0
             st = R.state()
             assert_same_policy("replan %d" % i, gg, pp, st.g, st.parent)
@@ -363,3 +363,59 @@ def test_breadth_first_order_agrees(P, monkeypatch):
     monkeypatch.setenv("PIRRT_ORDER", "bfs")
     wl = W.batched_6d(batches=4, batch=700, seed=103)
     run_both(P, wl.batches, {i: (0, 1) for i in range(4)}, wl.heuristic, True)
+
+
+# ---- narrowed Improve domain (PIRRT_LOOKAHEAD) against the oracle's mode of it
+
+@pytest.mark.parametrize("case", ["2d", "6d_batches", "6d_30k", "8d"])
+def test_lookahead_domain(P, case):
+    if case == "2d":
+        wl = W.plain_2d()
+        plan = {0: (0, 1)}
+    elif case == "6d_batches":
+        wl = W.batched_6d(batches=4, batch=700, seed=103)
+        plan = {i: (0, 1) for i in range(4)}
+    elif case == "6d_30k":
+        wl = W.plain_6d(samples=30_000, extra=2_000, seed=205)
+        plan = {0: (0, 1), 1: (0, 1)}
+    else:
+        wl = W.grow("8d", 8, W.make_obstacles(8, 20, "sphere", 7), 8, [3000, 1000])
+        plan = {0: (0, 1), 1: (0, 1)}
+    run_both(P, wl.batches, plan, wl.heuristic, True, check_insert=False, lookahead=True)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_lookahead_every_row_split(P, monkeypatch, variant):
+    monkeypatch.setenv("PIRRT_ROW_VARIANT", str(variant))
+    wl = W.batched_6d(batches=3, batch=800, seed=104)
+    run_both(P, wl.batches, {0: (0, 1), 2: (0, 1)}, wl.heuristic, True, check_insert=False, lookahead=True)
+
+
+def test_lookahead_without_pruning_is_the_full_domain(P):
+    wl = W.batched_6d(batches=2, batch=900, seed=106)
+    G = gpu_graph(P)
+    for b in wl.batches:
+        G.insert_rows(b)
+    G.snapshot_save()
+    h = wl.heuristic(G.n)
+    g1, p1, s1 = G.replan(0, 1, h, False, lookahead=True)
+    G.snapshot_restore()
+    g2, p2, s2 = G.replan(0, 1, h, False, lookahead=False)
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32)) and np.array_equal(p1, p2)
+    assert_same_stats("lookahead without pruning", s1, s2)
+
+
+def test_lookahead_worked_example(P):
+    """The hand-worked five-vertex example of the oracle pins, on the device."""
+    from oracle_pins import lookahead_example
+    edges, h, parent, pcost = lookahead_example()
+    want = {False: (2, 5, 8, 16, 1), True: (2, 5, 4, 10, 1)}
+    for look in (False, True):
+        G = gpu_graph(P)
+        G.insert_rows(W.from_edges(5, edges))
+        G.set_policy(np.zeros(5, np.float32), parent, pcost)
+        g, p, st = G.replan(0, 1, h, True, lookahead=look)
+        got = (st["iterations"], st["sum_P"], st["sum_D"], st["edges_examined"], st["changed_total"])
+        assert got == want[look], (look, got)
+        assert np.array_equal(g, np.array([0, 2, 1, 0.5, 1.5], np.float32))
+        assert np.array_equal(p, np.array([-1, 2, 0, 0, 2], np.int32))

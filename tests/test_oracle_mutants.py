@@ -32,7 +32,10 @@ MUTANTS = {
     "insert_orphan_zero": ("    G->g[v] = best;\n", "    G->g[v] = best_u >= 0 ? best : 0.0f;\n"),
     "evaluate_wrong_index": ("G->g[c] = G->g[v] + G->pcost[c];", "G->g[c] = G->g[v] + G->pcost[v];"),
     "evaluate_no_reset": ("for (int64_t v = 0; v < n; ++v) G->g[v] = INFINITY;", ""),
-    "domain_without_neighbours": ("for (int32_t j = 0; j < G->deg[v]; ++j) inD[G->nbr[v][j]] = 1;", ""),
+    "domain_without_neighbours": ("        inD[w] = 1;\n", ""),
+    "lookahead_drops_heuristic": ("float f = offer + (h ? h[w] : 0.0f);", "float f = offer;"),
+    "lookahead_target_g": ("float offer = G->g[v] + G->cst[v][j];", "float offer = G->g[w] + G->cst[v][j];"),
+    "lookahead_ignored": ("        if (lookahead) {", "        if (0) {"),
     "domain_keeps_root": ("inD[root] = 0;", ""),
     "promising_non_strict": ("inP[v] = f < thr;", "inP[v] = f <= thr;"),
     "threshold_wrong_vertex": ("float thr = prune ? G->g[goal] : INFINITY;", "float thr = prune ? G->g[root] : INFINITY;"),
