@@ -496,6 +496,108 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """Batched-Extension batch-size sweep (the paper's planning-time experiment, Sec.
+    VI and Alg. 3) on the 2D scene of the small configuration (unit square, 8 boxes):
+    for each total sample count N and batch size S, grow the RRG S free samples at a
+    time (device sampler and radius search, r at the current n) and replan only when
+    the batch added a promising vertex (|B'| > |B|: a new vertex whose insertion-time
+    g + h is below g(goal)).  Planning time is the whole loop; exploitation runs on
+    the GPU (the library) or, for the CPU columns, in the serial oracle on the host."""
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    d = 2
+    root_goal = np.array([[0.05, 0.05], [0.95, 0.95]])
+    Ns = [int(x) for x in args.sweep_n.split(",")]
+    Ss = [int(x) for x in args.sweep_s.split(",")]
+
+    def plan(N, S, seed, cpu):
+        obs = W.make_obstacles(d, 8, "box", seed)
+        R = P.Rrg(d, obs, stream=stream, point_capacity=N + 2)
+        R.add_points(root_goal)
+        G = P.Graph(stream=stream, vertex_capacity=N + 2)
+        O = None
+        if cpu:
+            import oracle
+            O = oracle.Graph()
+            rp_, col_, cost_ = R.rows(0, W.radius(2, d))
+            assert O.insert(rp_, col_, cost_) == 0
+        else:
+            R.connect(0, W.radius(2, d), G)
+        counter, n_old, replans = 0, 2, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while R.n - 2 < N:
+            counter = R.sample(seed + 1, 0, counter, min(S, N - (R.n - 2)))
+            n = R.n
+            r = W.radius(n, d)
+            h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
+            if cpu:
+                rp_, col_, cost_ = R.rows(n_old, r)
+                assert O.insert(rp_, col_, cost_) == 0
+                g = O.state().g
+                hh = h.cpu().numpy()
+                if bool(((g[n_old:] + hh[n_old:]) < g[1]).any()):
+                    rc, _ = O.replan(0, 1, hh, True)
+                    assert rc == 0
+                    replans += 1
+            else:
+                R.connect(n_old, r, G)
+                g, _, _ = G.get_policy(device=dev)
+                if bool(((g[n_old:] + h[n_old:]) < g[1]).any().item()):
+                    G.replan(0, 1, h, True, g_out=g, parent_out=torch.empty(n, dtype=torch.int32, device=dev))
+                    replans += 1
+            n_old = n
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        cost = float(O.state().g[1]) if cpu else float(G.get_policy()[0][1])
+        return t, replans, cost
+
+    rows = []
+    for N in Ns:
+        for S in Ss:
+            for cpu in ([False, True] if not args.no_cpu_baseline else [False]):
+                if cpu and N * 1.0 / S > args.sweep_cpu_batches:
+                    continue  # bounded host time: the oracle leg skips the smallest batches
+                ts, rs, cs = [], [], []
+                for trial in range(args.sweep_trials):
+                    t, rp_n, c = plan(N, S, 500 + 10 * trial, cpu)
+                    ts.append(t)
+                    rs.append(rp_n)
+                    cs.append(c)
+                row = {"N": N, "S": S, "exploitation": "cpu oracle" if cpu else "gpu",
+                       "planning_s": round(float(np.mean(ts)), 4), "planning_s_std": round(float(np.std(ts)), 4),
+                       "replans": round(float(np.mean(rs)), 1), "final_cost": round(float(np.mean(cs)), 5)}
+                rows.append(row)
+                log("sweep: %s" % json.dumps(row))
+    gpu = {(r["N"], r["S"]): r["planning_s"] for r in rows if r["exploitation"] == "gpu"}
+    cpu = {(r["N"], r["S"]): r["planning_s"] for r in rows if r["exploitation"] != "gpu"}
+    speed = {}
+    for N in Ns:
+        if (N, 1) in gpu:
+            speed["N=%d" % N] = {"S=%d" % S: round(gpu[(N, 1)] / gpu[(N, S)], 2) for S in Ss if (N, S) in gpu}
+    out = {
+        "metric": "Batched-Extension planning time vs batch size (2D, 8 boxes); speedup over S=1",
+        "value": max((v for d_ in speed.values() for v in d_.values()), default=None), "unit": "x",
+        "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2D unit square, 8 boxes (sides U(0.05,0.2)), root (0.05,0.05), goal (0.95,0.95); "
+                               "N free samples in batches of S, r = (ln n/n)^(1/2) at the current n, Replan when a "
+                               "batch adds a promising vertex; %d trial(s) per cell" % args.sweep_trials,
+                   "N": Ns, "S": Ss},
+        "speedup_over_s1": speed,
+        "gpu_over_cpu_exploitation": {"N=%d,S=%d" % k: round(cpu[k] / gpu[k], 2) for k in cpu if k in gpu},
+        "cells": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -509,11 +611,16 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
-    ap.add_argument("--workload", choices=["plain6d", "multi", "learned"], default="plain6d",
+    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep"], default="plain6d",
                     help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan; "
                          "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
     ap.add_argument("--tune-each", action="store_true", help="multi: autotune every sequential graph too")
+    ap.add_argument("--sweep-n", default="10000,30000", help="sweep: total free samples per plan")
+    ap.add_argument("--sweep-s", default="1,3,10,30,100,300,1000", help="sweep: batch sizes")
+    ap.add_argument("--sweep-trials", type=int, default=2)
+    ap.add_argument("--sweep-cpu-batches", type=int, default=3000,
+                    help="sweep: oracle exploitation only for cells with at most this many batches")
     ap.add_argument("--config", type=int, default=-1,
                     help="plain6d: fixed kernel configuration 0-7 (row split + 4 x workgroup-scope stamps) instead "
                          "of the autotuner")
@@ -533,6 +640,9 @@ def main():
         sys.exit(2)
     if args.workload == "multi":
         bench_multi(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
     if args.workload == "learned":
         bench_learned(args)
