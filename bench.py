@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of the MI355X
+FP64_PEAK_TFLOPS = 78.6  # binary64 vector peak of the MI355X (fused multiply-adds counted as two)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 IMPROVE_SRC = os.path.join(ROOT, "paper_2003_04920_amd", "csrc", "improve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_6d_1m_traffic.txt")
@@ -312,6 +313,27 @@ def bench_learned(args):
         R.connect(0, W.radius(n, d), G)
         return obs, R, G
 
+    # ---- exploration support on its own: one 200k-vertex 6D graph, the radius search
+    # (two passes over every pair u < v, binary64 squared distance: 3d - 1 = 17 flops
+    # a pair, no fused multiply-add) and the segment tests
+    obs0 = W.make_obstacles(d, 40, "sphere", 19_990)
+    R0 = P.Rrg(d, obs0, stream=stream, point_capacity=n_train)
+    R0.add_points(root_goal)
+    R0.sample(19_991, 0, 0, n_train - 2)
+    G0 = P.Graph(stream=stream, vertex_capacity=n_train)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R0.connect(0, W.radius(n_train, d), G0)
+    torch.cuda.synchronize()
+    connect_s = time.perf_counter() - t0
+    pair_tests = 2 * n_train * (n_train - 1) // 2
+    tf = pair_tests * (3 * d - 1) / connect_s / 1e12
+    explore = {"points": n_train, "d": d, "connect_ms": round(1e3 * connect_s, 2), "directed_edges": G0.nnz,
+               "pair_tests": pair_tests, "fp64_tflops": round(tf, 2), "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+               "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
+    log("exploration: %s" % json.dumps(explore))
+    del R0, G0
+
     # ---- training data
     t0 = time.perf_counter()
     xs, ys = [], []
@@ -491,6 +513,7 @@ def bench_learned(args):
         "inference_us_per_8192": round(infer_us, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "exploration": explore,
         "layouts": rows,
     }
     print(json.dumps(out), flush=True)
@@ -758,6 +781,14 @@ def main():
                    "edges_examined": s3["edges_examined"], "gteps": round(s3["edges_examined"] / t_np / 1e9, 2)}
         log("pruning off: %s" % json.dumps(noprune))
 
+    # Evaluate (walk): every vertex once per call, 28 B each (parent 4, parent-edge cost 4,
+    # the 8-byte epoch stamp read and written, g written 4): a latency-bound pointer chase
+    ev_bytes = 28 * n * tst["evaluate_calls"]
+    ev_gbs = ev_bytes / (tst["ms_evaluate"] * 1e-3) / 1e9
+    evaluate = {"calls": tst["evaluate_calls"], "ms": round(tst["ms_evaluate"], 4),
+                "bytes_per_call": 28 * n, "achieved_GBs": round(ev_gbs, 1),
+                "frac_of_hbm_peak": round(ev_gbs / HBM_PEAK_GBS, 4)}
+
     extra = None
     if not args.no_extra and len(wl.batches) > 1:
         # a further 10,000-vertex batch on the converged 1M-vertex policy
@@ -827,6 +858,7 @@ def main():
                    "autotuned_config": tuned, "parallelism": "single GPU"},
         "phases_ms": {k: round(tst[k], 4) for k in ("ms_evaluate", "ms_mark", "ms_improve")},
         "roofline": roofline,
+        "evaluate": evaluate,
         "cpu_baseline": cpu,
         "extra_batch": extra,
         "pruning_off": noprune,
