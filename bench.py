@@ -621,6 +621,127 @@ def bench_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_async(args):
+    """Exploration concurrent with exploitation (the asynchronous scheme the paper
+    proposes as future work, Sec. VII), on the Batched-Extension 6D scene (40 spheres,
+    batches of 1,000, r at the current n): an explorer thread samples and builds the
+    rows of each batch on its own stream and queues them; the exploiter inserts every
+    queued batch and replans on another stream, so the radius searches of later batches
+    overlap the Replan of earlier ones.  Against the same loop run in lockstep (sample,
+    connect, Replan per batch).  The two build the same graph; the exploiter replans
+    less often (once per drained queue)."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d, N, S = 6, args.async_n, args.async_s
+    obs = W.make_obstacles(d, 40, "sphere", 100)
+    root_goal = np.stack([np.full(d, 0.05), np.full(d, 0.95)])
+
+    def lockstep():
+        st = torch.cuda.Stream()
+        R = P.Rrg(d, obs, stream=st.cuda_stream, point_capacity=N + 2)
+        R.add_points(root_goal)
+        G = P.Graph(stream=st.cuda_stream, vertex_capacity=N + 2)
+        R.connect(0, W.radius(2, d), G)
+        counter, n_old, replans = 0, 2, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(st):
+            while R.n - 2 < N:
+                counter = R.sample(101, 0, counter, min(S, N - (R.n - 2)))
+                n = R.n
+                R.connect(n_old, W.radius(n, d), G)
+                h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
+                g, _, _ = G.replan(0, 1, h, True)
+                replans += 1
+                n_old = n
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, replans, float(g[1].item()), G.n, G.nnz
+
+    def concurrent():
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        R = P.Rrg(d, obs, stream=sa.cuda_stream, point_capacity=N + 2)
+        R.add_points(root_goal)
+        G = P.Graph(stream=sb.cuda_stream, vertex_capacity=N + 2)
+        rp0, c0, w0 = R.rows(0, W.radius(2, d), device=dev)
+        sa.synchronize()
+        with torch.cuda.stream(sb):
+            G.insert_batch(rp0, c0, w0)
+        q = queue.Queue()
+        err = []
+
+        def explorer():
+            try:
+                with torch.cuda.stream(sa):
+                    counter, n_old = 0, 2
+                    while R.n - 2 < N:
+                        counter = R.sample(101, 0, counter, min(S, N - (R.n - 2)))
+                        n = R.n
+                        rp, col, cost = R.rows(n_old, W.radius(n, d), device=dev)
+                        h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
+                        sa.synchronize()
+                        q.put((rp, col, cost, h))
+                        n_old = n
+            except Exception as e:  # reported by the exploiter
+                err.append(e)
+            q.put(None)
+
+        replans, done, g = 0, False, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = threading.Thread(target=explorer)
+        th.start()
+        with torch.cuda.stream(sb):
+            while not done:
+                items = [q.get()]
+                while True:
+                    try:
+                        items.append(q.get_nowait())
+                    except queue.Empty:
+                        break
+                h = None
+                for it in items:
+                    if it is None:
+                        done = True
+                        continue
+                    rp, col, cost, h = it
+                    G.insert_batch(rp, col, cost)
+                if h is not None:
+                    g, _, _ = G.replan(0, 1, h, True)
+                    replans += 1
+        th.join()
+        torch.cuda.synchronize()
+        if err:
+            raise err[0]
+        return time.perf_counter() - t0, replans, float(g[1].item()), G.n, G.nnz
+
+    lockstep()  # warm-up (kernel loading, allocations)
+    t_l, r_l, c_l, n_l, m_l = lockstep()
+    t_c, r_c, c_c, n_c, m_c = concurrent()
+    assert (n_l, m_l) == (n_c, m_c), ((n_l, m_l), (n_c, m_c))
+    out = {
+        "metric": "Exploration concurrent with exploitation: planning time, lockstep / concurrent",
+        "value": round(t_l / t_c, 3), "unit": "x", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "6D unit cube, 40 spheres; %d free samples in batches of %d, r = (ln n/n)^(1/6) at "
+                               "the current n, h = Euclidean distance to goal; explorer and exploiter on two "
+                               "streams of one GPU" % (N, S), "vertices": n_l, "directed_edges": m_l},
+        "lockstep": {"seconds": round(t_l, 3), "replans": r_l, "final_cost": c_l},
+        "concurrent": {"seconds": round(t_c, 3), "replans": r_c, "final_cost": c_c},
+    }
+    log("lockstep: %s" % json.dumps(out["lockstep"]))
+    log("concurrent: %s" % json.dumps(out["concurrent"]))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -634,7 +755,7 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
-    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep"], default="plain6d",
+    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep", "async"], default="plain6d",
                     help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan; "
                          "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
@@ -642,6 +763,8 @@ def main():
     ap.add_argument("--sweep-n", default="10000,30000", help="sweep: total free samples per plan")
     ap.add_argument("--sweep-s", default="1,3,10,30,100,300,1000", help="sweep: batch sizes")
     ap.add_argument("--sweep-trials", type=int, default=2)
+    ap.add_argument("--async-n", type=int, default=100_000, help="async: free samples")
+    ap.add_argument("--async-s", type=int, default=1000, help="async: batch size")
     ap.add_argument("--sweep-cpu-batches", type=int, default=3000,
                     help="sweep: oracle exploitation only for cells with at most this many batches")
     ap.add_argument("--config", type=int, default=-1,
@@ -666,6 +789,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "async":
+        bench_async(args)
         return
     if args.workload == "learned":
         bench_learned(args)

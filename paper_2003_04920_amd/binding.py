@@ -505,8 +505,28 @@ class Rrg:
         self._check(self._lib.pirrt_rrg_get_points(self._h, first, count, _ptr(out), PIRRT_MEM_HOST))
         return out
 
-    def rows(self, n_old: int, radius: float):
-        """Forward rows (row_ptr, col, cost) of points n_old .. n-1, on the host."""
+    def rows(self, n_old: int, radius: float, device=None, capacity: Optional[int] = None):
+        """Forward rows (row_ptr, col, cost) of points n_old .. n-1, on the host, or as
+        device tensors with `device` (one radius search when `capacity` entries suffice,
+        default 128 a row)."""
+        if device is not None:
+            import torch
+            rows = self.n - n_old
+            cap = int(capacity if capacity is not None else max(rows, 1) * 128)
+            nnz = ctypes.c_int64(0)
+            rp = torch.empty(rows + 1, dtype=torch.int64, device=device)
+            for _ in range(2):
+                col = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+                cost = torch.empty(max(cap, 1), dtype=torch.float32, device=device)
+                rc = self._lib.pirrt_rrg_rows(self._h, n_old, radius, _ptr(rp), _ptr(col), _ptr(cost), cap,
+                                              ctypes.byref(nnz), PIRRT_MEM_DEVICE)
+                if rc == PIRRT_OK:
+                    m = int(nnz.value)
+                    return rp, col[:m], cost[:m]
+                if rc != PIRRT_EINVAL or nnz.value <= cap:
+                    self._check(rc)
+                cap = int(nnz.value)
+            self._check(rc)
         nnz = ctypes.c_int64(0)
         rp = np.empty(self.n - n_old + 1, np.int64)
         rc = self._lib.pirrt_rrg_rows(self._h, n_old, radius, _ptr(rp), None, None, 0, ctypes.byref(nnz),
