@@ -54,6 +54,12 @@ def test_sample_rows_heuristic(P, d, count, kinds):
     assert np.array_equal(cost2.view(np.uint32), ocost2.view(np.uint32))
     h = G.heuristic(1)
     assert np.array_equal(h.view(np.uint32), R.heuristic(pts, pts[1]).view(np.uint32))
+    # the same rows into device buffers: room enough, and too little room (one retry)
+    import torch
+    for cap in (None, 3):
+        drp, dcol, dcost = G.rows(n + 2 - k, r, device=torch.device("cuda:0"), capacity=cap)
+        assert np.array_equal(drp.cpu().numpy(), orp2) and np.array_equal(dcol.cpu().numpy(), ocol2)
+        assert np.array_equal(dcost.cpu().numpy().view(np.uint32), ocost2.view(np.uint32))
 
 
 def test_connect_and_replan_in_batches(P):
