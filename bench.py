@@ -742,6 +742,64 @@ def bench_async(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_breakeven(args):
+    """Replan time against graph size, GPU library and serial oracle side by side (the
+    paper's exploitation-time comparison, Sec. VI): 2D scene of the small configuration
+    (unit square, 8 boxes), n free samples in one batch, one full Replan from the
+    insertion-time policy with pruning on.  The break-even size is where the library
+    overtakes the oracle on one host thread."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for n in [int(x) for x in args.breakeven_n.split(",")]:
+        wl = W.plain_2d(samples=n, seed=0)
+        b = wl.batches[0]
+        h = wl.heuristic(wl.n)
+        G = P.Graph(stream=stream)
+        G.insert_rows(b)
+        G.snapshot_save()
+        hd = torch.from_numpy(h).to(dev)
+        ts = []
+        for i in range(7):
+            G.snapshot_restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = G.replan(0, 1, hd, True)
+            ts.append(time.perf_counter() - t0)
+        gpu_ms = 1e3 * float(np.median(ts[2:]))
+        O = oracle.Graph()
+        assert O.insert_batch(b) == 0
+        t0 = time.perf_counter()
+        rc, so = O.replan(0, 1, h, True)
+        cpu_ms = 1e3 * (time.perf_counter() - t0)
+        assert rc == 0 and so["edges_examined"] == st["edges_examined"]
+        row = {"n": wl.n, "directed_edges": 2 * b.nnz, "iterations": st["iterations"],
+               "edges_examined": st["edges_examined"], "gpu_ms": round(gpu_ms, 3), "cpu_oracle_ms": round(cpu_ms, 3),
+               "speedup": round(cpu_ms / gpu_ms, 2)}
+        rows.append(row)
+        log("breakeven: %s" % json.dumps(row))
+    n0 = next((r["n"] for r in rows if r["speedup"] > 1.0), None)
+    out = {
+        "metric": "Replan time vs graph size, GPU library against the serial oracle (2D, 8 boxes)",
+        "value": n0, "unit": "vertices (break-even)", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D unit square, 8 boxes; n free samples in one batch, r = (ln n/n)^(1/2); one full "
+                               "Replan from the insertion-time policy, pruning on, h = Euclidean distance to goal; "
+                               "GPU: median of 5 after 2 warm-ups, synchronous call; oracle: one serial run"},
+        "cpu_baseline": {"kind": "oracle", "cores": 1, "unit": "ms", "sample": "one Replan per size"},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -755,7 +813,7 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
-    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep", "async"], default="plain6d",
+    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep", "async", "breakeven"], default="plain6d",
                     help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan; "
                          "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
@@ -764,6 +822,8 @@ def main():
     ap.add_argument("--sweep-s", default="1,3,10,30,100,300,1000", help="sweep: batch sizes")
     ap.add_argument("--sweep-trials", type=int, default=2)
     ap.add_argument("--async-n", type=int, default=100_000, help="async: free samples")
+    ap.add_argument("--breakeven-n", default="100,300,1000,3000,10000,30000,100000,300000",
+                    help="breakeven: free samples per graph")
     ap.add_argument("--async-s", type=int, default=1000, help="async: batch size")
     ap.add_argument("--sweep-cpu-batches", type=int, default=3000,
                     help="sweep: oracle exploitation only for cells with at most this many batches")
@@ -792,6 +852,9 @@ def main():
         return
     if args.workload == "async":
         bench_async(args)
+        return
+    if args.workload == "breakeven":
+        bench_breakeven(args)
         return
     if args.workload == "learned":
         bench_learned(args)
