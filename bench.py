@@ -931,6 +931,12 @@ def main():
                 "kernel": "k_improve", "launches": tst["improve_launches"],
                 "avg_launch_us": round(1e3 * tst["ms_improve"] / max(1, tst["improve_launches"]), 2),
                 "bytes_per_launch": int(nbytes / max(1, tst["improve_launches"]))}
+    # the 4-byte g gather of every examined edge, counted separately (it is served mostly
+    # by L2 and MALL, and `traffic` shows what it costs in fetched lines)
+    gbytes = nbytes + 4 * tst["edges_examined"]
+    achieved_g = gbytes / (tst["ms_improve"] * 1e-3) / 1e9
+    roofline["with_gather"] = {"achieved": round(achieved_g, 1), "frac": round(achieved_g / HBM_PEAK_GBS, 4),
+                               "bytes_per_launch": int(gbytes / max(1, tst["improve_launches"]))}
 
     goal_exact = float(g_out[1].item())
     # the narrowed Improve domain (PIRRT_LOOKAHEAD) on the same graph and policy

@@ -167,6 +167,7 @@ struct pirrt_graph {
   int32_t mid_hint = 64;
   int row_variant = 2;
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
+  bool small_graphs = true;  // single-workgroup Replan up to kSmallMax vertices (PIRRT_SMALL=0: off)
   bool poisoned = false;
   std::string err;
 };
@@ -897,6 +898,29 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   int64_t lb = (int64_t)n / 2048;
   ea.level_blocks = (int32_t)(lb < 16 ? 16 : (lb > 1024 ? 1024 : lb));
   if (G->eval_levels && P != 1) return fail(G, PIRRT_EINVAL, "the level-synchronous Evaluate takes one problem");
+  if (P == 1 && !G->batched && n <= kSmallMax && G->small_graphs && !timing && !G->trace && !G->eval_levels) {
+    // one workgroup runs the whole loop
+    launch_replan_small(n, G->rp, G->col, G->cst, h, G->ext_of, prune, G->lookahead, G->ps, G->parent, G->pcost,
+                        G->g, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->hps, G->ps, sizeof(ProblemState), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    const ProblemState& q = G->hps[0];
+    if (stats) {
+      pirrt_stats& st = stats[0];
+      memset(&st, 0, sizeof(st));
+      st.iterations = q.iterations;
+      st.edges_examined = (int64_t)q.edges;
+      st.sum_P = (int64_t)q.sum_P;
+      st.sum_D = (int64_t)q.sum_D;
+      st.changed_total = (int64_t)q.changed_total;
+      st.evaluate_calls = q.iterations;
+      st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    G->last_iterations = q.iterations;
+    if (q.status != 0) return fail(G, PIRRT_ENOTCONVERGED, "iteration cap reached");
+    return PIRRT_OK;
+  }
 
   pirrt_stats agg;
   memset(&agg, 0, sizeof(agg));
@@ -1178,6 +1202,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   if (wc) G->walk_coherent = atoi(wc) != 0;
   const char* gr = getenv("PIRRT_GRAPH");
   if (gr) G->use_graph = atoi(gr) != 0;
+  const char* sm = getenv("PIRRT_SMALL");
+  if (sm) G->small_graphs = atoi(sm) != 0;
   const char* variant = getenv("PIRRT_ROW_VARIANT");
   if (variant) {
     int v = atoi(variant);

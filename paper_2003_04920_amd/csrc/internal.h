@@ -164,6 +164,15 @@ struct StepArgs {
   bool lookahead;            // narrowed domain: stamp a neighbour only for a promising offer
 };
 constexpr int kRowVariants = 4;
+// One small graph (n <= kSmallMax vertices; the single workgroup is faster than the
+// multi-kernel loop up to about 1,700 vertices of a 2D graph) replanned by a single workgroup with its
+// vertex state in LDS: the whole loop in one launch (small.hip).  Reads the root,
+// goal and cap from ps[0] and leaves the counters and status there; parent / pcost
+// are read and written in place (the root's entries untouched), g written.
+constexpr int32_t kSmallMax = 1536;
+void launch_replan_small(int32_t n, const int64_t* rp, const int32_t* col, const float* cst, const float* h,
+                         const int32_t* ext_of, bool prune, bool lookahead, ProblemState* ps, int32_t* parent,
+                         float* pcost, float* g, hipStream_t s);
 void launch_mark(const StepArgs& a, int variant, hipStream_t s);
 // Compacts the stamped slots into dlist / ctl->ndomain (and clears every stamp when
 // the next mark epoch wraps its low byte).

@@ -419,3 +419,47 @@ def test_lookahead_worked_example(P):
         assert got == want[look], (look, got)
         assert np.array_equal(g, np.array([0, 2, 1, 0.5, 1.5], np.float32))
         assert np.array_equal(p, np.array([-1, 2, 0, 0, 2], np.int32))
+
+
+@pytest.mark.parametrize("prune,lookahead", [(True, False), (False, False), (True, True)])
+def test_single_workgroup_path_agrees(P, monkeypatch, prune, lookahead):
+    """Graphs of up to 1,536 vertices take the single-workgroup Replan; the multi-kernel
+    loop (PIRRT_SMALL=0) and the oracle must give the same policy and counters."""
+    cases = [W.plain_2d(samples=1530, seed=3), W.batched_6d(batches=2, batch=700, seed=107),
+             W.plain_2d(samples=60, seed=5), W.plain_2d(samples=1534, seed=6)]
+    for wl in cases:
+        outs = []
+        for small in ("1", "0"):
+            monkeypatch.setenv("PIRRT_SMALL", small)
+            G = gpu_graph(P)
+            for b in wl.batches:
+                G.insert_rows(b)
+            h = wl.heuristic(G.n)
+            g, p, st = G.replan(0, 1, h, prune, lookahead=lookahead)
+            outs.append((np.asarray(g).copy(), np.asarray(p).copy(), st))
+        R = O.Graph()
+        for b in wl.batches:
+            assert R.insert_batch(b) == 0
+        rc, so = R.replan(0, 1, wl.heuristic(R.n), prune, lookahead=lookahead)
+        st_o = R.state()
+        for tag, (g, p, st) in zip(("single workgroup", "multi-kernel"), outs):
+            assert_same_policy("%s %s" % (wl.name, tag), g, p, st_o.g, st_o.parent)
+            assert_same_stats("%s %s" % (wl.name, tag), st, so)
+
+
+def test_single_workgroup_iteration_cap(P):
+    """The cap inside the single-workgroup loop: ENOTCONVERGED after exactly the capped
+    passes, with the oracle's policy at that point."""
+    wl = W.plain_2d(samples=1500, seed=4)
+    for cap in (1, 2, 3):
+        G = gpu_graph(P, max_iters=cap)
+        G.insert_rows(wl.batches[0])
+        h = wl.heuristic(G.n)
+        g, p, st = G.replan(0, 1, h, True, allow_not_converged=True)
+        R = O.Graph()
+        assert R.insert_batch(wl.batches[0]) == 0
+        rc, so = R.replan(0, 1, h, True, max_iters=cap)
+        assert rc == O.ENOTCONVERGED and st["rc"] == P.PIRRT_ENOTCONVERGED
+        fin = R.state()
+        assert_same_policy("cap %d" % cap, g, p, fin.g, fin.parent)
+        assert_same_stats("cap %d" % cap, st, so)
