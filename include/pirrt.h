@@ -60,9 +60,9 @@ enum {
                                vertex is promising */
   PIRRT_TIMING = 1u << 1,   /* time each phase with HIP events (fills the ms_* and
                                per-kernel fields of pirrt_stats; adds event overhead) */
-  PIRRT_LOOKAHEAD = 1u << 2 /* narrowed Improve domain, a work-reduction variant of the
-                               "promising vertices and their neighbours" rule of Sec.
-                               IV-C: a neighbour w of a promising u joins the domain only
+  PIRRT_LOOKAHEAD = 1u << 2 /* narrowed Improve domain, a work-reduction variant of Sec.
+                               IV-C's domain (promising vertices plus their neighbours):
+                               a neighbour w of a promising u joins the domain only
                                if fl(fl(g(u) + c(u,w)) + h(w)) < G, i.e. if the candidate u
                                offers could be promising; promising vertices stay in.
                                Improve itself is unchanged.  The fixed point differs from
