@@ -842,7 +842,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Replan library runs on a single device and "
-              "this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
+              "the library has no multi-GPU path (--gpus %d requested)" % args.gpus)
         sys.exit(2)
     if args.workload == "multi":
         bench_multi(args)
