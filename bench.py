@@ -800,6 +800,77 @@ def bench_breakeven(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_berrt6d(args):
+    """The Batched-Extension 6D configuration: 100,000 vertices inserted in batches of
+    1,000 (r at the current n, 40 spheres), a full Replan (pruning on, h = Euclidean
+    distance to goal) after every batch.  Reports Replan time per batch and in total,
+    iterations and edges examined, and the serial oracle on the first batches."""
+    import numpy as np
+    import torch
+
+    import paper_2003_04920_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.time()
+    wl = W.batched_6d(batches=args.berrt_batches, batch=args.berrt_batch, seed=100)
+    log("workload %s: n=%d, %d batches (%.1fs)" % (wl.name, wl.n, len(wl.batches), time.time() - t0))
+
+    def run(timed_graph):
+        G = P.Graph(stream=stream)
+        per = []
+        edges = iters = 0
+        for b in wl.batches:
+            G.insert_rows(b)
+            h = torch.from_numpy(wl.heuristic(G.n)).to(dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g, _, st = G.replan(0, 1, h, True)
+            per.append(time.perf_counter() - t1)
+            edges += st["edges_examined"]
+            iters += st["iterations"]
+        return per, edges, iters, float(g[1].item())
+
+    run(False)  # warm-up: kernel loading and allocations
+    per, edges, iters, cost = run(True)
+    tot = sum(per)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        R = oracle.Graph()
+        spent = cpu_edges = 0
+        used = 0
+        for b in wl.batches:
+            assert R.insert_batch(b) == 0
+            t1 = time.perf_counter()
+            rc, so = R.replan(0, 1, wl.heuristic(R.n), True)
+            spent += time.perf_counter() - t1
+            assert rc == 0
+            cpu_edges += so["edges_examined"]
+            used += 1
+            if spent > 15.0:
+                break
+        gpu_same = sum(per[:used])
+        cpu = {"value": round(cpu_edges / spent / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "the Replans after the first %d batches (serial C oracle, one thread, %.2f s; the library "
+                         "took %.3f s for the same Replans)" % (used, spent, gpu_same)}
+        log("cpu baseline: %s" % json.dumps(cpu))
+    out = {
+        "metric": "Batched-Extension 6D: Replan after every batch, GTEPS over all Replans",
+        "value": round(edges / tot / 1e9, 3), "unit": "GTEPS", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "6D unit cube, 40 spheres; %d batches of %d free samples, r = (ln n/n)^(1/6) at "
+                               "the current n; full Replan after every batch, pruning on, h = Euclidean distance "
+                               "to goal" % (len(wl.batches), args.berrt_batch), "vertices": wl.n},
+        "replans": len(per), "replan_total_ms": round(1e3 * tot, 2), "replan_mean_ms": round(1e3 * tot / len(per), 3),
+        "replan_last_ms": round(1e3 * per[-1], 3), "iterations_total": iters, "edges_examined": edges,
+        "final_cost": cost, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -813,7 +884,7 @@ def main():
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR(s) and exit")
-    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep", "async", "breakeven"], default="plain6d",
+    ap.add_argument("--workload", choices=["plain6d", "multi", "learned", "sweep", "async", "breakeven", "berrt6d"], default="plain6d",
                     help="plain6d: the 6D 1M-vertex Replan (default); multi: batched multi-graph Replan; "
                          "learned: learned proposal trained and compared with the uniform planner")
     ap.add_argument("--problems", type=int, default=512, help="problems of the multi workload")
@@ -822,6 +893,8 @@ def main():
     ap.add_argument("--sweep-s", default="1,3,10,30,100,300,1000", help="sweep: batch sizes")
     ap.add_argument("--sweep-trials", type=int, default=2)
     ap.add_argument("--async-n", type=int, default=100_000, help="async: free samples")
+    ap.add_argument("--berrt-batches", type=int, default=100, help="berrt6d: batches")
+    ap.add_argument("--berrt-batch", type=int, default=1000, help="berrt6d: free samples per batch")
     ap.add_argument("--breakeven-n", default="100,300,1000,3000,10000,30000,100000,300000",
                     help="breakeven: free samples per graph")
     ap.add_argument("--async-s", type=int, default=1000, help="async: batch size")
@@ -855,6 +928,9 @@ def main():
         return
     if args.workload == "breakeven":
         bench_breakeven(args)
+        return
+    if args.workload == "berrt6d":
+        bench_berrt6d(args)
         return
     if args.workload == "learned":
         bench_learned(args)
