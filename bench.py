@@ -10,6 +10,12 @@ Prints one JSON line.  `value` is Replan GTEPS = edges examined by Improve / wal
 time of the timed steps.  `roofline` is the Improve kernel against HBM bandwidth,
 timed with HIP events on the library's stream; `cpu_baseline` is the serial
 oracle on this host's cores for one Replan of the same graph.
+
+Other records (`--workload`): multi (512 problems batched against one call each),
+learned (the learned sampling proposal: training, inference, planner comparison),
+sweep (Batched-Extension planning time against batch size, 2D), async (exploration
+concurrent with exploitation), breakeven (Replan time against graph size, library
+and oracle), berrt6d (100 batches of 1,000 in 6D, Replan after each).
 """
 from __future__ import annotations
 
