@@ -826,10 +826,14 @@ def bench_berrt6d(args):
 
     def run(timed_graph):
         G = P.Graph(stream=stream)
-        per = []
+        per, ins = [], []
         edges = iters = 0
         for b in wl.batches:
-            G.insert_rows(b)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            G.insert_rows(b)  # host rows: includes their copy and, now and then, the renumbering
+            torch.cuda.synchronize()
+            ins.append(time.perf_counter() - t1)
             h = torch.from_numpy(wl.heuristic(G.n)).to(dev)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -837,10 +841,10 @@ def bench_berrt6d(args):
             per.append(time.perf_counter() - t1)
             edges += st["edges_examined"]
             iters += st["iterations"]
-        return per, edges, iters, float(g[1].item())
+        return per, ins, edges, iters, float(g[1].item())
 
     run(False)  # warm-up: kernel loading and allocations
-    per, edges, iters, cost = run(True)
+    per, ins, edges, iters, cost = run(True)
     tot = sum(per)
     cpu = None
     if not args.no_cpu_baseline:
@@ -871,7 +875,8 @@ def bench_berrt6d(args):
                                "the current n; full Replan after every batch, pruning on, h = Euclidean distance "
                                "to goal" % (len(wl.batches), args.berrt_batch), "vertices": wl.n},
         "replans": len(per), "replan_total_ms": round(1e3 * tot, 2), "replan_mean_ms": round(1e3 * tot / len(per), 3),
-        "replan_last_ms": round(1e3 * per[-1], 3), "iterations_total": iters, "edges_examined": edges,
+        "replan_last_ms": round(1e3 * per[-1], 3), "insert_total_ms": round(1e3 * sum(ins), 2),
+        "iterations_total": iters, "edges_examined": edges,
         "final_cost": cost, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

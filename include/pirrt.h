@@ -159,7 +159,8 @@ int pirrt_replan(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uin
  * Evaluate's stamps (device, workgroup) -- each from the current policy, keeps the
  * fastest for later calls on this handle and restores the policy (results never
  * depend on the configuration).  *config (nullable) receives the index chosen,
- * row split + 4 x (workgroup-scope stamps).
+ * row split + 4 x (workgroup-scope stamps).  Without a tuning call a handle uses
+ * configuration 5 (8x2, workgroup-scope stamps).
  */
 int pirrt_tune(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uint32_t flags, int mem_kind,
                int32_t* config);
