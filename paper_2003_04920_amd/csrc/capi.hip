@@ -170,6 +170,8 @@ struct pirrt_graph {
   int32_t mid_hint = 64;
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
+  LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
+  bool have_prev_key = false;
   bool small_graphs = true;  // single-workgroup Replan up to kSmallMax vertices (PIRRT_SMALL=0: off)
   bool poisoned = false;
   std::string err;
@@ -976,13 +978,26 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
     }
   } else {
     // Planned launches: as many loop bodies as the previous Replan needed, back to
-    // back, then one iteration at a time until every problem has stopped.
+    // back, then one iteration at a time until every problem has stopped.  The loop
+    // bodies are captured graphs when this call's arguments (sizes, arrays) repeat the
+    // previous call's; a graph that changes every call (a planner inserting a batch
+    // before each Replan) would cost its capture and instantiation every time, so such
+    // calls enqueue the same kernels directly.
+    const LoopKey key1 = loop_key(G, L, 1);
+    const bool graphs = G->have_prev_key && G->prev_key == key1;
+    G->prev_key = key1;
+    G->have_prev_key = true;
     int64_t plan = G->last_iterations > 0 ? G->last_iterations : 8;
     for (;;) {
       const int k = plan >= 8 ? 3 : plan >= 4 ? 2 : plan >= 2 ? 1 : 0;
-      hipGraphExec_t exec = nullptr;
-      if ((rc = loop_graph(G, L, k, &exec))) return rc;
-      HIP_OR_FAIL(G, hipGraphLaunch(exec, s));
+      if (graphs) {
+        hipGraphExec_t exec = nullptr;
+        if ((rc = loop_graph(G, L, k, &exec))) return rc;
+        HIP_OR_FAIL(G, hipGraphLaunch(exec, s));
+      } else {
+        for (int i = 0; i < (1 << k); ++i) enqueue_iteration(G, L, s, false);
+        HIP_OR_FAIL(G, hipGetLastError());
+      }
       done_iters += 1 << k;
       plan -= 1 << k;
       if (plan > 0) continue;
