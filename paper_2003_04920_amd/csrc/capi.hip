@@ -28,7 +28,7 @@ struct HostBlock {
   LoopCtl ctl;
   unsigned long long hops;
   int32_t flag;
-  int32_t count[2];
+  int32_t count[3];
   int64_t word;
 };
 
@@ -707,24 +707,29 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
   drop_loops(G);
   // insertion-time policy, one dependency level at a time
   const int32_t insert_root = new_problem ? (int32_t)n_old : (n_old == 0 ? 0 : -1);
-  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 2 * sizeof(int32_t), s));
+  // dcount[0] / dcount[1]: the frontier sizes of alternate levels; dcount[2]: vertices
+  // placed.  Levels go out kLevelsPerCheck at a time (a level past the last one finds
+  // an empty frontier and does nothing), then one read-back tells whether more remain.
+  constexpr int kLevelsPerCheck = 4;
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 3 * sizeof(int32_t), s));
   launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
   HIP_OR_FAIL(G, hipGetLastError());
-  int64_t done = 0;
-  for (int level = 0;; ++level) {
-    const int cur = level & 1, nxt = cur ^ 1;
-    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->count[cur], &G->dcount[cur], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  for (int64_t level = 0;;) {
+    for (int i = 0; i < kLevelsPerCheck; ++i, ++level) {
+      const int cur = (int)(level & 1), nxt = cur ^ 1;
+      HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
+      launch_insert_level(n_new, &G->dcount[cur], &G->dcount[2], cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp,
+                          G->bcol, G->bslot, G->bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending,
+                          nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
+      HIP_OR_FAIL(G, hipGetLastError());
+    }
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->count, G->dcount, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    const int32_t size = G->host->count[cur];
-    if (size == 0) break;
-    done += size;
-    if (done > n_new) return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
-    HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
-    launch_insert_level(size, cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp, G->bcol, G->bslot, G->bcost, G->rp,
-                        G->col, G->g, G->parent, G->pcost, G->pending, nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
-    HIP_OR_FAIL(G, hipGetLastError());
+    if (G->host->count[level & 1] == 0) break;  // the next level's frontier is empty
+    if (G->host->count[2] > n_new || level > (int64_t)n_new + kLevelsPerCheck)
+      return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
   }
-  if (done != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
+  if (G->host->count[2] != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
   if (new_problem) {
     G->renumber_pending = true;
   } else if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
@@ -1164,7 +1169,7 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     *rc_out = PIRRT_EDEVICE;
     return nullptr;
   }
-  bool ok = dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 2) && dalloc(&G->dhops, 1) &&
+  bool ok = dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 3) && dalloc(&G->dhops, 1) &&
             dalloc(&G->ctl, 1);
   if (ok && hipHostMalloc((void**)&G->host, sizeof(HostBlock), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();

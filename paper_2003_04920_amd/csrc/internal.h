@@ -28,11 +28,14 @@ void launch_append(int32_t n_new, int64_t n_old, int64_t nnz_old, const int64_t*
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s);
 // bcol: neighbour ids as given (tie-break keys); bslot: the same in storage slots.
-// insert_root: the new vertex that gets g = 0 (x_init), or -1.
-void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, int32_t insert_root,
-                         const int64_t* brp, const int32_t* bcol, const int32_t* bslot, const float* bcost,
-                         const int64_t* rp, const int32_t* col, float* g, int32_t* parent, float* pcost,
-                         int32_t* pending, int32_t* next, int32_t* ncount, hipStream_t s);
+// insert_root: the new vertex that gets g = 0 (x_init), or -1.  The level's frontier
+// size is read on the device from *fsize (the grid covers max_size threads), and
+// *done accumulates the sizes, so several levels go out without a host round trip.
+void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, const int32_t* frontier,
+                         int64_t n_old, int32_t insert_root, const int64_t* brp, const int32_t* bcol,
+                         const int32_t* bslot, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
+                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
+                         hipStream_t s);
 
 // ---- reorder.hip ----
 struct PermuteArgs {

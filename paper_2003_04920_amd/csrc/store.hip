@@ -141,7 +141,9 @@ __global__ void __launch_bounds__(kThreads) k_pending(int32_t n_new, int64_t n_o
 // has all its lower neighbours final, so its local relaxation is final too.  The
 // minimum is over (g(u) + c, u, c) with u the caller's id (bcol); g is read at the
 // storage slot (bslot).  New vertices occupy slots equal to their ids.
-__global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const int32_t* __restrict__ frontier,
+__global__ void __launch_bounds__(kThreads) k_insert_level(const int32_t* __restrict__ fsize_dev,
+                                                          int32_t* __restrict__ done,
+                                                          const int32_t* __restrict__ frontier,
                                                           int64_t n_old, int32_t insert_root,
                                                           const int64_t* __restrict__ brp,
                                                           const int32_t* __restrict__ bcol,
@@ -152,7 +154,9 @@ __global__ void __launch_bounds__(kThreads) k_insert_level(int32_t fsize, const 
                                                           int32_t* __restrict__ parent, float* __restrict__ pcost,
                                                           int32_t* __restrict__ pending,
                                                           int32_t* __restrict__ next, int32_t* __restrict__ ncount) {
+  const int32_t fsize = *fsize_dev;  // this level's frontier (the grid covers the whole batch)
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && fsize > 0) atomicAdd(done, fsize);
   if (t >= fsize) return;
   const int32_t v = frontier[t];
   const int64_t i = v - n_old;
@@ -258,11 +262,12 @@ void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
                      frontier, fcount);
 }
 
-void launch_insert_level(int32_t fsize, const int32_t* frontier, int64_t n_old, int32_t insert_root,
-                         const int64_t* brp, const int32_t* bcol, const int32_t* bslot, const float* bcost,
-                         const int64_t* rp, const int32_t* col, float* g, int32_t* parent, float* pcost,
-                         int32_t* pending, int32_t* next, int32_t* ncount, hipStream_t s) {
-  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(fsize)), dim3(kThreads), 0, s, fsize, frontier, n_old,
+void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, const int32_t* frontier,
+                         int64_t n_old, int32_t insert_root, const int64_t* brp, const int32_t* bcol,
+                         const int32_t* bslot, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
+                         int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(max_size)), dim3(kThreads), 0, s, fsize, done, frontier, n_old,
                      insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
 }
 
