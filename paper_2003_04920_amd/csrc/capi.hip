@@ -1072,11 +1072,13 @@ int stage_h(pirrt_graph* G, const float* h, int mem_kind, const float** out) {
   return PIRRT_OK;
 }
 
-// Autotuner: the Replan of the call is run once per kernel configuration -- the
+// Autotuner: the Replan of the call is run for each kernel configuration -- the
 // Improve / mark row split (lanes per row x quads in flight) and the scope of the
 // walk's Evaluate stamps (device or workgroup) -- each from the same policy, the
-// fastest kept.  A first pass over the configurations captures their loop graphs;
-// the second is timed.  The policy and the root marks are restored at the end.
+// fastest kept.  Each configuration runs twice in a row: the first run loads its
+// kernels and launches them directly, the second repeats its arguments, so it runs
+// from captured graphs as repeated Replans do, and is the one timed.  The policy and
+// the root marks are restored at the end.
 constexpr int kTuneConfigs = kRowVariants * 2;
 
 int tune(pirrt_graph* G, int32_t P, const int32_t* rid, const int32_t* rs, const int32_t* gs, const float* hdev,
@@ -1103,10 +1105,10 @@ int tune(pirrt_graph* G, int32_t P, const int32_t* rid, const int32_t* rs, const
   };
   double best = 1e300;
   int bestc = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int c = 0; c < kTuneConfigs; ++c) {
-      G->row_variant = c % kRowVariants;
-      G->walk_coherent = c / kRowVariants == 0;
+  for (int c = 0; c < kTuneConfigs; ++c) {
+    G->row_variant = c % kRowVariants;
+    G->walk_coherent = c / kRowVariants == 0;
+    for (int pass = 0; pass < 2; ++pass) {  // the second run repeats the first: graphs
       if ((rc = restore())) return rc;
       const auto t0 = std::chrono::steady_clock::now();
       rc = run_replan(G, P, rid, rs, gs, hdev, prune, false, nullptr);
