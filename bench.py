@@ -1061,6 +1061,15 @@ def main():
         t_np = (time.perf_counter() - t0) / reps
         noprune = {"replan_ms": round(1e3 * t_np, 3), "iterations": s3["iterations"],
                    "edges_examined": s3["edges_examined"], "gteps": round(s3["edges_examined"] / t_np / 1e9, 2)}
+        # Improve alone with every reachable vertex in the domain: long runs of whole rows
+        G.snapshot_restore()
+        t3 = G.replan(0, 1, h, False, timing=True, g_out=g_out, parent_out=p_out)[2]
+        nb3 = improve_bytes(t3["edges_examined"], t3["sum_D"], n, t3["improve_launches"])
+        a3 = nb3 / (t3["ms_improve"] * 1e-3) / 1e9
+        noprune["improve"] = {"achieved": round(a3, 1), "frac": round(a3 / HBM_PEAK_GBS, 4), "unit": "GB/s",
+                              "launches": t3["improve_launches"],
+                              "avg_launch_us": round(1e3 * t3["ms_improve"] / max(1, t3["improve_launches"]), 2),
+                              "bytes_per_launch": int(nb3 / max(1, t3["improve_launches"]))}
         log("pruning off: %s" % json.dumps(noprune))
 
     # Evaluate (walk): every vertex once per call, 28 B each (parent 4, parent-edge cost 4,
