@@ -154,13 +154,15 @@ class Graph:
         return ptr, nbr[: self.nnz], cst[: self.nnz]
 
     def replan(self, root: int, goal: int, h=None, prune: bool = True, max_iters: int = 0,
-               lookahead: bool = False):
+               lookahead: bool = False, truncated: bool = False):
         """Returns (rc, stats dict).  The policy is updated in place.  lookahead selects
-        the narrowed Improve domain (see orc_replan_mode)."""
+        the narrowed Improve domain, truncated the truncated Evaluate (see
+        orc_replan_mode); both together are rejected."""
         st = Stats()
         hh = None if h is None else np.ascontiguousarray(h, np.float32)
+        mode = (1 if lookahead else 0) | (2 if truncated else 0)
         rc = self._lib.orc_replan_mode(self._h, int(root), int(goal), _ptr(hh), int(bool(prune)),
-                                       int(bool(lookahead)), int(max_iters), ctypes.byref(st))
+                                       mode, int(max_iters), ctypes.byref(st))
         return int(rc), st.as_dict()
 
     def evaluate(self, root: int) -> int:

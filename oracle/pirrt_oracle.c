@@ -34,6 +34,9 @@
  *     is strictly below g(v), as the strict comparison of Alg. 2 does.
  *   - The convergence test dJ < eps is taken with eps at its limit: stop when no
  *     parent changed (then dJ = 0); an iteration cap guards termination.
+ *   - A separate mode keeps Evaluate truncated as Alg. 2 prints it (children of
+ *     vertices that fail the promising test are not visited and keep their old g),
+ *     with the threshold read once before each walk.
  */
 #include <math.h>
 #include <stdint.h>
@@ -254,6 +257,46 @@ static int64_t evaluate(orc_graph* G, int32_t root, int32_t* child_ptr, int32_t*
 }
 
 /*
+ * Truncated Evaluate: Alg. 2's Evaluate as printed, with two readings.  A child is
+ * tested on its own fresh value (not its parent's), and the threshold G0 is the
+ * g(x_goal) held when the walk starts (the printed test reads g(x_goal) while the walk
+ * may still be changing it).  Breadth-first from the root with a FIFO queue: every
+ * child n of a popped vertex v gets g(n) = g(v) + c(v, n); n joins the queue and B
+ * only when g(n) + h(n) < G0.  The root is never in B.  Vertices the walk does not
+ * reach keep the g they held before it.  Fills inB and returns |B|.
+ */
+static int64_t evaluate_truncated(orc_graph* G, int32_t root, const float* h, float G0, int32_t* child_ptr,
+                                  int32_t* child, int32_t* queue, int32_t* cursor, unsigned char* inB) {
+  int64_t n = G->n;
+  for (int64_t v = 0; v <= n; ++v) child_ptr[v] = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (v != root && G->parent[v] >= 0) child_ptr[G->parent[v] + 1]++;
+  for (int64_t v = 0; v < n; ++v) child_ptr[v + 1] += child_ptr[v];
+  for (int64_t v = 0; v < n; ++v) cursor[v] = child_ptr[v];
+  for (int64_t v = 0; v < n; ++v)
+    if (v != root && G->parent[v] >= 0) child[cursor[G->parent[v]]++] = (int32_t)v;
+
+  for (int64_t v = 0; v < n; ++v) inB[v] = 0;
+  int64_t nb = 0, head = 0, tail = 0;
+  G->g[root] = 0.0f;
+  queue[tail++] = root;
+  while (head < tail) {
+    int32_t v = queue[head++];
+    for (int32_t k = child_ptr[v]; k < child_ptr[v + 1]; ++k) {
+      int32_t c = child[k];
+      G->g[c] = G->g[v] + G->pcost[c];
+      float f = G->g[c] + (h ? h[c] : 0.0f);
+      if (f < G0) {
+        queue[tail++] = c;
+        inB[c] = 1;
+        ++nb;
+      }
+    }
+  }
+  return nb;
+}
+
+/*
  * Replan (Alg. 2) from the stored policy: Evaluate, then repeat
  *   promising set  P = { v : g(v) + h(v) < G }          (G = g(goal) or +inf)
  *   Improve domain D = (P and every neighbour of P) minus the root
@@ -267,8 +310,24 @@ static int64_t evaluate(orc_graph* G, int32_t root, int32_t* child_ptr, int32_t*
  * one binary32 addition.  Promising vertices stay in D.  Improve over D is unchanged
  * (every neighbour is a candidate).  With pruning off (G = +inf) the filter keeps
  * every neighbour of a finite-g vertex, so the two modes coincide.
+ *
+ * mode: bit 0 (ORC_MODE_LOOKAHEAD) is the narrowed domain above; bit 1
+ * (ORC_MODE_TRUNCATED) replaces every Evaluate, the first one included, by the
+ * truncated Evaluate, and the promising set of each iteration by the B that walk
+ * returned (G0 = g(goal) just before the walk, or +inf without pruning).  The two
+ * bits together are rejected (EINVAL).  Truncation leaves stale g on the vertices the
+ * walk skips; Improve then compares against them, so the loop may stop on a policy
+ * that the full mode would still improve.  A stale vertex can also find its own
+ * parent below its stale g (dJ > 0) in every iteration, since no walk refreshes it;
+ * so in this mode an iteration counts as a change only when some parent or
+ * parent-edge cost actually changes, and the loop stops at the first Improve that
+ * leaves the policy as it was -- then Evaluate and Improve would repeat themselves
+ * exactly.  (In the full mode the two tests agree: a fresh g equals the offer of its
+ * own parent, so a strict decrease always moves the parent or the cost.)
  */
-int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int lookahead,
+#define ORC_MODE_LOOKAHEAD 1
+#define ORC_MODE_TRUNCATED 2
+int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int mode,
                     int32_t max_iters, orc_stats* st);
 
 int orc_replan(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int32_t max_iters,
@@ -276,12 +335,15 @@ int orc_replan(orc_graph* G, int32_t root, int32_t goal, const float* h, int pru
   return orc_replan_mode(G, root, goal, h, prune, 0, max_iters, st);
 }
 
-int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int lookahead,
+int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, int prune, int mode,
                     int32_t max_iters, orc_stats* st) {
   int64_t n = G->n;
   orc_stats local;
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
+  const int lookahead = (mode & ORC_MODE_LOOKAHEAD) != 0, truncated = (mode & ORC_MODE_TRUNCATED) != 0;
+  if (mode & ~(ORC_MODE_LOOKAHEAD | ORC_MODE_TRUNCATED)) return ORC_EINVAL;
+  if (lookahead && truncated) return ORC_EINVAL;
   if (root < 0 || root >= n || goal < 0 || goal >= n) return ORC_EINVAL;
   if (h) {
     for (int64_t v = 0; v < n; ++v)
@@ -303,16 +365,25 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
   }
   G->parent[root] = -1;
   G->pcost[root] = 0.0f;
-  evaluate(G, root, child_ptr, child, queue, depth);
+  int64_t nb = 0; /* |B| of the last truncated Evaluate (inP holds B) */
+  if (truncated)
+    nb = evaluate_truncated(G, root, h, prune ? G->g[goal] : INFINITY, child_ptr, child, queue, depth, inP);
+  else
+    evaluate(G, root, child_ptr, child, queue, depth);
   for (;;) {
     float thr = prune ? G->g[goal] : INFINITY;
     int64_t np = 0, nd = 0, ex = 0, nchg = 0;
-    for (int64_t v = 0; v < n; ++v) {
-      float hv = h ? h[v] : 0.0f;
-      float f = G->g[v] + hv;
-      inP[v] = f < thr;
-      np += inP[v];
-      inD[v] = 0;
+    if (truncated) {
+      np = nb;
+      for (int64_t v = 0; v < n; ++v) inD[v] = 0;
+    } else {
+      for (int64_t v = 0; v < n; ++v) {
+        float hv = h ? h[v] : 0.0f;
+        float f = G->g[v] + hv;
+        inP[v] = f < thr;
+        np += inP[v];
+        inD[v] = 0;
+      }
     }
     for (int64_t v = 0; v < n; ++v) {
       if (!inP[v]) continue;
@@ -346,7 +417,9 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
           best_c = G->cst[v][j];
         }
       }
-      if (best_u >= 0 && best < G->g[v]) {
+      /* Truncated mode: a vertex the last walk skipped may offer its own parent below
+         its stale g; that keeps the policy as it is and is not a switch. */
+      if (best_u >= 0 && best < G->g[v] && (!truncated || best_u != G->parent[v] || best_c != G->pcost[v])) {
         newpar[v] = best_u;
         newpc[v] = best_c;
         ++nchg;
@@ -360,7 +433,10 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
     if (nchg == 0) break;
     memcpy(G->parent, newpar, sizeof(int32_t) * (size_t)n);
     memcpy(G->pcost, newpc, sizeof(float) * (size_t)n);
-    evaluate(G, root, child_ptr, child, queue, depth);
+    if (truncated)
+      nb = evaluate_truncated(G, root, h, prune ? G->g[goal] : INFINITY, child_ptr, child, queue, depth, inP);
+    else
+      evaluate(G, root, child_ptr, child, queue, depth);
     if (st->iterations >= cap) {
       rc = ORC_ENOTCONVERGED;
       break;

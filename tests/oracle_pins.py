@@ -528,6 +528,88 @@ def pin_lookahead_properties(lib):
         assert np.array_equal(fold.view(np.uint32), g.view(np.uint32))
 
 
+def truncated_example():
+    """A six-vertex graph worked by hand for the truncated Evaluate.
+
+    Edges 0-1 (4), 0-2 (3), 0-5 (1), 5-2 (1), 2-3 (3), 3-4 (1); root 0, goal 1,
+    h = 0, pruning on; starting policy 1<-0, 2<-0, 3<-2, 4<-3, 5<-0 with its
+    consistent g = (0, 4, 3, 6, 7, 1).
+    First Evaluate: G0 = g(1) = 4.  From the root: g(1) = 4 (not < 4, not queued),
+    g(2) = 3 and g(5) = 1 (queued, B = {2, 5}); from 2: g(3) = 6 (not queued); 4 is
+    not reached and keeps 7.
+    Iteration 1: P = {2, 5}; D = {2, 5} and their neighbours minus the root =
+    {2, 3, 5} (degrees 3 + 2 + 2 = 7 entries).  Improve: 2 has 0+3, 1+1 = 2, 6+3 -> it
+    moves under 5 (2 < 3); 3 has 3+3 = 6 and 7+1 = 8 (6 is not below 6); 5 keeps 0.
+    Evaluate: G0 = 4; g(1) = 4 (not queued), g(5) = 1 (queued), then g(2) = 2
+    (queued), then g(3) = 2 + 3 = 5 (not queued); 4 is not reached: g(4) stays 7
+    although its path now costs 6.
+    Iteration 2: P = {2, 5}, D = {2, 3, 5} again; nothing switches (2 has 2, 3 has
+    5 and 7 + 1, 5 has 1).  Totals (iterations, sum_P, sum_D, edges, changed) =
+    (2, 4, 6, 14, 1); final g = (0, 4, 2, 5, 7, 1), parents (-1, 0, 5, 2, 3, 0).
+    The full mode from the same policy puts the root in P (D = {1, 2, 3, 5}), ends
+    with g(4) = 6 and counts (2, 6, 8, 16, 1)."""
+    edges = [(0, 1, 4.0), (0, 2, 3.0), (0, 5, 1.0), (5, 2, 1.0), (2, 3, 3.0), (3, 4, 1.0)]
+    parent = np.array([-1, 0, 0, 2, 3, 0], np.int32)
+    pcost = np.array([0.0, 4.0, 3.0, 3.0, 1.0, 1.0], np.float32)
+    g = np.array([0.0, 4.0, 3.0, 6.0, 7.0, 1.0], np.float32)
+    return edges, g, parent, pcost
+
+
+def pin_truncated_worked_example(lib):
+    edges, g0, parent, pcost = truncated_example()
+    want = {True: ((2, 4, 6, 14, 1), [0, 4, 2, 5, 7, 1]), False: ((2, 6, 8, 16, 1), [0, 4, 2, 5, 6, 1])}
+    for trunc in (True, False):
+        G = build_graph(lib, [W.from_edges(6, edges)])
+        assert G.set_state(g0, parent, pcost) == 0
+        rc, st = G.replan(0, 1, np.zeros(6, np.float32), True, truncated=trunc)
+        assert rc == 0
+        got = (st["iterations"], st["sum_P"], st["sum_D"], st["edges_examined"], st["changed_total"])
+        assert got == want[trunc][0], (trunc, got)
+        fin = G.state()
+        assert np.array_equal(fin.g, np.array(want[trunc][1], np.float32)), (trunc, fin.g)
+        assert np.array_equal(fin.parent, np.array([-1, 0, 5, 2, 3, 0], np.int32))
+    G = build_graph(lib, [W.from_edges(6, edges)])
+    assert G.replan(0, 1, None, True, truncated=True, lookahead=True)[0] == O.EINVAL
+
+
+def pin_truncated_properties(lib):
+    """Truncated Evaluate: without pruning (G0 = +inf) every vertex the root reaches
+    is visited and queued, so from the insertion-time state -- where every neighbour
+    of vertex 0 is attached to the tree and every unattached vertex holds +inf -- B is
+    the full mode's P minus the root, N(root) lies in B, and the two modes give the
+    same counters and bits.  With pruning, the first iteration's B lies inside the full
+    mode's P minus the root (the visited vertices get the same values from a
+    consistent start, and each of them passed the same test), so its domain is no
+    larger; g(goal) is still the cost of a path, so never below the FP64 shortest
+    distance."""
+    for wl in (W.plain_2d(samples=800, seed=0), W.batched_6d(batches=3, batch=400, seed=100)):
+        G = build_graph(lib, wl.batches)
+        H = build_graph(lib, wl.batches)
+        h = wl.heuristic(G.n)
+        rc1, s1 = G.replan(0, 1, h, False, truncated=True)
+        rc2, s2 = H.replan(0, 1, h, False)
+        assert rc1 == rc2 == 0
+        s2 = dict(s2, sum_P=s2["sum_P"] - s2["iterations"])  # the root is in every full-mode P
+        assert s1 == s2, (wl.name, s1, s2)
+        a, b = G.state(), H.state()
+        assert np.array_equal(a.g.view(np.uint32), b.g.view(np.uint32)) and np.array_equal(a.parent, b.parent)
+        G = build_graph(lib, wl.batches)
+        H = build_graph(lib, wl.batches)
+        _, f1 = G.replan(0, 1, h, True, max_iters=1, truncated=True)
+        _, f2 = H.replan(0, 1, h, True, max_iters=1)
+        assert f1["sum_P"] < f2["sum_P"] and f1["sum_D"] <= f2["sum_D"], (f1, f2)  # the root is in P
+        assert f1["edges_examined"] <= f2["edges_examined"]
+        G = build_graph(lib, wl.batches)
+        rc, st = G.replan(0, 1, h, True, truncated=True)
+        assert rc == 0
+        d = fp64_dist(G, 0)
+        g1 = float(G.state().g[1])
+        assert np.isfinite(d[1]) == np.isfinite(g1)
+        if np.isfinite(g1):
+            assert g1 >= d[1] * (1 - 1e-4), (wl.name, g1, d[1])
+
+
 PINS = [pin_golden, pin_path_fold, pin_errors, pin_lattice, pin_complete_graph, pin_insertion_local,
         pin_monotone, pin_invariants, pin_dijkstra, pin_pruned_exactness, pin_any_initial_policy,
-        pin_bruteforce_small, pin_lookahead_worked_example, pin_lookahead_properties]
+        pin_bruteforce_small, pin_lookahead_worked_example, pin_lookahead_properties,
+        pin_truncated_worked_example, pin_truncated_properties]

@@ -16,7 +16,7 @@ from oracle_pins import PINS
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "pirrt_oracle.c")
 
 MUTANTS = {
-    "improve_non_strict": ("if (best_u >= 0 && best < G->g[v]) {", "if (best_u >= 0 && best <= G->g[v]) {"),
+    "improve_non_strict": ("if (best_u >= 0 && best < G->g[v] && (", "if (best_u >= 0 && best <= G->g[v] && ("),
     "improve_tie_highest": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))",
                             "(u > best_u || (u == best_u && G->cst[v][j] < best_c))"),
     "improve_cost_tie_ignored": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))", "(u < best_u)"),
@@ -30,7 +30,7 @@ MUTANTS = {
                            "(u > best_u || (u == best_u && cost[j] < best_c))"),
     "insert_cost_tie_ignored": ("(u < best_u || (u == best_u && cost[j] < best_c))", "(u < best_u)"),
     "insert_orphan_zero": ("    G->g[v] = best;\n", "    G->g[v] = best_u >= 0 ? best : 0.0f;\n"),
-    "evaluate_wrong_index": ("G->g[c] = G->g[v] + G->pcost[c];", "G->g[c] = G->g[v] + G->pcost[v];"),
+    "evaluate_wrong_index": ("G->g[c] = G->g[v] + G->pcost[c];\n      depth[c]", "G->g[c] = G->g[v] + G->pcost[v];\n      depth[c]"),
     "evaluate_no_reset": ("for (int64_t v = 0; v < n; ++v) G->g[v] = INFINITY;", ""),
     "domain_without_neighbours": ("        inD[w] = 1;\n", ""),
     "lookahead_drops_heuristic": ("float f = offer + (h ? h[w] : 0.0f);", "float f = offer;"),
@@ -42,6 +42,15 @@ MUTANTS = {
     "heuristic_dropped": ("float hv = h ? h[v] : 0.0f;", "float hv = 0.0f;"),
     "single_iteration": ("if (nchg == 0) break;", "break;"),
     "edges_stat_per_vertex": ("ex += G->deg[v];", "ex += 1;"),
+    "trunc_wrong_index": ("G->g[c] = G->g[v] + G->pcost[c];\n      float f", "G->g[c] = G->g[v] + G->pcost[v];\n      float f"),
+    "trunc_counts_own_parent": ("best < G->g[v] && (!truncated || best_u != G->parent[v] || best_c != G->pcost[v])",
+                                "best < G->g[v]"),
+    "trunc_tests_parent": ("float f = G->g[c] + (h ? h[c] : 0.0f);", "float f = G->g[v] + (h ? h[v] : 0.0f);"),
+    "trunc_non_strict": ("      if (f < G0) {", "      if (f <= G0) {"),
+    "trunc_resets_unvisited": ("  G->g[root] = 0.0f;\n  queue[tail++] = root;",
+                               "  for (int64_t v = 0; v < n; ++v) G->g[v] = INFINITY;\n  G->g[root] = 0.0f;\n  queue[tail++] = root;"),
+    "trunc_root_in_b": ("  return nb;\n}", "  inB[root] = 1;\n  return nb + 1;\n}"),
+    "trunc_full_promising_test": ("    if (truncated) {\n      np = nb;", "    if (0) {\n      np = nb;"),
     "mirror_wrong_endpoint": ("push_adj(G, col[j], (int32_t)v, cost[j])", "push_adj(G, col[j], col[j], cost[j])"),
 }
 
