@@ -60,7 +60,7 @@ enum {
                                vertex is promising */
   PIRRT_TIMING = 1u << 1,   /* time each phase with HIP events (fills the ms_* and
                                per-kernel fields of pirrt_stats; adds event overhead) */
-  PIRRT_LOOKAHEAD = 1u << 2 /* narrowed Improve domain, a work-reduction variant of Sec.
+  PIRRT_LOOKAHEAD = 1u << 2, /* narrowed Improve domain, a work-reduction variant of Sec.
                                IV-C's domain (promising vertices plus their neighbours):
                                a neighbour w of a promising u joins the domain only
                                if fl(fl(g(u) + c(u,w)) + h(w)) < G, i.e. if the candidate u
@@ -69,6 +69,21 @@ enum {
                                the default's in general; g(goal) keeps the default's
                                optimality argument under a consistent h.  Without
                                pruning both rules coincide. */
+  PIRRT_TRUNCATED = 1u << 3 /* truncated Evaluate, Alg. 2's Evaluate as printed (single
+                               graphs only; not with PIRRT_LOOKAHEAD, EINVAL otherwise).
+                               Every Evaluate of the call walks the policy tree
+                               breadth-first from the root with G0 = g(goal) as held
+                               when the walk starts (+inf with PIRRT_NO_PRUNE): a child
+                               of a queued vertex gets its fresh g and is queued only
+                               when fl(g + h) < G0; the root is never queued.  Vertices
+                               the walk does not reach keep their previous g (they are
+                               not reset to +inf).  P of the next iteration is the set
+                               the walk queued; D, Improve and the cap as above, except
+                               that a minimum equal to a vertex's own parent and cost
+                               is not a switch (a skipped vertex's stale g could
+                               otherwise keep the loop going forever).  The result may
+                               stop above the full mode's fixed point, and g holds
+                               stale values on skipped vertices. */
 };
 
 typedef struct pirrt_graph pirrt_graph;

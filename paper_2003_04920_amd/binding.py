@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libpirrt.so")
 
 PIRRT_OK, PIRRT_EINVAL, PIRRT_ENOMEM, PIRRT_EDEVICE, PIRRT_ENOTCONVERGED = 0, -1, -2, -3, -4
 PIRRT_MEM_HOST, PIRRT_MEM_DEVICE = 0, 1
-PIRRT_NO_PRUNE, PIRRT_TIMING, PIRRT_LOOKAHEAD = 1, 2, 4
+PIRRT_NO_PRUNE, PIRRT_TIMING, PIRRT_LOOKAHEAD, PIRRT_TRUNCATED = 1, 2, 4, 8
 
 EXPORTS = [
     "pirrt_config_init", "pirrt_graph_create", "pirrt_graph_destroy", "pirrt_insert_batch", "pirrt_replan",
@@ -246,10 +246,12 @@ class Graph:
         return self.insert_batch(batch.row_ptr, batch.col, batch.cost)
 
     def replan(self, root: int, goal: int, h=None, prune: bool = True, timing: bool = False,
-               g_out=None, parent_out=None, allow_not_converged: bool = False, lookahead: bool = False):
+               g_out=None, parent_out=None, allow_not_converged: bool = False, lookahead: bool = False,
+               truncated: bool = False):
         """Runs Replan.  Outputs are numpy arrays unless device buffers are given
         (torch tensors on the GPU) or h is a device tensor.  lookahead selects the
-        narrowed Improve domain (PIRRT_LOOKAHEAD)."""
+        narrowed Improve domain (PIRRT_LOOKAHEAD), truncated the truncated Evaluate
+        (PIRRT_TRUNCATED)."""
         h = _check_dtype(h, np.float32, "float32")
         n = self.n
         if g_out is None and parent_out is None and _is_device(h):
@@ -260,7 +262,8 @@ class Graph:
             g_out = np.empty(n, np.float32)
             parent_out = np.empty(n, np.int32)
         kind = _mem_kind(h, g_out, parent_out)
-        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0) | (PIRRT_LOOKAHEAD if lookahead else 0)
+        flags = ((0 if prune else PIRRT_NO_PRUNE) | (PIRRT_TIMING if timing else 0) |
+                 (PIRRT_LOOKAHEAD if lookahead else 0) | (PIRRT_TRUNCATED if truncated else 0))
         st = pirrt_stats()
         rc = self._lib.pirrt_replan(self._h, int(root), int(goal), _ptr(h), flags, _ptr(g_out), _ptr(parent_out),
                                     kind, ctypes.byref(st))
@@ -269,11 +272,13 @@ class Graph:
         d["rc"] = rc
         return g_out, parent_out, d
 
-    def tune(self, root: int, goal: int, h=None, prune: bool = True, lookahead: bool = False) -> int:
+    def tune(self, root: int, goal: int, h=None, prune: bool = True, lookahead: bool = False,
+             truncated: bool = False) -> int:
         """Autotunes the kernel configuration on this Replan; returns its index."""
         h = _check_dtype(h, np.float32, "float32")
         cfg = ctypes.c_int32(-1)
-        flags = (0 if prune else PIRRT_NO_PRUNE) | (PIRRT_LOOKAHEAD if lookahead else 0)
+        flags = ((0 if prune else PIRRT_NO_PRUNE) | (PIRRT_LOOKAHEAD if lookahead else 0) |
+                 (PIRRT_TRUNCATED if truncated else 0))
         self._check(self._lib.pirrt_tune(self._h, int(root), int(goal), _ptr(h), flags, _mem_kind(h),
                                          ctypes.byref(cfg)))
         return int(cfg.value)

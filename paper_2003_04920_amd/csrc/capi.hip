@@ -62,7 +62,7 @@ thread_local std::string g_create_error;
 struct LoopKey {
   const void* ptrs[16];
   int64_t n, nnz;
-  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead;
+  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead, truncated;
   bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
 };
 
@@ -170,6 +170,7 @@ struct pirrt_graph {
   int32_t mid_hint = 64;
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
+  bool truncated = false;  // truncated Evaluate for the current call (PIRRT_TRUNCATED)
   LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
   bool have_prev_key = false;
   bool small_graphs = true;  // single-workgroup Replan up to kSmallMax vertices (PIRRT_SMALL=0: off)
@@ -752,7 +753,7 @@ struct LoopArgs {
 // Enqueues Evaluate for every problem that needs it (walk, or level-synchronous
 // for a single problem).
 void enqueue_evaluate(pirrt_graph* G, LoopArgs& L, hipStream_t s) {
-  if (G->eval_levels)
+  if (G->eval_levels && !L.wa.truncated)  // the truncated Evaluate is a walk
     launch_evaluate(L.ea, s);
   else
     launch_eval_walk(L.wa, s);
@@ -792,6 +793,7 @@ LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   k.iters = iters;
   k.mid = L.ea.mid_launches;
   k.lookahead = L.sa.lookahead;
+  k.truncated = L.sa.truncated;
   return k;
 }
 
@@ -850,7 +852,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, root_ids, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
   G->nroots = P;
   G->hroots.assign(root_ids, root_ids + P);
-  launch_replan_init(P, G->ps, G->parent, G->pcost, G->ctr, G->ctl, s);
+  launch_replan_init(P, G->ps, G->parent, G->pcost, G->ctr, G->ctl, G->g, prune ? 1 : 0, s);
   HIP_OR_FAIL(G, hipGetLastError());
 
   LoopArgs L;
@@ -876,6 +878,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.plist = G->fr1;  // free during a Replan (the level evaluator's frontiers run only between marks)
   sa.tiles = G->tiles;
   sa.lookahead = G->lookahead;
+  sa.truncated = G->truncated;
+  sa.word = G->word;
   WalkArgs& wa = L.wa;
   wa.n = n;
   wa.prob = problem_map(G);
@@ -889,6 +893,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.parts = G->walk_parts;
   wa.coherent = G->walk_coherent;
   wa.tiles = G->tiles;
+  wa.truncated = G->truncated;
+  wa.h = h;
   EvalArgs& ea = L.ea;
   ea.n = n;
   ea.root = root_slots[0];
@@ -908,7 +914,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   int64_t lb = (int64_t)n / 2048;
   ea.level_blocks = (int32_t)(lb < 16 ? 16 : (lb > 1024 ? 1024 : lb));
   if (G->eval_levels && P != 1) return fail(G, PIRRT_EINVAL, "the level-synchronous Evaluate takes one problem");
-  if (P == 1 && !G->batched && n <= kSmallMax && G->small_graphs && !timing && !G->trace && !G->eval_levels) {
+  if (P == 1 && !G->batched && n <= kSmallMax && G->small_graphs && !timing && !G->trace && !G->eval_levels &&
+      !G->truncated) {
     // one workgroup runs the whole loop
     launch_replan_small(n, G->rp, G->col, G->cst, h, G->ext_of, prune, G->lookahead, G->ps, G->parent, G->pcost,
                         G->g, s);
@@ -1300,6 +1307,8 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   if (rc) return rc;
   if (G->batched) return fail(G, PIRRT_EINVAL, "this handle holds a batch of problems");
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if ((flags & PIRRT_TRUNCATED) && (flags & PIRRT_LOOKAHEAD))
+    return fail(G, PIRRT_EINVAL, "PIRRT_TRUNCATED and PIRRT_LOOKAHEAD cannot be combined");
   if (G->n <= 0) return fail(G, PIRRT_EINVAL, "empty graph");
   if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
   const float* hdev = nullptr;
@@ -1307,6 +1316,7 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   pirrt_stats st;
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
+  G->truncated = (flags & PIRRT_TRUNCATED) != 0;
   rc = run_replan(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, (flags & PIRRT_TIMING) != 0,
                   &st);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
@@ -1325,12 +1335,15 @@ int pirrt_tune(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uint3
   if (rc) return rc;
   if (G->batched) return fail(G, PIRRT_EINVAL, "this handle holds a batch of problems");
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if ((flags & PIRRT_TRUNCATED) && (flags & PIRRT_LOOKAHEAD))
+    return fail(G, PIRRT_EINVAL, "PIRRT_TRUNCATED and PIRRT_LOOKAHEAD cannot be combined");
   if (G->n <= 0) return fail(G, PIRRT_EINVAL, "empty graph");
   if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
+  G->truncated = (flags & PIRRT_TRUNCATED) != 0;
   return tune(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 
@@ -1543,6 +1556,7 @@ int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goal
   const int32_t P = (int32_t)G->pbase.size() - 1;
   if (P <= 0) return fail(G, PIRRT_EINVAL, "empty batch");
   if (!roots || !goals) return fail(G, PIRRT_EINVAL, "roots or goals is NULL");
+  if (flags & PIRRT_TRUNCATED) return fail(G, PIRRT_EINVAL, "the truncated Evaluate takes a single graph");
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
   for (int32_t i = 0; i < P; ++i) {
     const int64_t b = G->pbase[(size_t)i], len = G->pbase[(size_t)i + 1] - b;
@@ -1561,6 +1575,7 @@ int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goal
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
+  G->truncated = false;
   rc = run_replan(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0,
                   (flags & PIRRT_TIMING) != 0, stats);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
@@ -1581,6 +1596,7 @@ int pirrt_batch_tune(pirrt_batch* B, const int32_t* roots, const int32_t* goals,
   const int32_t P = (int32_t)G->pbase.size() - 1;
   if (P <= 0) return fail(G, PIRRT_EINVAL, "empty batch");
   if (!roots || !goals) return fail(G, PIRRT_EINVAL, "roots or goals is NULL");
+  if (flags & PIRRT_TRUNCATED) return fail(G, PIRRT_EINVAL, "the truncated Evaluate takes a single graph");
   if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
   for (int32_t i = 0; i < P; ++i) {
     const int64_t b = G->pbase[(size_t)i], len = G->pbase[(size_t)i + 1] - b;
@@ -1599,6 +1615,7 @@ int pirrt_batch_tune(pirrt_batch* B, const int32_t* roots, const int32_t* goals,
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
+  G->truncated = false;
   return tune(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0, config);
 }
 

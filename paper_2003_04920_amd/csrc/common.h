@@ -49,6 +49,11 @@ struct LoopCtl {
   int32_t pad;
 };
 
+// Truncated Evaluate: the low word of a vertex's walk stamp carries this bit when the
+// walk does not visit its children (the vertex was not reached, or failed the
+// promising test); g bits are >= 0, so their sign bit is free.
+constexpr uint32_t kWalkNoChildren = 0x80000000u;
+
 // Batches run their per-slot kernels over tiles of kTileSlots consecutive slots;
 // after each Evaluate the tiles that overlap a problem still iterating are listed
 // (LoopCtl::ntiles, -1 = all tiles in slot order).

@@ -16,9 +16,12 @@ __device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ?
 // (the cleared stamp).
 __device__ __forceinline__ uint32_t next_mark_epoch(uint32_t e) { return ((e + 1) & 0xffu) == 0 ? e + 2 : e + 1; }
 
-// Marks the roots, clears the counters and takes fresh epochs.
-__global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, int32_t* __restrict__ parent,
-                              float* __restrict__ pcost, IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl) {
+// Marks the roots, clears the counters and takes fresh epochs.  The threshold is set
+// to g(goal) as stored before any Evaluate of this Replan (the truncated Evaluate's
+// first walk reads it; the full one ignores it).
+__global__ void k_replan_init(int32_t P, ProblemState* __restrict__ ps, int32_t* __restrict__ parent,
+                              float* __restrict__ pcost, IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl,
+                              const float* __restrict__ g, int prune) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < (int64_t)P * kCounterSlots) {
     IterCounters& c = ctr[t];
@@ -31,6 +34,7 @@ __global__ void k_replan_init(int32_t P, const ProblemState* __restrict__ ps, in
     const int32_t r = ps[t].root;
     parent[r] = kRootMark;
     pcost[r] = 0.0f;
+    ps[t].thr = prune ? g[ps[t].goal] : pos_inf();
   }
   if (t == 0) {
     ctl->epoch = next_mark_epoch(ctl->epoch);
@@ -129,11 +133,11 @@ __global__ void k_after_eval(int32_t P, ProblemState* __restrict__ ps, const flo
 
 }  // namespace
 
-void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
-                        LoopCtl* ctl, hipStream_t s) {
+void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
+                        LoopCtl* ctl, const float* g, int prune, hipStream_t s) {
   const int64_t t = (int64_t)P * kCounterSlots;
   hipLaunchKernelGGL(k_replan_init, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, P, ps, parent, pcost, ctr,
-                     ctl);
+                     ctl, g, prune);
 }
 
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s) {

@@ -202,6 +202,15 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
 // its top kRing vertices, stamps them and walks again from v (which now stops
 // there).  A walk longer than n hops can only be a parent cycle away from the
 // root; its vertices are unreachable and get +inf.
+//
+// kTrunc (single graphs): the truncated Evaluate.  A vertex is visited only when its
+// parent is the root or a visited vertex with fl(g + h) < G0, G0 being the problem's
+// threshold when the launch starts (g(goal) before this Evaluate).  The fold carries
+// that rule down the path: a visited vertex gets its fresh g, and its stamp says
+// whether its children are visited (kWalkNoChildren clear) or not; vertices below
+// one whose children are not visited -- and detached or cyclic chains -- are stamped
+// kWalkNoChildren and keep the g they had.  The stamps of this walk are what the
+// next promising list reads.
 constexpr int kWalkThreads = 256;
 constexpr int kRing = 16;
 
@@ -222,7 +231,7 @@ __device__ __forceinline__ void store_word(unsigned long long* p, unsigned long 
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool kCountHops, bool kCoherent, bool kBatched>
+template <bool kCountHops, bool kCoherent, bool kBatched, bool kTrunc>
 __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t hi, int32_t n,
                                                            const int32_t* __restrict__ prob,
                                                            const ProblemState* __restrict__ ps,
@@ -231,11 +240,14 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
                                                            const float* __restrict__ pcost, float* __restrict__ g,
                                                            unsigned long long* __restrict__ word,
                                                            unsigned long long* __restrict__ hops,
-                                                           const int32_t* __restrict__ tiles) {
+                                                           const int32_t* __restrict__ tiles,
+                                                           const float* __restrict__ h) {
+  static_assert(!(kTrunc && kBatched), "the truncated Evaluate takes a single graph");
   __shared__ int32_t ring_v[kRing][kWalkThreads];
   __shared__ float ring_c[kRing][kWalkThreads];
   if (ctl->any_eval == 0) return;  // no problem changed in this iteration
   const unsigned long long tag = (unsigned long long)ctl->eval_epoch << 32;
+  const float G0 = kTrunc ? ps[0].thr : 0.0f;
   unsigned long long walked = 0;
   // a batch loops over the units of its active tiles; a single graph has one unit
   const int64_t units = kBatched ? tile_units(ctl, n, kWalkThreads) : 1;
@@ -267,13 +279,28 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
       ring_c[k % kRing][threadIdx.x] = c;
       ++k;
       if (p < 0 || k > n) {  // detached chain (or a cycle): unreachable
-        top = 0x7f800000u;
+        top = kTrunc ? kWalkNoChildren : 0x7f800000u;
         break;
       }
       u = p;
     }
     walked += (unsigned long long)k;
     const int64_t stop = k > kRing ? k - kRing : 0;
+    if (kTrunc) {
+      // top: stamp bits of the vertex above the path (kWalkNoChildren or its g)
+      uint32_t st = top;
+      for (int64_t i = k - 1; i >= stop; --i) {
+        const int32_t x = ring_v[i % kRing][threadIdx.x];
+        if (!(st & kWalkNoChildren)) {  // x is visited: fresh g, then its own test
+          const float acc = add_rn(__uint_as_float(st), ring_c[i % kRing][threadIdx.x]);
+          g[x] = acc;
+          st = __float_as_uint(acc) | (add_rn(acc, h ? h[x] : 0.0f) < G0 ? 0u : kWalkNoChildren);
+        }
+        store_word<kCoherent>(&word[x], tag | st);
+      }
+      if (stop == 0) break;
+      continue;
+    }
     float acc = __uint_as_float(top);
     for (int64_t i = k - 1; i >= stop; --i) {
       const int32_t x = ring_v[i % kRing][threadIdx.x];
@@ -301,9 +328,20 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
     const dim3 grid(a.prob ? (unsigned)(units < kBatchBlocks ? (units > 0 ? units : 1) : kBatchBlocks)
                            : blocks_for(hi - lo, kWalkThreads));
 #define PIRRT_WALK(H, C, B)                                                                                \
-  hipLaunchKernelGGL((k_eval_walk<H, C, B>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, a.ctl, \
-                     a.parent, a.pcost, a.g, a.word, a.hops, a.tiles)
+  hipLaunchKernelGGL((k_eval_walk<H, C, B, false>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \
+                     a.ctl, a.parent, a.pcost, a.g, a.word, a.hops, a.tiles, a.h)
+#define PIRRT_WALK_TRUNC(H, C)                                                                                \
+  hipLaunchKernelGGL((k_eval_walk<H, C, false, true>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \
+                     a.ctl, a.parent, a.pcost, a.g, a.word, a.hops, a.tiles, a.h)
     const bool b = a.prob != nullptr;
+    if (a.truncated && !b) {  // the host rejects the truncated Evaluate for batches
+      if (a.hops) {
+        if (a.coherent) PIRRT_WALK_TRUNC(true, true); else PIRRT_WALK_TRUNC(true, false);
+      } else {
+        if (a.coherent) PIRRT_WALK_TRUNC(false, true); else PIRRT_WALK_TRUNC(false, false);
+      }
+      continue;
+    }
     if (a.hops) {
       if (a.coherent) { if (b) PIRRT_WALK(true, true, true); else PIRRT_WALK(true, true, false); }
       else { if (b) PIRRT_WALK(true, false, true); else PIRRT_WALK(true, false, false); }
@@ -312,6 +350,7 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
       else { if (b) PIRRT_WALK(false, false, true); else PIRRT_WALK(false, false, false); }
     }
 #undef PIRRT_WALK
+#undef PIRRT_WALK_TRUNC
   }
 }
 

@@ -14,6 +14,10 @@
 //
 // kBatched: several problems share the arrays; prob[slot] names the problem of a
 // slot.  Without it every slot belongs to problem 0.
+//
+// kTrunc (truncated Evaluate, single graphs): g(v) may be stale, and the minimum may
+// be v's own parent and cost below it; that leaves the policy as it is and is not
+// counted as a switch.
 #include "rowpass.h"
 
 namespace pirrt {
@@ -36,7 +40,7 @@ using rows::batch_grid;
 //
 // Improve runs over the compacted domain: group i takes entry i of dlist; workgroups
 // past the domain's end leave at once.
-template <int GW, int Q, typename Idx, bool kBatched>
+template <int GW, int Q, typename Idx, bool kBatched, bool kTrunc>
 __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* __restrict__ prob,
                                                      const ProblemState* __restrict__ ps,
                                                      const LoopCtl* __restrict__ ctl, const float* __restrict__ g,
@@ -125,7 +129,8 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
   const int32_t wu = __shfl(bu, src, kWave);
   const uint32_t wc = __shfl(bc, src, kWave);
   int changed = 0;
-  if (in && gl == 0 && wb != 0 && __uint_as_float(mv) < gx) {
+  if (in && gl == 0 && wb != 0 && __uint_as_float(mv) < gx &&
+      (!kTrunc || wu != parent[x] || wc != __float_as_uint(pcost[x]))) {
     parent[x] = wu;
     pcost[x] = __uint_as_float(wc);
     changed = 1;
@@ -134,20 +139,25 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
   }
 }
 
-template <int GW, int U, bool B>
+template <int GW, int U, bool B, bool T>
 void launch_improve_t(const StepArgs& a, hipStream_t s) {
   const dim3 grid = B ? batch_grid(a.n, kThreads / GW) : grid_for(a.n, GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
-    hipLaunchKernelGGL((k_improve<GW, U, uint32_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
+    hipLaunchKernelGGL((k_improve<GW, U, uint32_t, B, T>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
                        a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);
   else
-    hipLaunchKernelGGL((k_improve<GW, U, int64_t, B>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
+    hipLaunchKernelGGL((k_improve<GW, U, int64_t, B, T>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
                        a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);
 }
 
 template <int GW, int U>
 void launch_improve_b(const StepArgs& a, hipStream_t s) {
-  if (a.prob) launch_improve_t<GW, U, true>(a, s); else launch_improve_t<GW, U, false>(a, s);
+  if (a.prob)
+    launch_improve_t<GW, U, true, false>(a, s);
+  else if (a.truncated)
+    launch_improve_t<GW, U, false, true>(a, s);
+  else
+    launch_improve_t<GW, U, false, false>(a, s);
 }
 
 }  // namespace

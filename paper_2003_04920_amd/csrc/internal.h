@@ -132,12 +132,18 @@ struct WalkArgs {
   int parts;               // launches over consecutive slot ranges (single graphs)
   const int32_t* tiles;    // batches: active tile list
   bool coherent;           // device-scope stamp accesses
+  // Truncated Evaluate (single graphs): only the children of vertices with
+  // fl(g + h) < ps[0].thr are visited; unvisited vertices keep their g.
+  bool truncated;
+  const float* h;          // nullable (h = 0)
 };
 void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 
 // ---- driver.hip ----
-void launch_replan_init(int32_t P, const ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
-                        LoopCtl* ctl, hipStream_t s);
+// Also sets each problem's threshold to g(goal) as stored (+inf without pruning): the
+// threshold the truncated Evaluate reads in the first walk.
+void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
+                        LoopCtl* ctl, const float* g, int prune, hipStream_t s);
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s);
 // prob / tiles: a batch's problem map and the active tile list it rebuilds (NULL
 // for a single graph).
@@ -165,6 +171,10 @@ struct StepArgs {
   int32_t* plist;            // single graphs: compacted promising set (n entries of room)
   const int32_t* tiles;      // batches: active tile list (see LoopCtl::ntiles)
   bool lookahead;            // narrowed domain: stamp a neighbour only for a promising offer
+  // Truncated Evaluate (single graphs): P is the set the last walk queued (read from
+  // the walk stamps), and Improve counts a switch only when it changes the policy.
+  bool truncated;
+  const unsigned long long* word;  // the walk stamps
 };
 constexpr int kRowVariants = 4;
 // One small graph (n <= kSmallMax vertices; the single workgroup is faster than the

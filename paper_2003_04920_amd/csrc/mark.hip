@@ -181,17 +181,27 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
 // vertices per thread (16-byte loads of g and h), stamps the promising ones and lists
 // them (one atomic per workgroup); k_mark_rows then stamps the neighbours of the
 // listed vertices only, so the row work follows |P| rather than n.
+// kTrunc: P is the set the last (truncated) walk queued: the vertices other than the
+// root whose walk stamp lacks kWalkNoChildren (every vertex is stamped by each walk).
+template <bool kTrunc>
 __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, const ProblemState* __restrict__ ps,
                                                             LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                             const float* __restrict__ h,
                                                             uint8_t* __restrict__ stamp, int32_t* __restrict__ plist,
-                                                            IterCounters* __restrict__ ctr) {
+                                                            IterCounters* __restrict__ ctr,
+                                                            const unsigned long long* __restrict__ word) {
   if (ctl->any_active == 0) return;  // the problem has converged
   const uint8_t ep = (uint8_t)ctl->epoch;
   const float G = ps[0].thr;
   const int64_t v0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kListPer;
   uint32_t mask = 0;
-  if (v0 + kListPer <= n) {
+  if (kTrunc) {
+    const int32_t root = ps[0].root;
+    for (int i = 0; i < kListPer; ++i) {
+      const int64_t v = v0 + i;
+      if (v < n && v != root && !((uint32_t)word[v] & kWalkNoChildren)) mask |= 1u << i;
+    }
+  } else if (v0 + kListPer <= n) {
     const float4* g4 = reinterpret_cast<const float4*>(g + v0);
     const float4* h4 = reinterpret_cast<const float4*>(h ? h + v0 : g);
 #pragma unroll
@@ -352,8 +362,13 @@ template <int GW, int U, bool B>
 void launch_mark_t(const StepArgs& a, hipStream_t s) {
   if (!B) {  // single graph: promising list, then the rows of the listed vertices
     const int64_t per_block = (int64_t)kThreads * kListPer;
-    hipLaunchKernelGGL(k_promising_list, dim3((unsigned)((a.n + per_block - 1) / per_block)), dim3(kThreads), 0, s,
-                       a.n, a.ps, a.ctl, a.g, a.h, a.stamp, a.plist, a.ctr);
+    const dim3 pgrid((unsigned)((a.n + per_block - 1) / per_block));
+    if (a.truncated)
+      hipLaunchKernelGGL(k_promising_list<true>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
+                         a.plist, a.ctr, a.word);
+    else
+      hipLaunchKernelGGL(k_promising_list<false>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
+                         a.plist, a.ctr, a.word);
     const bool narrow = a.nnz < ((int64_t)1 << 32) - 64 * GW;
 #define PIRRT_MARK_ROWS(I, L)                                                                                   \
   hipLaunchKernelGGL((k_mark_rows<GW, U, I, L>), grid_for(a.n, GW), dim3(kThreads), 0, s, a.ps, a.ctl, a.plist, \

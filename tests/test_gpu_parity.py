@@ -47,7 +47,8 @@ def assert_same_stats(tag, sg, so):
         assert sg[k] == so[k], "%s: %s gpu %d oracle %d" % (tag, k, sg[k], so[k])
 
 
-def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True, lookahead=False):
+def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True, lookahead=False, truncated=False,
+             timing=False):
     """Inserts `batches` into both and, after each batch i in `plan`, replans
     (root, goal) = plan[i] on both and compares everything."""
     G = gpu_graph(P)
@@ -63,8 +64,8 @@ def run_both(P, batches, plan, h_of=None, prune=True, check_insert=True, lookahe
         if i in plan:
             root, goal = plan[i]
             h = None if h_of is None else h_of(G.n)
-            gg, pp, sg = G.replan(root, goal, h, prune, lookahead=lookahead)
-            rc, so = R.replan(root, goal, h, prune, lookahead=lookahead)
+            gg, pp, sg = G.replan(root, goal, h, prune, lookahead=lookahead, truncated=truncated, timing=timing)
+            rc, so = R.replan(root, goal, h, prune, lookahead=lookahead, truncated=truncated)
             assert rc == 0 and sg["rc"] == 0
             st = R.state()
             assert_same_policy("replan %d" % i, gg, pp, st.g, st.parent)
@@ -419,6 +420,96 @@ def test_lookahead_worked_example(P):
         assert got == want[look], (look, got)
         assert np.array_equal(g, np.array([0, 2, 1, 0.5, 1.5], np.float32))
         assert np.array_equal(p, np.array([-1, 2, 0, 0, 2], np.int32))
+
+
+# ---- truncated Evaluate (PIRRT_TRUNCATED) against the oracle's mode of it
+
+@pytest.mark.parametrize("case", ["2d", "2d_noprune", "6d_batches", "6d_30k", "2d_1200"])
+def test_truncated_evaluate(P, case):
+    """Every Replan of the plan in the truncated mode; the next batch is inserted on top
+    of the stale g it leaves, and the insertion-time policy is compared too."""
+    prune = case != "2d_noprune"
+    if case in ("2d", "2d_noprune"):
+        wl = W.plain_2d()
+        plan = {0: (0, 1)}
+    elif case == "6d_batches":
+        wl = W.batched_6d(batches=4, batch=700, seed=103)
+        plan = {i: (0, 1) for i in range(4)}
+    elif case == "6d_30k":
+        wl = W.plain_6d(samples=30_000, extra=2_000, seed=205)
+        plan = {0: (0, 1), 1: (0, 1)}
+    else:  # small enough for the single-workgroup path, which the truncated mode skips
+        wl = W.plain_2d(samples=1200, seed=8)
+        plan = {0: (0, 1)}
+    run_both(P, wl.batches, plan, wl.heuristic, prune, check_insert=True, truncated=True)
+
+
+@pytest.mark.parametrize("variant,coherent", [(v, c) for v in range(4) for c in ("0", "1")])
+def test_truncated_every_configuration(P, monkeypatch, variant, coherent):
+    monkeypatch.setenv("PIRRT_ROW_VARIANT", str(variant))
+    monkeypatch.setenv("PIRRT_WALK_COHERENT", coherent)
+    wl = W.batched_6d(batches=3, batch=600, seed=108)
+    run_both(P, wl.batches, {0: (0, 1), 2: (0, 1)}, wl.heuristic, True, check_insert=False, truncated=True)
+
+
+def test_truncated_direct_launches_and_level_setting(P, monkeypatch):
+    """The timing pass (direct launches), and PIRRT_EVALUATE=levels, which the truncated
+    mode overrides with its walk."""
+    wl = W.batched_6d(batches=2, batch=800, seed=109)
+    run_both(P, wl.batches, {0: (0, 1), 1: (0, 1)}, wl.heuristic, True, check_insert=False, truncated=True,
+             timing=True)
+    monkeypatch.setenv("PIRRT_EVALUATE", "levels")
+    run_both(P, wl.batches, {1: (0, 1)}, wl.heuristic, True, check_insert=False, truncated=True)
+
+
+def test_truncated_worked_example(P):
+    """The hand-worked six-vertex example of the oracle pins, on the device: vertex 4
+    is skipped by the walks and keeps g = 7 although its path costs 6."""
+    from oracle_pins import truncated_example
+    edges, g0, parent, pcost = truncated_example()
+    want = {True: ((2, 4, 6, 14, 1), [0, 4, 2, 5, 7, 1]), False: ((2, 6, 8, 16, 1), [0, 4, 2, 5, 6, 1])}
+    for trunc in (True, False):
+        G = gpu_graph(P)
+        G.insert_rows(W.from_edges(6, edges))
+        G.set_policy(g0, parent, pcost)
+        g, p, st = G.replan(0, 1, np.zeros(6, np.float32), True, truncated=trunc)
+        got = (st["iterations"], st["sum_P"], st["sum_D"], st["edges_examined"], st["changed_total"])
+        assert got == want[trunc][0], (trunc, got)
+        assert np.array_equal(g, np.array(want[trunc][1], np.float32)), (trunc, g)
+        assert np.array_equal(p, np.array([-1, 0, 5, 2, 3, 0], np.int32))
+
+
+def test_truncated_after_other_root_and_rejections(P):
+    """A truncated Replan rooted at the goal after one rooted at x_init reads the stale
+    g(goal) of the first as its threshold, as the oracle does; the mode is refused
+    together with PIRRT_LOOKAHEAD and for batches, leaving the state as it was."""
+    wl = W.plain_2d(samples=3000, seed=9)
+    G = gpu_graph(P)
+    R = O.Graph()
+    G.insert_rows(wl.batches[0])
+    assert R.insert_batch(wl.batches[0]) == 0
+    h = wl.heuristic(G.n)
+    for root, goal in ((0, 1), (1, 0), (0, 1)):
+        gg, pp, sg = G.replan(root, goal, h, True, truncated=True)
+        rc, so = R.replan(root, goal, h, True, truncated=True)
+        assert rc == 0
+        st = R.state()
+        assert_same_policy("root %d" % root, gg, pp, st.g, st.parent)
+        assert_same_stats("root %d" % root, sg, so)
+    before = G.get_policy()
+    with pytest.raises(P.PirrtError):
+        G.replan(0, 1, h, True, truncated=True, lookahead=True)
+    after = G.get_policy()
+    assert all(np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32))
+               for a, b in zip(before, after))
+    B = P.Batch()
+    b0 = wl.batches[0]
+    B.add_problem(b0.row_ptr, b0.col, b0.cost)
+    roots = np.zeros(1, np.int32)
+    goals = np.ones(1, np.int32)
+    rc = B._lib.pirrt_batch_replan(B._h, roots.ctypes.data, goals.ctypes.data, None, P.PIRRT_TRUNCATED, None,
+                                   None, P.PIRRT_MEM_HOST, None)
+    assert rc == P.PIRRT_EINVAL
 
 
 @pytest.mark.parametrize("prune,lookahead", [(True, False), (False, False), (True, True)])
