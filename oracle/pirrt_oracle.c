@@ -1,7 +1,7 @@
 /*
  * ORACLE -- test infrastructure only.  A plain, slow, serial CPU statement of what
  * PI-RRT#'s exploitation phase computes, used by the tests, the smoke check and the
- * CPU baseline of the benchmark to judge the GPU library.  It shares no code with
+ * CPU baseline of the benchmark to check the GPU library.  It shares no code with
  * the GPU path and is never part of the product path.
  *
  * Source: Arslan-style PI-RRT# as restated in "GPU Parallelization of Policy

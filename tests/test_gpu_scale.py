@@ -77,6 +77,29 @@ def test_plain_6d_1m(P, big):
     print("+10k replan stats", sg, flush=True)
 
 
+def test_truncated_6d_1m(P, big):
+    """The truncated Evaluate at full size: the Replan, the +10k batch inserted on top of
+    the stale g it leaves (the insertion-time policy compared too), the second Replan."""
+    wl = big
+    G = gpu_graph(P)
+    R = O.Graph()
+    for i, b in enumerate(wl.batches):
+        G.insert_rows(b)
+        assert R.insert_batch(b) == 0
+        if i > 0:
+            g, p, c = G.get_policy()
+            st = R.state()
+            assert_same_policy("insert %d after truncated Replan" % i, g, p, st.g, st.parent)
+        h = wl.heuristic(G.n)
+        gg, pp, sg = G.replan(0, 1, h, True, truncated=True)
+        rc, so = R.replan(0, 1, h, True, truncated=True)
+        assert rc == 0
+        st = R.state()
+        assert_same_policy("truncated replan %d" % i, gg, pp, st.g, st.parent)
+        assert_same_stats("truncated replan %d" % i, sg, so)
+        print("truncated replan %d stats" % i, sg, flush=True)
+
+
 def test_multi_graph_512(P):
     """The 512-problem multi-graph set (28.6M vertices) built on the device and
     replanned by one batched call, as the benchmark's multi workload does.  Eight
