@@ -363,6 +363,8 @@ def bench_learned(args):
         ys.append(lab[pick])
         pos_total += int(lab.sum())
         del R, G
+        if (i + 1) % 100 == 0:
+            log("training data: %d of %d layouts (%.1f s)" % (i + 1, args.layouts, time.perf_counter() - t0))
     X = torch.from_numpy(np.ascontiguousarray(np.concatenate(xs), np.float32)).to(dev)
     Y = torch.from_numpy(np.concatenate(ys)).to(dev)
     data_s = time.perf_counter() - t0
