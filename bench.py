@@ -795,6 +795,34 @@ def bench_breakeven(args):
         rows.append(row)
         log("breakeven: %s" % json.dumps(row))
     n0 = next((r["n"] for r in rows if r["speedup"] > 1.0), None)
+    # the small configuration itself (2,000 free samples, 2,002 vertices): time per
+    # Replan with pruning on and off, same protocol
+    small = []
+    wl = W.plain_2d()
+    b = wl.batches[0]
+    h = wl.heuristic(wl.n)
+    hd = torch.from_numpy(h).to(dev)
+    for prune in (True, False):
+        G = P.Graph(stream=stream)
+        G.insert_rows(b)
+        G.snapshot_save()
+        ts = []
+        for i in range(25):
+            G.snapshot_restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = G.replan(0, 1, hd, prune)
+            ts.append(time.perf_counter() - t0)
+        O = oracle.Graph()
+        assert O.insert_batch(b) == 0
+        t0 = time.perf_counter()
+        rc, so = O.replan(0, 1, h, prune)
+        cpu_us = 1e6 * (time.perf_counter() - t0)
+        assert rc == 0 and so["edges_examined"] == st["edges_examined"]
+        row = {"prune": prune, "n": wl.n, "iterations": st["iterations"], "edges_examined": st["edges_examined"],
+               "gpu_us": round(1e6 * float(np.median(ts[5:])), 1), "cpu_oracle_us": round(cpu_us, 1)}
+        small.append(row)
+        log("small configuration: %s" % json.dumps(row))
     out = {
         "metric": "Replan time vs graph size, GPU library against the serial oracle (2D, 8 boxes)",
         "value": n0, "unit": "vertices (break-even)", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
@@ -804,6 +832,7 @@ def bench_breakeven(args):
                                "GPU: median of 5 after 2 warm-ups, synchronous call; oracle: one serial run"},
         "cpu_baseline": {"kind": "oracle", "cores": 1, "unit": "ms", "sample": "one Replan per size"},
         "sizes": rows,
+        "small_config": small,
     }
     print(json.dumps(out), flush=True)
 
