@@ -512,6 +512,49 @@ def test_truncated_after_other_root_and_rejections(P):
     assert rc == P.PIRRT_EINVAL
 
 
+def test_truncated_degenerate_graphs(P):
+    """The truncated mode on a lone vertex (root == goal), on isolated vertices, a
+    detached component and zero-cost edges, and from a policy whose parents form a
+    cycle (the walk must leave the cycle's vertices unvisited, with their old g, until
+    Improve breaks it); both modes, pruning on and off, against the oracle."""
+    G = gpu_graph(P)
+    G.insert_batch(np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    g, p, st = G.replan(0, 0, truncated=True)
+    assert g[0] == 0 and p[0] == -1 and st["iterations"] == 1 and st["sum_P"] == 0
+    b = W.from_edges(8, [(0, 2, 0.0), (2, 3, 1.0), (4, 5, 1.0), (5, 6, 0.5), (3, 1, 2.0)])
+    for prune in (True, False):
+        G2 = gpu_graph(P)
+        R = O.Graph()
+        G2.insert_rows(b)
+        R.insert_batch(b)
+        gg, pp, sg = G2.replan(0, 1, None, prune, truncated=True)
+        rc, so = R.replan(0, 1, None, prune, truncated=True)
+        assert rc == 0
+        st = R.state()
+        assert_same_policy("degenerate truncated", gg, pp, st.g, st.parent)
+        assert_same_stats("degenerate truncated", sg, so)
+    cyc = W.from_edges(5, [(0, 1, 1.0), (1, 2, 1.0), (2, 3, 1.0), (3, 4, 1.0), (0, 4, 5.0)])
+    g0 = np.array([0, 1, 7, 8, 9], np.float32)
+    par = np.array([-1, 0, 3, 2, 3], np.int32)
+    pc = np.array([0, 1, 1, 1, 1], np.float32)
+    for trunc in (True, False):
+        for prune in (True, False):
+            G3 = gpu_graph(P)
+            R = O.Graph()
+            G3.insert_rows(cyc)
+            R.insert_batch(cyc)
+            G3.set_policy(g0, par, pc)
+            assert R.set_state(g0, par, pc) == 0
+            gg, pp, sg = G3.replan(0, 4, None, prune, truncated=trunc)
+            rc, so = R.replan(0, 4, None, prune, truncated=trunc)
+            assert rc == 0
+            st = R.state()
+            tag = "cycle truncated=%s prune=%s" % (trunc, prune)
+            assert_same_policy(tag, gg, pp, st.g, st.parent)
+            assert_same_stats(tag, sg, so)
+            assert np.array_equal(pp, np.array([-1, 0, 1, 2, 3], np.int32)), (tag, pp)
+
+
 @pytest.mark.parametrize("prune,lookahead", [(True, False), (False, False), (True, True)])
 def test_single_workgroup_path_agrees(P, monkeypatch, prune, lookahead):
     """Graphs of up to 1,536 vertices take the single-workgroup Replan; the multi-kernel
