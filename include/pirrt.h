@@ -161,8 +161,10 @@ int pirrt_insert_batch(pirrt_graph* g, int32_t n_new, const int64_t* row_ptr, co
  *                { (parent(v), v) } (Alg. 1 output).
  *   mem_kind   : location of h, g_out and parent_out.
  *   stats      : optional.
- * Errors: EINVAL (root/goal out of range, bad h), ENOTCONVERGED (cap reached; the
- * state is a consistent policy with its g), EDEVICE.
+ * Errors: EINVAL (root/goal out of range, bad h, PIRRT_TRUNCATED with
+ * PIRRT_LOOKAHEAD), ENOTCONVERGED (cap reached; the state is a consistent policy with
+ * its g -- with PIRRT_TRUNCATED, except for the stale g the mode leaves on vertices its
+ * walks skip), EDEVICE.
  */
 int pirrt_replan(pirrt_graph* g, int32_t root, int32_t goal, const float* h, uint32_t flags,
                  float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
@@ -248,8 +250,10 @@ int64_t pirrt_batch_problem_offset(const pirrt_batch* b, int32_t problem);
 
 /*
  * Replan (Alg. 2) for every problem.  roots / goals: host int32[P] local ids.  h,
- * g_out, parent_out: concatenated per-vertex arrays (nullable) at mem_kind.  stats:
- * host pirrt_stats[P] or NULL (phase timings are filled only for P = 1).
+ * g_out, parent_out: concatenated per-vertex arrays (nullable) at mem_kind.  flags:
+ * as pirrt_replan, except that PIRRT_TRUNCATED is rejected (EINVAL).  stats: host
+ * pirrt_stats[P] or NULL (with PIRRT_TIMING the phase timings cover all problems
+ * together and are copied into every entry).
  * Returns ENOTCONVERGED if any problem reached the cap (each problem's state is
  * still a consistent policy with its g).
  */

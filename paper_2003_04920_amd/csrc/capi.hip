@@ -768,11 +768,14 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   if (timing) (void)hipEventRecord(G->ev[3], s);
   launch_improve(L.sa, G->row_variant, s);
   if (timing) (void)hipEventRecord(G->ev[4], s);
-  launch_finish(L.P, G->ps, G->ctr, G->ctl, s);
+  const bool single = L.sa.prob == nullptr;
+  launch_finish(L.P, G->ps, G->ctr, G->ctl, single, s);
   if (timing) (void)hipEventRecord(G->ev[0], s);
   enqueue_evaluate(G, L, s);
   if (timing) (void)hipEventRecord(G->ev[1], s);
-  launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), G->tiles, s);
+  // a single graph's promising list (next iteration) takes the thresholds step
+  if (!single)
+    launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), G->tiles, s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
@@ -864,6 +867,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.prob = problem_map(G);
   sa.ps = G->ps;
   sa.ctl = G->ctl;
+  sa.prune = prune ? 1 : 0;
   sa.g = G->g;
   sa.h = h;
   sa.rp = G->rp;
@@ -946,7 +950,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
   enqueue_evaluate(G, L, s);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
-  launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), G->tiles, s);
+  if (problem_map(G))  // a single graph's first promising list takes the thresholds step
+    launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), G->tiles, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));

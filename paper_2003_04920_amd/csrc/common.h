@@ -88,6 +88,9 @@ struct EvalInfo {
 
 __device__ __forceinline__ float pos_inf() { return __int_as_float(0x7f800000); }
 
+// Next Evaluate epoch (0 is never used, so a cleared stamp word never matches).
+__device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ? 1u : e + 1; }
+
 // Binary32 addition with round-to-nearest-even, never contracted.
 __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
 

@@ -10,8 +10,6 @@ namespace pirrt {
 
 namespace {
 
-__device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ? 1u : e + 1; }
-
 // Mark epochs are stored as their low byte: skip the values whose low byte is 0
 // (the cleared stamp).
 __device__ __forceinline__ uint32_t next_mark_epoch(uint32_t e) { return ((e + 1) & 0xffu) == 0 ? e + 2 : e + 1; }
@@ -42,13 +40,18 @@ __global__ void k_replan_init(int32_t P, ProblemState* __restrict__ ps, int32_t*
     ctl->any_active = 1;
     ctl->any_eval = 1;
     ctl->ntiles = -1;
+    ctl->ndomain = 0;
+    ctl->npromising = 0;
   }
 }
 
 // One workgroup of kCounterSlots threads per problem: sums and clears the counter
-// copies, then applies the convergence test and the iteration cap.
+// copies, then applies the convergence test and the iteration cap.  single: a single
+// graph, whose loop has no after-eval step -- its promising list takes that step's
+// place -- so the problem's state goes to the loop flags here.
 __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemState* __restrict__ ps,
-                                                          IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl) {
+                                                          IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl,
+                                                          int single) {
   const int32_t i = blockIdx.x;
   const int t = threadIdx.x;
   IterCounters& c = ctr[(int64_t)i * kCounterSlots + t];
@@ -85,6 +88,10 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
       }
     } else {
       s.needs_eval = 0;
+    }
+    if (single) {
+      ctl->any_active = s.active;
+      ctl->npromising = 0;
     }
   }
   if (i == 0 && t == 0) ctl->epoch = next_mark_epoch(ctl->epoch);
@@ -140,8 +147,8 @@ void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pco
                      ctl, g, prune);
 }
 
-void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(P), dim3(kCounterSlots), 0, s, P, ps, ctr, ctl);
+void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(P), dim3(kCounterSlots), 0, s, P, ps, ctr, ctl, single ? 1 : 0);
 }
 
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,

@@ -144,9 +144,11 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 // threshold the truncated Evaluate reads in the first walk.
 void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
                         LoopCtl* ctl, const float* g, int prune, hipStream_t s);
-void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, hipStream_t s);
+// single: one graph (P == 1, no problem map); see launch_after_eval.
+void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s);
 // prob / tiles: a batch's problem map and the active tile list it rebuilds (NULL
-// for a single graph).
+// for a single graph).  Only batches launch it: a single graph's promising list does
+// the same work for its one problem at the start of the next iteration.
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
                        const int32_t* prob, int32_t* tiles, hipStream_t s);
 
@@ -155,8 +157,9 @@ struct StepArgs {
   int32_t n;
   int64_t nnz;               // adjacency entries (selects 32-bit offsets when they fit)
   const int32_t* prob;       // problem of each slot, or NULL for a single problem
-  const ProblemState* ps;    // thresholds and roots
+  ProblemState* ps;          // thresholds and roots
   LoopCtl* ctl;              // epoch, any_active, ndomain
+  int prune;                 // single graphs: threshold g(goal) (1) or +inf (0)
   const float* g;
   const float* h;            // nullable
   const int64_t* rp;

@@ -183,16 +183,30 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
 // listed vertices only, so the row work follows |P| rather than n.
 // kTrunc: P is the set the last (truncated) walk queued: the vertices other than the
 // root whose walk stamp lacks kWalkNoChildren (every vertex is stamped by each walk).
+//
+// It also takes the place of the after-eval step of a batch: every workgroup derives
+// the threshold G from g(goal) of the last Evaluate (or +inf without pruning; the loop
+// stops once the problem is inactive), and workgroup 0 publishes it with the loop
+// flags for the kernels that follow and takes a fresh Evaluate epoch.
 template <bool kTrunc>
-__global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, const ProblemState* __restrict__ ps,
+__global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemState* __restrict__ ps,
                                                             LoopCtl* __restrict__ ctl, const float* __restrict__ g,
                                                             const float* __restrict__ h,
                                                             uint8_t* __restrict__ stamp, int32_t* __restrict__ plist,
                                                             IterCounters* __restrict__ ctr,
-                                                            const unsigned long long* __restrict__ word) {
-  if (ctl->any_active == 0) return;  // the problem has converged
+                                                            const unsigned long long* __restrict__ word, int prune) {
+  const bool active = ps[0].active != 0;
+  const float G = active ? (prune ? g[ps[0].goal] : pos_inf()) : -pos_inf();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ps[0].thr = G;
+    ctl->any_active = active ? 1 : 0;
+    ctl->any_eval = 0;
+    ctl->ndomain = 0;
+    ctl->ntiles = -1;
+    ctl->eval_epoch = next_epoch(ctl->eval_epoch);
+  }
+  if (!active) return;  // the problem has converged
   const uint8_t ep = (uint8_t)ctl->epoch;
-  const float G = ps[0].thr;
   const int64_t v0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kListPer;
   uint32_t mask = 0;
   if (kTrunc) {
@@ -365,10 +379,10 @@ void launch_mark_t(const StepArgs& a, hipStream_t s) {
     const dim3 pgrid((unsigned)((a.n + per_block - 1) / per_block));
     if (a.truncated)
       hipLaunchKernelGGL(k_promising_list<true>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
-                         a.plist, a.ctr, a.word);
+                         a.plist, a.ctr, a.word, a.prune);
     else
       hipLaunchKernelGGL(k_promising_list<false>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
-                         a.plist, a.ctr, a.word);
+                         a.plist, a.ctr, a.word, a.prune);
     const bool narrow = a.nnz < ((int64_t)1 << 32) - 64 * GW;
 #define PIRRT_MARK_ROWS(I, L)                                                                                   \
   hipLaunchKernelGGL((k_mark_rows<GW, U, I, L>), grid_for(a.n, GW), dim3(kThreads), 0, s, a.ps, a.ctl, a.plist, \
