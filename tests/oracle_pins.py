@@ -609,7 +609,35 @@ def pin_truncated_properties(lib):
             assert g1 >= d[1] * (1 - 1e-4), (wl.name, g1, d[1])
 
 
+def pin_row_order(lib):
+    """Metamorphic: shuffling the entries inside every input row changes neither the
+    insertion-time policy nor the Replan (both take lexicographic minima, so the order
+    in which candidates are met cannot matter), including on a lattice full of ties."""
+    import dataclasses
+    rng = np.random.default_rng(5)
+    for wl in (W.plain_2d(samples=1500, seed=12), W.batched_6d(batches=2, batch=300, seed=110)):
+        shuffled = []
+        for b in wl.batches:
+            col, cost = b.col.copy(), b.cost.copy()
+            for v in range(b.n_new):
+                a, e = int(b.row_ptr[v]), int(b.row_ptr[v + 1])
+                perm = a + rng.permutation(e - a)
+                col[a:e], cost[a:e] = b.col[perm], b.cost[perm]
+            shuffled.append(dataclasses.replace(b, col=col, cost=cost))
+        outs = []
+        for batches in (wl.batches, shuffled):
+            G = build_graph(lib, batches)
+            ins = G.state()
+            rc, st = G.replan(0, 1, wl.heuristic(G.n), True)
+            assert rc == 0
+            fin = G.state()
+            outs.append((ins.g.view(np.uint32).copy(), ins.parent.copy(), fin.g.view(np.uint32).copy(),
+                         fin.parent.copy(), st))
+        for x, y in zip(outs[0], outs[1]):
+            assert (x == y) if isinstance(x, dict) else np.array_equal(x, y), wl.name
+
+
 PINS = [pin_golden, pin_path_fold, pin_errors, pin_lattice, pin_complete_graph, pin_insertion_local,
         pin_monotone, pin_invariants, pin_dijkstra, pin_pruned_exactness, pin_any_initial_policy,
         pin_bruteforce_small, pin_lookahead_worked_example, pin_lookahead_properties,
-        pin_truncated_worked_example, pin_truncated_properties]
+        pin_truncated_worked_example, pin_truncated_properties, pin_row_order]

@@ -173,6 +173,39 @@ def test_degenerate_graphs(P):
     assert np.isinf(gg[4:]).all() and gg[7] == np.inf
 
 
+def test_permuted_row_order_is_invisible(P):
+    """The entries of every input row shuffled: insertion and Replan take lexicographic
+    minima, so the policy, g and counters are the same bits as for the rows in order
+    (and as the oracle's)."""
+    import dataclasses
+    wl = W.plain_2d(samples=3000, seed=12)
+    b = wl.batches[0]
+    rng = np.random.default_rng(5)
+    col, cost = b.col.copy(), b.cost.copy()
+    for v in range(b.n_new):
+        a, e = int(b.row_ptr[v]), int(b.row_ptr[v + 1])
+        perm = a + rng.permutation(e - a)
+        col[a:e], cost[a:e] = b.col[perm], b.cost[perm]
+    bp = dataclasses.replace(b, col=col, cost=cost)
+    h = wl.heuristic(wl.n)
+    outs = []
+    for batch in (b, bp):
+        G = gpu_graph(P)
+        G.insert_rows(batch)
+        gi, pi, _ = G.get_policy()
+        gg, pp, sg = G.replan(0, 1, h, True)
+        outs.append((np.asarray(gi).copy(), np.asarray(pi).copy(), np.asarray(gg).copy(), np.asarray(pp).copy(), sg))
+    R = O.Graph()
+    assert R.insert_batch(bp) == 0
+    rc, so = R.replan(0, 1, h, True)
+    st = R.state()
+    for tag, (gi, pi, gg, pp, sg) in zip(("rows in order", "rows shuffled"), outs):
+        assert_same_policy(tag, gg, pp, st.g, st.parent)
+        assert_same_stats(tag, sg, so)
+    assert np.array_equal(outs[0][0].view(np.uint32), outs[1][0].view(np.uint32))
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_rows_longer_than_a_wave(P):
     # a hub with 300 neighbours and a ring: rows far longer than 64 entries
     rng = np.random.default_rng(9)

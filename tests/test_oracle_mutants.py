@@ -19,6 +19,7 @@ MUTANTS = {
     "improve_non_strict": ("if (best_u >= 0 && best < G->g[v] && (", "if (best_u >= 0 && best <= G->g[v] && ("),
     "improve_tie_highest": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))",
                             "(u > best_u || (u == best_u && G->cst[v][j] < best_c))"),
+    "improve_tie_first_seen": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))", "0"),
     "improve_cost_tie_ignored": ("(u < best_u || (u == best_u && G->cst[v][j] < best_c))", "(u < best_u)"),
     "improve_max": (
         "float cand = G->g[u] + G->cst[v][j];\n        if (cand < best ||",
