@@ -272,6 +272,16 @@ def test_invalid_arguments_leave_state(P):
         G.replan(0, 1, h)
 
 
+def test_device_allocation_failure(P):
+    """An adjacency reservation far beyond the device's memory (2^42 entries): creation
+    reports ENOMEM without a handle, and the device stays usable for the next graph."""
+    with pytest.raises(P.PirrtError) as e:
+        gpu_graph(P, edge_capacity=1 << 42)
+    assert e.value.code == P.PIRRT_ENOMEM
+    wl = W.plain_2d(samples=500, seed=13)
+    run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, True)
+
+
 def test_snapshot_restore_repeatable(P):
     wl = W.batched_6d(batches=2, batch=2000, seed=100)
     G = gpu_graph(P)
