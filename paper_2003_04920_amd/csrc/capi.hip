@@ -848,14 +848,19 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
     q.needs_eval = 1;
     q.cap = (int32_t)std::min<int64_t>(cap_iters, INT32_MAX);
   }
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->ps, G->hps, sizeof(ProblemState) * (size_t)P, hipMemcpyHostToDevice, s));
-  HIP_OR_FAIL(G, hipMemsetAsync(G->stamp, 0, (size_t)n, s));  // no stamp older than this Replan
-  // the previous roots lose their mark; the new roots get it
-  launch_unmark_roots(G->nroots, G->droots, G->slot_of, G->parent, s);
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, root_ids, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
+  if (P == 1 && !G->batched) {
+    // one launch from scalar arguments: no host-to-device copies on the latency path
+    launch_replan_init_single(G->ps, root_slots[0], goal_slots[0], G->hps[0].cap, root_ids[0], G->nroots, G->droots,
+                              G->slot_of, G->parent, G->pcost, G->ctr, G->ctl, G->g, prune ? 1 : 0, s);
+  } else {
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->ps, G->hps, sizeof(ProblemState) * (size_t)P, hipMemcpyHostToDevice, s));
+    // the previous roots lose their mark; the new roots get it
+    launch_unmark_roots(G->nroots, G->droots, G->slot_of, G->parent, s);
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, root_ids, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
+    launch_replan_init(P, G->ps, G->parent, G->pcost, G->ctr, G->ctl, G->g, prune ? 1 : 0, s);
+  }
   G->nroots = P;
   G->hroots.assign(root_ids, root_ids + P);
-  launch_replan_init(P, G->ps, G->parent, G->pcost, G->ctr, G->ctl, G->g, prune ? 1 : 0, s);
   HIP_OR_FAIL(G, hipGetLastError());
 
   LoopArgs L;
@@ -943,6 +948,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
     return PIRRT_OK;
   }
 
+  // the multi-kernel loop's marks: no stamp older than this Replan
+  HIP_OR_FAIL(G, hipMemsetAsync(G->stamp, 0, (size_t)n, s));
   pirrt_stats agg;
   memset(&agg, 0, sizeof(agg));
   // first Evaluate of every problem

@@ -45,6 +45,47 @@ __global__ void k_replan_init(int32_t P, ProblemState* __restrict__ ps, int32_t*
   }
 }
 
+// A single graph's set-up in one launch, with no copies from the host: the previous
+// roots (caller ids in droots[0..nold)) lose their mark, the new root gets it and is
+// recorded in droots[0], and the problem state starts from the kernel arguments.
+// Otherwise as k_replan_init.
+__global__ void __launch_bounds__(kCounterSlots) k_replan_init_single(
+    ProblemState* __restrict__ ps, int32_t root, int32_t goal, int32_t cap, int32_t root_id, int32_t nold,
+    int32_t* __restrict__ droots, const int32_t* __restrict__ slot_of, int32_t* __restrict__ parent,
+    float* __restrict__ pcost, IterCounters* __restrict__ ctr, LoopCtl* __restrict__ ctl, const float* __restrict__ g,
+    int prune) {
+  const int t = threadIdx.x;
+  IterCounters& c = ctr[t];
+  c.changed = 0;
+  c.nP = 0;
+  c.nD = 0;
+  c.edges = 0ull;
+  if (t == 0) {
+    for (int32_t i = 0; i < nold; ++i) {  // in order, before the new mark (a root may repeat)
+      const int32_t s = slot_of[droots[i]];
+      if (parent[s] == kRootMark) parent[s] = -1;
+    }
+    droots[0] = root_id;
+    parent[root] = kRootMark;
+    pcost[root] = 0.0f;
+    ProblemState q = {};
+    q.root = root;
+    q.goal = goal;
+    q.thr = prune ? g[goal] : pos_inf();
+    q.active = 1;
+    q.needs_eval = 1;
+    q.cap = cap;
+    ps[0] = q;
+    ctl->epoch = next_mark_epoch(ctl->epoch);
+    ctl->eval_epoch = next_epoch(ctl->eval_epoch);
+    ctl->any_active = 1;
+    ctl->any_eval = 1;
+    ctl->ntiles = -1;
+    ctl->ndomain = 0;
+    ctl->npromising = 0;
+  }
+}
+
 // One workgroup of kCounterSlots threads per problem: sums and clears the counter
 // copies, then applies the convergence test and the iteration cap.  single: a single
 // graph, whose loop has no after-eval step -- its promising list takes that step's
@@ -145,6 +186,13 @@ void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pco
   const int64_t t = (int64_t)P * kCounterSlots;
   hipLaunchKernelGGL(k_replan_init, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, P, ps, parent, pcost, ctr,
                      ctl, g, prune);
+}
+
+void launch_replan_init_single(ProblemState* ps, int32_t root, int32_t goal, int32_t cap, int32_t root_id,
+                               int32_t nold, int32_t* droots, const int32_t* slot_of, int32_t* parent, float* pcost,
+                               IterCounters* ctr, LoopCtl* ctl, const float* g, int prune, hipStream_t s) {
+  hipLaunchKernelGGL(k_replan_init_single, dim3(1), dim3(kCounterSlots), 0, s, ps, root, goal, cap, root_id, nold,
+                     droots, slot_of, parent, pcost, ctr, ctl, g, prune);
 }
 
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s) {

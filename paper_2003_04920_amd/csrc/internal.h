@@ -144,6 +144,12 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 // threshold the truncated Evaluate reads in the first walk.
 void launch_replan_init(int32_t P, ProblemState* ps, int32_t* parent, float* pcost, IterCounters* ctr,
                         LoopCtl* ctl, const float* g, int prune, hipStream_t s);
+// A single graph's set-up from scalar arguments (no host copies): unmarks the nold
+// previous roots listed in droots (caller ids), marks root (a slot), writes root_id to
+// droots[0] and initialises ps[0] with goal (a slot) and cap.
+void launch_replan_init_single(ProblemState* ps, int32_t root, int32_t goal, int32_t cap, int32_t root_id,
+                               int32_t nold, int32_t* droots, const int32_t* slot_of, int32_t* parent, float* pcost,
+                               IterCounters* ctr, LoopCtl* ctl, const float* g, int prune, hipStream_t s);
 // single: one graph (P == 1, no problem map); see launch_after_eval.
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s);
 // prob / tiles: a batch's problem map and the active tile list it rebuilds (NULL
