@@ -828,11 +828,20 @@ int loop_graph(pirrt_graph* G, LoopArgs& L, int k, hipGraphExec_t* out) {
   return PIRRT_OK;
 }
 
+// Caller buffers that receive the final policy (see policy_out).
+struct PolicyOut {
+  float* g;
+  int32_t* parent;
+  int mem_kind;
+};
+
 // Runs Replan for P problems with the given root ids and root / goal slots.  h is
 // a device array in slot order (or NULL).  Fills per-problem stats (P entries,
-// nullable).
+// nullable).  out (nullable): the policy copy-out is enqueued before the final wait,
+// so a call waits for the device once at its end.
 int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t* root_slots,
-               const int32_t* goal_slots, const float* h, bool prune, bool timing, pirrt_stats* stats) {
+               const int32_t* goal_slots, const float* h, bool prune, bool timing, pirrt_stats* stats,
+               const PolicyOut* out = nullptr) {
   hipStream_t s = G->stream;
   int rc;
   auto t_start = std::chrono::steady_clock::now();
@@ -929,6 +938,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
     launch_replan_small(n, G->rp, G->col, G->cst, h, G->ext_of, prune, G->lookahead, G->ps, G->parent, G->pcost,
                         G->g, s);
     HIP_OR_FAIL(G, hipGetLastError());
+    if (out && (out->g || out->parent) && (rc = policy_out(G, out->g, out->parent, nullptr, out->mem_kind)))
+      return rc;
     HIP_OR_FAIL(G, hipMemcpyAsync(G->hps, G->ps, sizeof(ProblemState), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
     const ProblemState& q = G->hps[0];
@@ -1032,6 +1043,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
       plan = 1;
     }
   }
+  if (out && (out->g || out->parent) && (rc = policy_out(G, out->g, out->parent, nullptr, out->mem_kind)))
+    return rc;
   HIP_OR_FAIL(G, hipMemcpyAsync(G->hps, G->ps, sizeof(ProblemState) * (size_t)P, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   int32_t most = 0;
@@ -1329,16 +1342,12 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
   pirrt_stats st;
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   G->truncated = (flags & PIRRT_TRUNCATED) != 0;
+  const PolicyOut po{g_out, parent_out, mem_kind};
   rc = run_replan(G, 1, &root, &rslot, &gslot, hdev, (flags & PIRRT_NO_PRUNE) == 0, (flags & PIRRT_TIMING) != 0,
-                  &st);
+                  &st, &po);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
-  const int keep = rc;
-  if (g_out || parent_out) {
-    if ((rc = policy_out(G, g_out, parent_out, nullptr, mem_kind))) return rc;
-  }
-  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
   if (stats) *stats = st;
-  return keep;
+  return rc;
 }
 
 int pirrt_tune(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uint32_t flags, int mem_kind,
@@ -1588,15 +1597,11 @@ int pirrt_batch_replan(pirrt_batch* B, const int32_t* roots, const int32_t* goal
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   G->lookahead = (flags & PIRRT_LOOKAHEAD) != 0;
   G->truncated = false;
+  const PolicyOut po{g_out, parent_out, mem_kind};
   rc = run_replan(G, P, rid.data(), rs.data(), gs.data(), hdev, (flags & PIRRT_NO_PRUNE) == 0,
-                  (flags & PIRRT_TIMING) != 0, stats);
+                  (flags & PIRRT_TIMING) != 0, stats, &po);
   if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
-  const int keep = rc;
-  if (g_out || parent_out) {
-    if ((rc = policy_out(G, g_out, parent_out, nullptr, mem_kind))) return rc;
-  }
-  HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
-  return keep;
+  return rc;
 }
 
 int pirrt_batch_tune(pirrt_batch* B, const int32_t* roots, const int32_t* goals, const float* h, uint32_t flags,
