@@ -37,6 +37,7 @@ FP64_PEAK_TFLOPS = 78.6  # binary64 vector peak of the MI355X (fused multiply-ad
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 IMPROVE_SRC = os.path.join(ROOT, "paper_2003_04920_amd", "csrc", "improve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_6d_1m_traffic.txt")
+MULTI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_multi512_traffic.txt")
 CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
@@ -65,13 +66,13 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per k_improve launch from the committed counter summary, or None
     when the summary is missing or was taken on another version of the kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
@@ -158,6 +159,9 @@ def bench_multi(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream().cuda_stream
     specs = [W.multi_problem_spec(i) for i in range(args.problems)]
+    if args.config >= 0:  # a fixed kernel configuration instead of the autotuner's choice
+        os.environ["PIRRT_ROW_VARIANT"] = str(args.config % 4)
+        os.environ["PIRRT_WALK_COHERENT"] = "0" if args.config >= 4 else "1"
     B = P.Batch(stream=stream)
     rrgs, hs = [], []
     torch.cuda.synchronize()
@@ -183,7 +187,7 @@ def bench_multi(args):
     roots = np.zeros(len(specs), np.int32)
     goals = np.ones(len(specs), np.int32)
     t0 = time.perf_counter()
-    tuned = B.tune(roots, goals, h, True)
+    tuned = B.tune(roots, goals, h, True) if args.config < 0 else args.config
     log("autotuner: configuration %d (row split %d, %s-scope Evaluate stamps), %.2f s" %
         (tuned, tuned % 4, "workgroup" if tuned >= 4 else "device", time.perf_counter() - t0))
 
@@ -211,16 +215,27 @@ def bench_multi(args):
     nbytes = improve_bytes(edges, sum_d, n, t0s["improve_launches"])
     achieved = nbytes / (t0s["ms_improve"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_improve (batched)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(MULTI_TRAFFIC_FILE),
+                "kernel": "k_improve (batched)",
                 "launches": t0s["improve_launches"],
                 "avg_launch_us": round(1e3 * t0s["ms_improve"] / max(1, t0s["improve_launches"]), 2),
                 "bytes_per_launch": int(nbytes / max(1, t0s["improve_launches"]))}
     log("timing pass: improve %.3f ms over %d launches, %.1f GB/s algorithmic" %
         (t0s["ms_improve"], t0s["improve_launches"], achieved))
+    if args.copy_calibration:
+        x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)  # one elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        del x, y
+        log("copy calibration: 1 GiB read + 1 GiB written")
     # the same problems, one graph handle and one pirrt_replan call each
     graphs = []
     off = B.offsets
-    for i, (R, sp) in enumerate(zip(rrgs, specs)):
+    ms_seq = None
+    for i, (R, sp) in enumerate(zip(rrgs, specs) if not args.no_sequential else []):
         G = P.Graph(stream=stream)
         R.connect(0, sp.radius, G)
         G.snapshot_save()
@@ -235,17 +250,18 @@ def bench_multi(args):
             tot += G.replan(0, 1, hh, True, g_out=gg, parent_out=pp)[2]["edges_examined"]
         return tot
 
-    for _ in range(max(1, args.warmup // 2)):
-        seq_edges = seq_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = max(1, args.steps // 2)
-    for _ in range(reps):
-        seq_edges = seq_step()
-    torch.cuda.synchronize()
-    ms_seq = 1e3 * (time.perf_counter() - t0) / reps
-    assert seq_edges == edges, (seq_edges, edges)
-    log("sequential: %.3f ms for %d pirrt_replan calls" % (ms_seq, len(graphs)))
+    if not args.no_sequential:
+        for _ in range(max(1, args.warmup // 2)):
+            seq_edges = seq_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, args.steps // 2)
+        for _ in range(reps):
+            seq_edges = seq_step()
+        torch.cuda.synchronize()
+        ms_seq = 1e3 * (time.perf_counter() - t0) / reps
+        assert seq_edges == edges, (seq_edges, edges)
+        log("sequential: %.3f ms for %d pirrt_replan calls" % (ms_seq, len(graphs)))
     cpu = None
     if not args.no_cpu_baseline:
         # the serial oracle on the first problems, up to about 15 s of host time
@@ -282,8 +298,9 @@ def bench_multi(args):
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "sequential_ms": round(ms_seq, 3), "speedup_vs_sequential": round(ms_seq / ms_batch, 2),
-        "sequential_gteps": round(edges / ms_seq / 1e6, 3),
+        "sequential_ms": round(ms_seq, 3) if ms_seq else None,
+        "speedup_vs_sequential": round(ms_seq / ms_batch, 2) if ms_seq else None,
+        "sequential_gteps": round(edges / ms_seq / 1e6, 3) if ms_seq else None,
         "device_build_s": round(build_s, 3),
         "autotuned_config": tuned,
     }
@@ -921,6 +938,8 @@ def main():
     ap.add_argument("--samples", type=int, default=1_000_000)
     ap.add_argument("--extra", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="multi: skip the one-call-per-problem comparison (for counter runs)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB elementwise copy (reference for HBM byte counters)")
