@@ -41,8 +41,34 @@ MULTI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_multi512_traffic.
 CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
+CPU_REPS = 3  # oracle Replans timed for cpu_baseline (median)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    """The host CPU model string and the number of CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count() or 0
+    return {"cpu": model, "nproc": nproc}
+
+
+def host_fields() -> dict:
+    h = host_info()
+    return {"host_cpu": h["cpu"], "host_nproc": h["nproc"]}
 
 
 def improve_bytes(edges: int, sum_d: int, n: int, launches: int) -> int:
@@ -284,6 +310,7 @@ def bench_multi(args):
         cpu = {"value": round(cpu_edges / spent / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": "one full Replan of each of the first %d problems (%d examined edges, serial C oracle, "
                          "one thread, %.2f s)" % (used, cpu_edges, spent)}
+        cpu.update(host_fields())
         log("cpu baseline: %s" % json.dumps(cpu))
     out = {
         "metric": "Batched multi-graph Replan GTEPS (%d problems, one pirrt_batch_replan per step)" % len(specs),
@@ -474,6 +501,7 @@ def bench_learned(args):
         cpu = {"value": round(reps * bs / cpu_s, 1), "unit": "training samples/s", "cores": 1, "kind": "oracle",
                "sample": "%d training steps of %d samples with the numpy oracle (forward, backward, Adam; "
                          "one BLAS thread, %.1f s)" % (reps, bs, cpu_s)}
+        cpu.update(host_fields())
         log("cpu baseline: %s" % json.dumps(cpu))
 
     # ---- planner comparison on held-out layouts
@@ -847,7 +875,8 @@ def bench_breakeven(args):
         "config": {"workload": "2D unit square, 8 boxes; n free samples in one batch, r = (ln n/n)^(1/2); one full "
                                "Replan from the insertion-time policy, pruning on, h = Euclidean distance to goal; "
                                "GPU: median of 5 after 2 warm-ups, synchronous call; oracle: one serial run"},
-        "cpu_baseline": {"kind": "oracle", "cores": 1, "unit": "ms", "sample": "one Replan per size"},
+        "cpu_baseline": dict({"kind": "oracle", "cores": 1, "unit": "ms", "sample": "one Replan per size"},
+                             **host_fields()),
         "sizes": rows,
         "small_config": small,
     }
@@ -914,6 +943,7 @@ def bench_berrt6d(args):
         cpu = {"value": round(cpu_edges / spent / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": "the Replans after the first %d batches (serial C oracle, one thread, %.2f s; the library "
                          "took %.3f s for the same Replans)" % (used, spent, gpu_same)}
+        cpu.update(host_fields())
         log("cpu baseline: %s" % json.dumps(cpu))
     out = {
         "metric": "Batched-Extension 6D: Replan after every batch, GTEPS over all Replans",
@@ -1060,6 +1090,10 @@ def main():
     for s in stats:
         assert s["edges_examined"] == st["edges_examined"] and s["iterations"] == st["iterations"]
     log("timed: %d steps, %.3f ms/step, %.1f GTEPS" % (args.steps, ms_per_step, gteps))
+    # the policy the last timed step produced (the captured-graph path), kept for the
+    # bit-exact comparison with the oracle below
+    g_timed = g_out.cpu().numpy().copy()
+    p_timed = p_out.cpu().numpy().copy()
 
     nbytes = improve_bytes(tst["edges_examined"], tst["sum_D"], n, tst["improve_launches"])
     achieved = nbytes / (tst["ms_improve"] * 1e-3) / 1e9
@@ -1185,13 +1219,30 @@ def main():
         R = oracle.Graph()
         assert R.insert_batch(b0) == 0
         hh = wl.heuristic(n)
-        t0 = time.perf_counter()
-        rc, so = R.replan(0, 1, hh, True)
-        t_cpu = time.perf_counter() - t0
-        assert rc == 0 and so["edges_examined"] == st["edges_examined"], (so, st)
+        s0 = R.state()
+        times = []
+        for rep in range(CPU_REPS):
+            if rep:
+                assert R.set_state(s0.g, s0.parent, s0.pcost) == 0
+            t0 = time.perf_counter()
+            rc, so = R.replan(0, 1, hh, True)
+            times.append(time.perf_counter() - t0)
+            assert rc == 0
+        t_cpu = sorted(times)[len(times) // 2]
+        # the timed GPU steps against the oracle: g bit for bit, parents and counters exact
+        ref = R.state()
+        bad_g = int(np.count_nonzero(g_timed.view(np.uint32) != ref.g.view(np.uint32)))
+        bad_p = int(np.count_nonzero(p_timed != ref.parent))
+        if bad_g or bad_p:
+            raise SystemExit("timed Replan differs from the oracle: %d g values, %d parents" % (bad_g, bad_p))
+        for k in ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total"):
+            if so[k] != st[k]:
+                raise SystemExit("timed Replan differs from the oracle in %s: %d against %d" % (k, st[k], so[k]))
         cpu = {"value": round(so["edges_examined"] / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": "one full Replan of the same 1M-vertex graph from its insertion-time policy "
-                         "(serial C oracle, one thread, %.2f s)" % t_cpu}
+               "sample": "one full Replan of the same 1M-vertex graph from its insertion-time policy, median of %d "
+                         "(serial C oracle, one thread, %.2f s each)" % (CPU_REPS, t_cpu),
+               "parity": "timed GPU Replan equals the oracle: g bit for bit, parents and counters exact"}
+        cpu.update(host_fields())
         log("cpu baseline: %s" % json.dumps(cpu))
 
     if args.copy_calibration:

@@ -99,7 +99,7 @@ typedef struct {
 
 typedef struct {
   int32_t iterations;     /* Improve passes, including the last one with no change */
-  int32_t eval_levels;    /* tree levels visited by the last Evaluate */
+  int32_t reserved0;      /* 0 */
   int64_t edges_examined; /* sum over iterations of the degrees of the Improve domain */
   int64_t sum_P;          /* sum over iterations of |promising set| */
   int64_t sum_D;          /* sum over iterations of |Improve domain| */

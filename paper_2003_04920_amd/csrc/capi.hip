@@ -174,6 +174,12 @@ struct pirrt_graph {
   LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
   bool have_prev_key = false;
   bool small_graphs = true;  // single-workgroup Replan up to kSmallMax vertices (PIRRT_SMALL=0: off)
+  // Host-side fault hook (PIRRT_FAULT_INJECT at create): "launch" makes the next
+  // Replan fail as if a kernel launch had returned a HIP error (no device work is
+  // involved; the handle is poisoned like after a real one), "alloc" makes the next
+  // growth of the vertex storage fail as if the device allocation had.
+  bool fault_launch = false;
+  bool fault_alloc = false;
   bool poisoned = false;
   std::string err;
 };
@@ -276,6 +282,10 @@ void forget_vertex_arrays(pirrt_graph* T) {
 // row offsets, the id maps and the problem map.  On failure nothing changes.
 int ensure_vcap(pirrt_graph* G, int64_t need) {
   if (need <= G->vcap) return PIRRT_OK;
+  if (G->fault_alloc) {  // injected failure, once
+    G->fault_alloc = false;
+    return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed (injected by PIRRT_FAULT_INJECT)");
+  }
   int64_t cap = G->vcap + G->vcap / 2;
   if (cap < need) cap = need;
   if (cap < kMinVertexCap) cap = kMinVertexCap;
@@ -871,6 +881,10 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   G->nroots = P;
   G->hroots.assign(root_ids, root_ids + P);
   HIP_OR_FAIL(G, hipGetLastError());
+  if (G->fault_launch) {  // injected failure: behave as a failed launch would
+    G->fault_launch = false;
+    return fail_device(G, hipErrorLaunchFailure, "Replan launch (injected by PIRRT_FAULT_INJECT)");
+  }
 
   LoopArgs L;
   L.P = P;
@@ -915,7 +929,6 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.h = h;
   EvalArgs& ea = L.ea;
   ea.n = n;
-  ea.root = root_slots[0];
   ea.ps = G->ps;
   ea.parent = G->parent;
   ea.pcost = G->pcost;
@@ -1261,6 +1274,11 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   if (gr) G->use_graph = atoi(gr) != 0;
   const char* sm = getenv("PIRRT_SMALL");
   if (sm) G->small_graphs = atoi(sm) != 0;
+  const char* fi = getenv("PIRRT_FAULT_INJECT");
+  if (fi) {
+    G->fault_launch = strcmp(fi, "launch") == 0;
+    G->fault_alloc = strcmp(fi, "alloc") == 0;
+  }
   const char* variant = getenv("PIRRT_ROW_VARIANT");
   if (variant) {
     int v = atoi(variant);

@@ -43,10 +43,13 @@ __device__ __forceinline__ int32_t load_counter(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root, const ProblemState* __restrict__ ps,
+// The root is read from the problem state (not baked into a launch argument), so a
+// captured loop body stays valid when a later Replan on the same graph changes it.
+__global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, const ProblemState* __restrict__ ps,
                                                        const int32_t* __restrict__ parent, float* __restrict__ g,
                                                        int32_t* __restrict__ child_cnt) {
   if (!ps->needs_eval) return;
+  const int32_t root = ps->root;
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   if (v == root) {
@@ -58,11 +61,12 @@ __global__ void __launch_bounds__(kThreads) k_eval_prep(int32_t n, int32_t root,
   if (p >= 0) atomicAdd(&child_cnt[p], 1);
 }
 
-__global__ void __launch_bounds__(kThreads) k_eval_fill(int32_t n, int32_t root, const ProblemState* __restrict__ ps,
+__global__ void __launch_bounds__(kThreads) k_eval_fill(int32_t n, const ProblemState* __restrict__ ps,
                                                        const int32_t* __restrict__ parent,
                                                        const int32_t* __restrict__ child_ptr,
                                                        int32_t* __restrict__ child_cnt, int32_t* __restrict__ child) {
   if (!ps->needs_eval) return;
+  const int32_t root = ps->root;
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || v == root) return;
   int32_t p = parent[v];
@@ -108,10 +112,10 @@ struct Bfs {
   const ProblemState* ps;  // the walk runs only when ps->needs_eval
 };
 
-__global__ void __launch_bounds__(kWgThreads) k_bfs_head(int32_t root, int32_t limit, Bfs B) {
+__global__ void __launch_bounds__(kWgThreads) k_bfs_head(int32_t limit, Bfs B) {
   if (!B.ps->needs_eval) return;
   if (threadIdx.x == 0) {
-    B.fr0[0] = root;
+    B.fr0[0] = B.ps->root;
     B.lvl[0] = 1;
     B.lvl[1] = 0;
     B.lvl[2] = 0;
@@ -356,13 +360,12 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
 
 void launch_evaluate(const EvalArgs& a, hipStream_t s) {
   const int32_t n = a.n;
-  hipLaunchKernelGGL(k_eval_prep, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.ps, a.parent, a.g,
-                     a.child_cnt);
+  hipLaunchKernelGGL(k_eval_prep, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.ps, a.parent, a.g, a.child_cnt);
   scan_i32_to_i32(a.child_cnt, n, a.child_ptr, a.scan_scratch, s);
-  hipLaunchKernelGGL(k_eval_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.root, a.ps, a.parent, a.child_ptr,
+  hipLaunchKernelGGL(k_eval_fill, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a.ps, a.parent, a.child_ptr,
                      a.child_cnt, a.child);
   Bfs B{a.child_ptr, a.child, a.pcost, a.g, a.fr0, a.fr1, a.lvl, a.info, a.ps};
-  hipLaunchKernelGGL(k_bfs_head, dim3(1), dim3(kWgThreads), 0, s, a.root, (int32_t)kWgThreads, B);
+  hipLaunchKernelGGL(k_bfs_head, dim3(1), dim3(kWgThreads), 0, s, (int32_t)kWgThreads, B);
   for (int32_t j = 0; j < a.mid_launches; ++j)
     hipLaunchKernelGGL(k_bfs_level, dim3(a.level_blocks), dim3(kThreads), 0, s, j, (int32_t)kWgThreads, B);
   hipLaunchKernelGGL(k_bfs_tail, dim3(1), dim3(kWgThreads), 0, s, a.mid_launches, (int32_t)kWgThreads, B);

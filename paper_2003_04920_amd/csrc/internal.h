@@ -100,8 +100,7 @@ void launch_policy_from_ext(int32_t n, const int32_t* slot_of, const int32_t* pr
 // ---- evaluate.hip ----
 struct EvalArgs {
   int32_t n;
-  int32_t root;
-  const ProblemState* ps;  // one problem; the walk runs only when ps->needs_eval
+  const ProblemState* ps;  // one problem (its root); the walk runs only when ps->needs_eval
   int32_t* parent;
   float* pcost;
   float* g;

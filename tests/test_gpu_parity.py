@@ -282,6 +282,51 @@ def test_device_allocation_failure(P):
     run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, True)
 
 
+def test_injected_launch_failure_poisons_the_handle(P, monkeypatch):
+    """A HIP error in a Replan (forced on the host by PIRRT_FAULT_INJECT=launch; no
+    kernel faults) returns EDEVICE, and every later call on that handle returns
+    EDEVICE too; destroying it works, and another handle on the device is unaffected."""
+    wl = W.plain_2d(samples=2000, seed=14)
+    monkeypatch.setenv("PIRRT_FAULT_INJECT", "launch")
+    G = gpu_graph(P)
+    monkeypatch.delenv("PIRRT_FAULT_INJECT")
+    G.insert_rows(wl.batches[0])
+    with pytest.raises(P.PirrtError) as e:
+        G.replan(0, 1, wl.heuristic(), True)
+    assert e.value.code == P.PIRRT_EDEVICE
+    assert "injected" in str(e.value)
+    for call in (lambda: G.replan(0, 1, wl.heuristic(), True), lambda: G.get_policy(),
+                 lambda: G.insert_rows(wl.batches[0]), lambda: G.snapshot_save()):
+        with pytest.raises(P.PirrtError) as e:
+            call()
+        assert e.value.code == P.PIRRT_EDEVICE
+    G.close()
+    run_both(P, wl.batches, {0: (0, 1)}, wl.heuristic, True)
+
+
+def test_injected_allocation_failure_leaves_the_graph_unchanged(P, monkeypatch):
+    """A failed growth of the vertex storage (forced on the host by
+    PIRRT_FAULT_INJECT=alloc) returns ENOMEM with the graph as it was; the same
+    insertion then succeeds and the results equal the oracle's."""
+    wl = W.batched_6d(batches=2, batch=1500, seed=105)
+    monkeypatch.setenv("PIRRT_FAULT_INJECT", "alloc")
+    G = gpu_graph(P)
+    monkeypatch.delenv("PIRRT_FAULT_INJECT")
+    R = O.Graph()
+    b0, b1 = wl.batches
+    with pytest.raises(P.PirrtError) as e:
+        G.insert_rows(b0)
+    assert e.value.code == P.PIRRT_ENOMEM and G.n == 0
+    for b in (b0, b1):
+        G.insert_rows(b)
+        assert R.insert_batch(b) == 0
+    gg, pp, sg = G.replan(0, 1, wl.heuristic(G.n), True)
+    rc, so = R.replan(0, 1, wl.heuristic(G.n), True)
+    st = R.state()
+    assert_same_policy("after ENOMEM", gg, pp, st.g, st.parent)
+    assert_same_stats("after ENOMEM", sg, so)
+
+
 def test_snapshot_restore_repeatable(P):
     wl = W.batched_6d(batches=2, batch=2000, seed=100)
     G = gpu_graph(P)
@@ -369,6 +414,31 @@ def test_level_synchronous_evaluator_agrees(P, monkeypatch):
     run_both(P, wl.batches, {i: (0, 1) for i in range(4)}, wl.heuristic, True)
     b = lattice_batch(40, 0.9, 5)
     run_both(P, [b], {0: (0, 1)}, None, False)
+
+
+@pytest.mark.parametrize("evaluator", ["levels", "walk"])
+def test_repeated_replans_with_a_new_root(P, monkeypatch, evaluator):
+    """Repeated Replans on one graph replay captured loop bodies; a later Replan with
+    another root on the same graph (and the same arguments otherwise) must not replay
+    anything tied to the old root.  Root 0 twice, then root k twice, then root 0
+    again, each against the oracle from the same state."""
+    monkeypatch.setenv("PIRRT_EVALUATE", evaluator)
+    wl = W.batched_6d(batches=1, batch=3000, seed=104)
+    G = gpu_graph(P)
+    R = O.Graph()
+    b = wl.batches[0]
+    G.insert_rows(b)
+    assert R.insert_batch(b) == 0
+    n = G.n
+    h = wl.heuristic(n)
+    k = n // 2
+    for call, (root, goal) in enumerate([(0, 1), (0, 1), (k, 1), (k, 1), (0, 1)]):
+        gg, pp, sg = G.replan(root, goal, h, True)
+        rc, so = R.replan(root, goal, h, True)
+        assert rc == 0
+        st = R.state()
+        assert_same_policy("%s call %d root %d" % (evaluator, call, root), gg, pp, st.g, st.parent)
+        assert_same_stats("%s call %d root %d" % (evaluator, call, root), sg, so)
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])

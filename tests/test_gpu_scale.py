@@ -1,7 +1,10 @@
 """Parity at the full workload sizes: the 6D batched-extension run (100 batches of
 1,000 vertices, Replan after every batch) and the 6D 1,000,000-vertex graph (one
 Replan from the insertion-time policy, then a further 10,000-vertex batch and a
-second Replan), in the same launch configuration the benchmark times."""
+second Replan; the benchmark's timed path of repeated Replans from captured loop
+graphs) and the 512-problem batched set, every problem against the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -77,6 +80,39 @@ def test_plain_6d_1m(P, big):
     print("+10k replan stats", sg, flush=True)
 
 
+def test_plain_6d_1m_timed_path(P, big):
+    """The benchmark's timed path at full size: the 1M-vertex graph on the caller's
+    stream, the autotuner's configuration, then repeated Replans from the restored
+    insertion-time policy into device buffers.  The second call with the same
+    arguments captures the loop bodies as HIP graphs and the third replays them;
+    every call's g (bit for bit), parents and counters must equal the oracle's."""
+    import torch
+    wl = big
+    dev = torch.device("cuda:0")
+    G = gpu_graph(P, device=0)
+    b0 = wl.batches[0]
+    G.insert_rows(b0)
+    G.snapshot_save()
+    n = G.n
+    hh = wl.heuristic(n)
+    h = torch.from_numpy(hh).to(dev)
+    g_out = torch.empty(n, dtype=torch.float32, device=dev)
+    p_out = torch.empty(n, dtype=torch.int32, device=dev)
+    config = G.tune(0, 1, h, True)
+    R = O.Graph()
+    assert R.insert_batch(b0) == 0
+    rc, so = R.replan(0, 1, hh, True)
+    assert rc == 0
+    st = R.state()
+    for call in range(3):
+        G.snapshot_restore()
+        _, _, sg = G.replan(0, 1, h, True, g_out=g_out, parent_out=p_out)
+        tag = "1M call %d (configuration %d)" % (call, config)
+        assert_same_policy(tag, g_out.cpu().numpy(), p_out.cpu().numpy(), st.g, st.parent)
+        assert_same_stats(tag, sg, so)
+    print("1M timed path: configuration %d, %d iterations" % (config, so["iterations"]), flush=True)
+
+
 def test_truncated_6d_1m(P, big):
     """The truncated Evaluate at full size: the Replan, the +10k batch inserted on top of
     the stale g it leaves (the insertion-time policy compared too), the second Replan."""
@@ -100,13 +136,26 @@ def test_truncated_6d_1m(P, big):
         print("truncated replan %d stats" % i, sg, flush=True)
 
 
+def _oracle_problem(rows, h, root, goal):
+    """One problem replanned by the oracle on rows given as (row_ptr, col, cost)."""
+    orc = O.Graph()
+    assert orc.insert(*rows) == 0
+    rc, so = orc.replan(root, goal, h, True)
+    st = orc.state()
+    return rc, so, st.g, st.parent
+
+
 def test_multi_graph_512(P):
     """The 512-problem multi-graph set (28.6M vertices) built on the device and
-    replanned by one batched call, as the benchmark's multi workload does.  Eight
-    problems of different dimensions are compared with the oracle on its own build
-    (points, rows and Replan); every problem is checked for a consistent, rooted
-    policy (g(v) = g(parent) + pcost bit for bit, g(root) = 0) and for stopping."""
+    replanned by one batched call, as the benchmark's multi workload does.  Every
+    problem is compared with the oracle run on that problem alone: the oracle reads
+    the problem's rows and heuristic as the device built them (the device builder's
+    rows and heuristic equal the exploration oracle's bit for bit, which
+    test_gpu_rrg.py checks), and the g bits, parents and counters must be equal.
+    Eight problems of different dimensions are also rebuilt from scratch by the
+    exploration oracle (points, rows, heuristic) to tie the chain end to end."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import rrg as RR
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
@@ -126,6 +175,36 @@ def test_multi_graph_512(P):
     g, parent = g.cpu().numpy(), parent.cpu().numpy()
     assert all(s["rc"] == 0 for s in stats)
     off = B.offsets
+    hh = h.cpu().numpy()
+    # every problem against the oracle, several problems at a time on the host's
+    # cores (the oracle runs in C and releases the interpreter lock)
+    try:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    except (AttributeError, OSError):
+        workers = max(1, min(16, os.cpu_count() or 1))
+    order = sorted(range(512), key=lambda i: -specs[i].n)  # largest first: better packing
+    done = 0
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        pending = []
+
+        def drain(limit):
+            nonlocal done
+            while len(pending) > limit:
+                i, fut = pending.pop(0)
+                rc, so, go, po = fut.result()
+                assert rc == 0, i
+                tag = "problem %d (d=%d n=%d)" % (i, specs[i].d, specs[i].n)
+                assert_same_policy(tag, g[off[i]:off[i + 1]], parent[off[i]:off[i + 1]], go, po)
+                assert_same_stats(tag, stats[i], so)
+                done += 1
+
+        for i in order:
+            rows = rrgs[i].rows(0, specs[i].radius)
+            pending.append((i, ex.submit(_oracle_problem, rows, hh[off[i]:off[i + 1]], 0, 1)))
+            drain(2 * workers)
+        drain(0)
+    assert done == 512
+    print("all 512 problems equal the oracle (%d host threads)" % workers, flush=True)
     # invariants on every problem (device arithmetic: binary32 adds, no contraction)
     gd, pd, cd = B.get_policy(device=dev)
     base = torch.from_numpy(np.repeat(off[:-1], np.diff(off))).to(dev)
@@ -155,4 +234,4 @@ def test_multi_graph_512(P):
         assert_same_policy("problem %d (d=%d n=%d)" % (i, sp.d, sp.n), g[off[i]:off[i + 1]],
                            parent[off[i]:off[i + 1]], st.g, st.parent)
         assert_same_stats("problem %d" % i, stats[i], so)
-    print("compared problems %s with the oracle" % [sp.index for sp in picked], flush=True)
+    print("compared problems %s with the oracle's own build" % [sp.index for sp in picked], flush=True)
