@@ -385,6 +385,26 @@ int pirrt_mlp_set_params(pirrt_mlp* net, const float* params, int mem_kind);
 int pirrt_mlp_get_params(pirrt_mlp* net, float* params, int mem_kind);
 /* logits: float[B]. */
 int pirrt_mlp_forward(pirrt_mlp* net, int32_t B, const float* x, float* logits, int mem_kind);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the forward pass of
+ * pirrt_mlp_forward with the same kernels and the same logits bit for bit, with its
+ * staged features and hidden activations in a fixed array inside the library
+ * (12.5 MiB per GPU, allocated with the code object and held until the process ends)
+ * instead of the handle's buffers.  It calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   x: device float[B * in_dim] (row-major features); logits: device float[B].
+ *   1 <= B <= PIRRT_MLP_NOALLOC_MAX_BATCH (any max_batch of the handle); a larger B,
+ *   or a NULL pointer, returns PIRRT_EINVAL with nothing enqueued.
+ * Asynchronous: the work is enqueued on the handle's stream and the call returns
+ * without waiting (it makes no stream or device synchronisation, so it may be
+ * captured); logits are valid once the stream reaches that point.  Every call on a
+ * GPU shares that GPU's array: calls on one stream are ordered, but calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and may
+ * return wrong logits.  EDEVICE if the array's device address cannot be obtained.
+ */
+#define PIRRT_MLP_NOALLOC_MAX_BATCH 8192
+int pirrt_mlp_forward_noalloc(pirrt_mlp* net, int32_t B, const float* x, float* logits);
 /* Gradient of the mean loss into grads (parameter layout, nullable) and the loss
    into *loss (host, nullable); parameters unchanged. */
 int pirrt_mlp_gradients(pirrt_mlp* net, int32_t B, const float* x, const float* y, float* grads, float* loss,

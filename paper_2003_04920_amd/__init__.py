@@ -4,4 +4,4 @@ C ABI (include/pirrt.h), after "GPU Parallelization of Policy Iteration RRT#"
 from .binding import (Graph, Batch, Rrg, Mlp, PirrtError, load, pirrt_config, pirrt_stats, LIB_PATH, EXPORTS,  # noqa: F401
                       PIRRT_OK, PIRRT_EINVAL, PIRRT_ENOMEM, PIRRT_EDEVICE, PIRRT_ENOTCONVERGED,
                       PIRRT_MEM_HOST, PIRRT_MEM_DEVICE, PIRRT_NO_PRUNE, PIRRT_TIMING, PIRRT_LOOKAHEAD,
-                      PIRRT_TRUNCATED)
+                      PIRRT_TRUNCATED, PIRRT_MLP_NOALLOC_MAX_BATCH)

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libpirrt.so")
 PIRRT_OK, PIRRT_EINVAL, PIRRT_ENOMEM, PIRRT_EDEVICE, PIRRT_ENOTCONVERGED = 0, -1, -2, -3, -4
 PIRRT_MEM_HOST, PIRRT_MEM_DEVICE = 0, 1
 PIRRT_NO_PRUNE, PIRRT_TIMING, PIRRT_LOOKAHEAD, PIRRT_TRUNCATED = 1, 2, 4, 8
+PIRRT_MLP_NOALLOC_MAX_BATCH = 8192
 
 EXPORTS = [
     "pirrt_config_init", "pirrt_graph_create", "pirrt_graph_destroy", "pirrt_insert_batch", "pirrt_replan",
@@ -35,6 +36,7 @@ EXPORTS = [
     "pirrt_mlp_num_params", "pirrt_mlp_create", "pirrt_mlp_destroy", "pirrt_mlp_set_params", "pirrt_mlp_get_params",
     "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
     "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned", "pirrt_tune", "pirrt_batch_tune",
+    "pirrt_mlp_forward_noalloc",
 ]
 
 
@@ -131,6 +133,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_mlp_set_params": (cint, [vp, vp, cint]),
         "pirrt_mlp_get_params": (cint, [vp, vp, cint]),
         "pirrt_mlp_forward": (cint, [vp, i32, vp, vp, cint]),
+        "pirrt_mlp_forward_noalloc": (cint, [vp, i32, vp, vp]),
         "pirrt_mlp_gradients": (cint, [vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
         "pirrt_mlp_train_step": (cint, [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_float), cint]),
         "pirrt_mlp_last_error": (ctypes.c_char_p, [vp]),
@@ -610,6 +613,15 @@ class Mlp:
                 out = np.empty(B, np.float32)
         self._check(self._lib.pirrt_mlp_forward(self._h, B, _ptr(x), _ptr(out), _mem_kind(x, out)))
         return out
+
+    def forward_noalloc(self, x, out):
+        """pirrt_mlp_forward_noalloc: device tensors only; enqueued on the handle's
+        stream without waiting (the caller synchronises)."""
+        x = _check_dtype(x, np.float32, "float32")
+        out = _check_dtype(out, np.float32, "float32")
+        if not (_is_device(x) and _is_device(out)):
+            raise ValueError("forward_noalloc takes device tensors")
+        return self._check(self._lib.pirrt_mlp_forward_noalloc(self._h, int(x.shape[0]), _ptr(x), _ptr(out)))
 
     def gradients(self, x, y):
         x = _check_dtype(x, np.float32, "float32")

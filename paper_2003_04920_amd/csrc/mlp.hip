@@ -15,12 +15,15 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
 #include "pirrt.h"
 
 using namespace pirrt;
+
+static __device__ __align__(256) uint16_t scratch[(PIRRT_MLP_NOALLOC_MAX_BATCH) * (288 + 2 * 256)];
 
 namespace {
 
@@ -34,6 +37,20 @@ constexpr int64_t kOffW3 = kOffB2 + kHidden;
 constexpr int64_t kOffB3 = kOffW3 + kHidden;
 constexpr int64_t kNumParams = kOffB3 + 1;
 constexpr int kThreads = 256;
+
+// Scratch of pirrt_mlp_forward_noalloc: the staged bf16 features X [kNoAllocRows x kIn]
+// followed by the bf16 activations A1 and A2 [kNoAllocRows x kHidden each], 12.5 MiB.
+// Each GPU the library runs on holds its own copy until the process ends.  Host code
+// never passes this name to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current GPU (noalloc_scratch below).
+constexpr int32_t kNoAllocRows = PIRRT_MLP_NOALLOC_MAX_BATCH;  // a multiple of 64
+constexpr int64_t kScratchX = 0;
+constexpr int64_t kScratchA1 = kScratchX + (int64_t)kNoAllocRows * kIn;
+constexpr int64_t kScratchA2 = kScratchA1 + (int64_t)kNoAllocRows * kHidden;
+constexpr int64_t kScratchElems = kScratchA2 + (int64_t)kNoAllocRows * kHidden;
+static_assert(kNoAllocRows % 64 == 0, "rows are padded to 64");
+static_assert(sizeof(scratch) == sizeof(uint16_t) * (size_t)kScratchElems, "scratch layout");
+static_assert((kScratchA1 * 2) % 256 == 0 && (kScratchA2 * 2) % 256 == 0, "each part stays 256-byte aligned");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -135,6 +152,7 @@ __global__ void k_features(int32_t B, int32_t Bp, int32_t in_dim, const float* _
 
 // z = A2 w3 + b3 per row (one thread per row, k ascending); with labels also
 // dz = (sigmoid(z) - y) / B and the workgroup's loss sum (rows in order) in lpart.
+// Without labels only rows b < B of z are written (z may be the caller's logits).
 __global__ void __launch_bounds__(kThreads) k_layer3(int32_t B, int32_t Bp, const uint16_t* __restrict__ A2,
                                                      const uint16_t* __restrict__ w3b, const float* __restrict__ P,
                                                      const float* __restrict__ y, float* __restrict__ z,
@@ -158,7 +176,7 @@ __global__ void __launch_bounds__(kThreads) k_layer3(int32_t B, int32_t Bp, cons
       }
     }
     const float zb = s + P[kOffB3];
-    z[b] = zb;
+    if (y || b < B) z[b] = zb;  // a forward pass writes the B logits only
     if (y) {
       if (b < B) {
         const float yb = y[b];
@@ -423,21 +441,23 @@ int stage_inputs(pirrt_mlp* N, int32_t B, int32_t Bp, const float* x, const floa
   return PIRRT_OK;
 }
 
-void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z) {
+// X [Bp x kIn] -> A1 -> A2 ([Bp x kHidden] each, bf16); keep_z also stores the fp32
+// pre-activations in the handle's Z1 / Z2 for the backward pass.
+void enqueue_forward(pirrt_mlp* N, int32_t Bp, bool keep_z, const uint16_t* X, uint16_t* A1, uint16_t* A2) {
   hipStream_t s = N->stream;
   // element (k, n) of W1 is W1t[n * kIn + k]: contiguous in k
-  GemmArgs g1{Bp, kHidden, kIn, N->X, kIn, 1, N->W1t, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
-              N->A1, kIn};
+  GemmArgs g1{Bp, kHidden, kIn, X, kIn, 1, N->W1t, 1, kIn, N->P + kOffB1, nullptr, keep_z ? N->Z1 : nullptr,
+              A1, kIn};
   launch_gemm(g1, true, true, kEpiFwd, s);
-  GemmArgs g2{Bp, kHidden, kHidden, N->A1, kHidden, 1, N->W2t, 1, kHidden, N->P + kOffB2, nullptr,
-              keep_z ? N->Z2 : nullptr, N->A2, kHidden};
+  GemmArgs g2{Bp, kHidden, kHidden, A1, kHidden, 1, N->W2t, 1, kHidden, N->P + kOffB2, nullptr,
+              keep_z ? N->Z2 : nullptr, A2, kHidden};
   launch_gemm(g2, true, true, kEpiFwd, s);
 }
 
 // Forward + loss + gradients into N->G (the loss lands in N->dloss).
 int enqueue_gradients(pirrt_mlp* N, int32_t B, int32_t Bp, const float* yd) {
   hipStream_t s = N->stream;
-  enqueue_forward(N, Bp, true);
+  enqueue_forward(N, Bp, true, N->X, N->A1, N->A2);
   const unsigned nb3 = nblocks(Bp);
   hipLaunchKernelGGL(k_layer3, dim3(nb3), dim3(kThreads), 0, s, B, Bp, N->A2, N->w3b, N->P, yd, N->z, N->dz,
                      N->part);
@@ -470,6 +490,27 @@ int check_batch(pirrt_mlp* N, int32_t B, const float* x, int mem_kind) {
 
 inline int32_t padded(int32_t B) { return (B + 63) / 64 * 64; }
 
+// Device address of `scratch` on each GPU, looked up once per device with that device
+// current (at pirrt_mlp_create, or at the first no-allocation call on the device).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint16_t* g_scratch_dev[kMaxDevices] = {};
+
+// dev must be the current device.  Returns nullptr when the lookup fails.
+uint16_t* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_dev[dev] = static_cast<uint16_t*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -497,6 +538,7 @@ int pirrt_mlp_create(pirrt_mlp** out, const pirrt_mlp_config* cfg) {
     return PIRRT_EDEVICE;
   }
   N->device = dev;
+  (void)noalloc_scratch(dev);  // set-up of the no-allocation forward on this device
   N->stream = (hipStream_t)cfg->hip_stream;
   N->in_dim = cfg->in_dim;
   N->max_batch = cfg->max_batch;
@@ -591,13 +633,33 @@ int pirrt_mlp_forward(pirrt_mlp* N, int32_t B, const float* x, float* logits, in
   const int32_t Bp = padded(B);
   const float* yd = nullptr;
   if ((rc = stage_inputs(N, B, Bp, x, nullptr, mem_kind, &yd))) return rc;
-  enqueue_forward(N, Bp, false);
+  enqueue_forward(N, Bp, false, N->X, N->A1, N->A2);
   hipLaunchKernelGGL(k_layer3, dim3(nblocks(Bp)), dim3(kThreads), 0, N->stream, B, Bp, N->A2, N->w3b, N->P, nullptr,
                      N->z, nullptr, nullptr);
   MHIP(N, hipGetLastError());
   MHIP(N, hipMemcpyAsync(logits, N->z, sizeof(float) * (size_t)B,
                          mem_kind == PIRRT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, N->stream));
   MHIP(N, hipStreamSynchronize(N->stream));
+  return PIRRT_OK;
+}
+
+int pirrt_mlp_forward_noalloc(pirrt_mlp* N, int32_t B, const float* x, float* logits) {
+  int rc = mguard(N);
+  if (rc) return rc;
+  if (B < 1 || B > kNoAllocRows) return mfail(N, PIRRT_EINVAL, "batch size outside 1..PIRRT_MLP_NOALLOC_MAX_BATCH");
+  if (!x || !logits) return mfail(N, PIRRT_EINVAL, "x or logits is NULL");
+  uint16_t* base = noalloc_scratch(N->device);
+  if (!base) return mfail(N, PIRRT_EDEVICE, "device address of the no-allocation scratch not available");
+  const int32_t Bp = padded(B);
+  hipStream_t s = N->stream;
+  uint16_t* X = base + kScratchX;
+  uint16_t* A1 = base + kScratchA1;
+  uint16_t* A2 = base + kScratchA2;
+  hipLaunchKernelGGL(k_features, dim3(nblocks((int64_t)Bp * kIn)), dim3(kThreads), 0, s, B, Bp, N->in_dim, x, X);
+  enqueue_forward(N, Bp, false, X, A1, A2);
+  hipLaunchKernelGGL(k_layer3, dim3(nblocks(Bp)), dim3(kThreads), 0, s, B, Bp, A2, N->w3b, N->P, nullptr, logits,
+                     nullptr, nullptr);
+  MHIP(N, hipGetLastError());
   return PIRRT_OK;
 }
 
