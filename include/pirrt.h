@@ -95,6 +95,17 @@ typedef struct {
   void* hip_stream;        /* hipStream_t for all device work; NULL = the null stream */
   int32_t max_iters;       /* Replan iteration cap; 0 = 4n + 8 */
   int32_t device;          /* HIP device ordinal; -1 = the device current at create */
+  /* Optional device-memory callbacks (both or neither; NULL = hipMalloc / hipFree),
+     e.g. a framework's caching allocator.  alloc(bytes, alloc_ctx) returns device
+     memory on the handle's device, aligned to at least 256 bytes, or NULL (the call
+     then fails with ENOMEM and the handle is unchanged); free(ptr, alloc_ctx) returns
+     a block alloc gave.  Both are called on the thread that calls the library, with
+     the handle's device current, at create, when storage grows and at destroy; the
+     memory is used on hip_stream, and every block is freed before destroy returns.
+     The callbacks must not call back into this handle. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } pirrt_config;
 
 typedef struct {
@@ -117,7 +128,8 @@ typedef struct {
   int32_t reserved;
 } pirrt_stats;
 
-/* Fills *cfg with defaults (capacities 0, NULL stream, cap 0, device -1). */
+/* Fills *cfg with defaults (capacities 0, NULL stream, cap 0, device -1, no allocator
+   callbacks). */
 int pirrt_config_init(pirrt_config* cfg);
 
 /* Creates an empty graph (no vertices) on the configured device.  cfg may be NULL
@@ -200,6 +212,29 @@ int pirrt_snapshot_restore(pirrt_graph* g);
    (any may be NULL).  The order of entries inside a row is unspecified. */
 int pirrt_get_adjacency(pirrt_graph* g, int64_t* ptr, int32_t* nbr, float* cost, int mem_kind);
 
+/*
+ * Checkpoint and resume of a graph handle (the state Replan of Alg. 2 works on: the
+ * graph with its cached costs, Sec. IV-A, and the policy with its g) through caller
+ * memory.  The blob is host memory the caller owns: a 48-byte header, the graph as
+ * forward rows (row_ptr int64[n+1], then each vertex's lower-id neighbours col
+ * int32[m] with their costs float[m], m = nnz / 2, the pirrt_insert_batch format),
+ * then g float[n], parent int32[n] and pcost float[n] in caller ids.
+ *   pirrt_state_size: bytes of the blob for the handle's current state (-1 for NULL,
+ *     a poisoned handle or a batch's graph).
+ *   pirrt_state_save: writes the blob into `blob` (size >= pirrt_state_size, else
+ *     EINVAL); the handle is unchanged.
+ *   pirrt_state_restore: reads a blob of pirrt_state_save.  Into an empty handle it
+ *     inserts the saved graph and sets the saved policy, so the handle then holds
+ *     exactly the saved graph and policy; into a handle holding the same vertex and
+ *     edge counts it replaces the policy only (the caller vouches that the graph is
+ *     the saved one).  A blob that is not one, is truncated, or holds a bad policy
+ *     or rows, or a handle holding another graph, gives EINVAL with the handle
+ *     unchanged.  Root marks are not saved: parents of roots read -1 either way.
+ */
+int64_t pirrt_state_size(pirrt_graph* g);
+int pirrt_state_save(pirrt_graph* g, void* blob, int64_t size);
+int pirrt_state_restore(pirrt_graph* g, const void* blob, int64_t size);
+
 int64_t pirrt_num_vertices(const pirrt_graph* g);
 int64_t pirrt_num_edges(const pirrt_graph* g); /* directed entries = 2 x undirected */
 
@@ -240,6 +275,26 @@ int pirrt_batch_destroy(pirrt_batch* b);
  */
 int pirrt_batch_add_problem(pirrt_batch* b, int32_t n, const int64_t* row_ptr, const int32_t* col,
                             const float* cost, int mem_kind, int32_t* index);
+
+/*
+ * Grows problems of the batch: Alg. 3's exploration step for many planners at once
+ * (each extends its own graph by a batch of vertices, Sec. III Extend), before one
+ * pirrt_batch_replan replans them all.  For k in [0, count), n_new[k] >= 0 vertices
+ * are appended to problem problems[k] (host arrays; indices distinct).  The rows of
+ * all blocks are concatenated in k order: row_ptr int64[T + 1] (T = sum of n_new),
+ * col int32 / cost float indexed by it, at mem_kind.  Row i of block k is the new
+ * local vertex n_p + i of its problem p (n_p = p's vertex count before the call) and
+ * lists its neighbours j < n_p + i in p's local ids, each undirected edge once, as
+ * in pirrt_insert_batch.  Each new vertex takes the insertion-time policy of
+ * pirrt_insert_batch.  Afterwards problem p holds n_p + n_new vertices with local ids
+ * unchanged for the old ones, and the per-vertex offsets of the problems move
+ * (pirrt_batch_problem_offset gives the new ones).  A snapshot taken before the call
+ * is dropped.  Errors: EINVAL (bad count, index, repeated problem, rows or costs;
+ * the batch unchanged), ENOMEM, EDEVICE.  Work: one pass over the batch's adjacency
+ * plus the new rows.
+ */
+int pirrt_batch_insert(pirrt_batch* b, int32_t count, const int32_t* problems, const int32_t* n_new,
+                       const int64_t* row_ptr, const int32_t* col, const float* cost, int mem_kind);
 
 int32_t pirrt_batch_num_problems(const pirrt_batch* b);
 int64_t pirrt_batch_num_vertices(const pirrt_batch* b); /* all problems together */

@@ -36,13 +36,43 @@ EXPORTS = [
     "pirrt_mlp_num_params", "pirrt_mlp_create", "pirrt_mlp_destroy", "pirrt_mlp_set_params", "pirrt_mlp_get_params",
     "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
     "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned", "pirrt_tune", "pirrt_batch_tune",
-    "pirrt_mlp_forward_noalloc",
+    "pirrt_mlp_forward_noalloc", "pirrt_batch_insert", "pirrt_state_size", "pirrt_state_save",
+    "pirrt_state_restore",
 ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class pirrt_config(ctypes.Structure):
     _fields_ = [("vertex_capacity", ctypes.c_int64), ("edge_capacity", ctypes.c_int64),
-                ("hip_stream", ctypes.c_void_p), ("max_iters", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("hip_stream", ctypes.c_void_p), ("max_iters", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """Allocator callbacks of pirrt_config that take device memory from torch's
+    caching allocator on a given device and stream (marshalling only: the library
+    calls them when its storage grows)."""
+
+    def __init__(self, device: int, stream: Optional[int]):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device < 0 else device
+        self.stream = stream or 0
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except RuntimeError:
+            return None
+
+    def _free(self, ptr, ctx):
+        if ptr:
+            self._torch.cuda.caching_allocator_delete(ptr)
 
 
 class pirrt_rrg_config(ctypes.Structure):
@@ -100,6 +130,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_snapshot_save": (cint, [vp]),
         "pirrt_snapshot_restore": (cint, [vp]),
         "pirrt_get_adjacency": (cint, [vp, vp, vp, vp, cint]),
+        "pirrt_state_size": (i64, [vp]),
+        "pirrt_state_save": (cint, [vp, vp, i64]),
+        "pirrt_state_restore": (cint, [vp, vp, i64]),
         "pirrt_num_vertices": (i64, [vp]),
         "pirrt_num_edges": (i64, [vp]),
         "pirrt_last_error": (ctypes.c_char_p, [vp]),
@@ -107,6 +140,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_batch_create": (cint, [ctypes.POINTER(vp), ctypes.POINTER(pirrt_config)]),
         "pirrt_batch_destroy": (cint, [vp]),
         "pirrt_batch_add_problem": (cint, [vp, i32, vp, vp, vp, cint, ctypes.POINTER(i32)]),
+        "pirrt_batch_insert": (cint, [vp, i32, vp, vp, vp, vp, vp, cint]),
         "pirrt_batch_num_problems": (i32, [vp]),
         "pirrt_batch_num_vertices": (i64, [vp]),
         "pirrt_batch_num_edges": (i64, [vp]),
@@ -193,7 +227,8 @@ class Graph:
     ``torch.cuda.current_stream().cuda_stream``) or None for the null stream."""
 
     def __init__(self, stream: Optional[int] = None, device: int = -1, max_iters: int = 0,
-                 vertex_capacity: int = 0, edge_capacity: int = 0, lib: Optional[ctypes.CDLL] = None):
+                 vertex_capacity: int = 0, edge_capacity: int = 0, lib: Optional[ctypes.CDLL] = None,
+                 torch_allocator: bool = False):
         self._lib = lib or load()
         cfg = pirrt_config()
         self._lib.pirrt_config_init(ctypes.byref(cfg))
@@ -202,6 +237,10 @@ class Graph:
         cfg.hip_stream = stream or None
         cfg.max_iters = max_iters
         cfg.device = device
+        self._alloc = TorchAllocator(device, stream) if torch_allocator else None
+        if self._alloc is not None:
+            cfg.alloc = self._alloc.alloc
+            cfg.free = self._alloc.free
         h = ctypes.c_void_p()
         rc = self._lib.pirrt_graph_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != PIRRT_OK:
@@ -311,6 +350,22 @@ class Graph:
     def snapshot_restore(self) -> int:
         return self._check(self._lib.pirrt_snapshot_restore(self._h))
 
+    def state_size(self) -> int:
+        return int(self._lib.pirrt_state_size(self._h))
+
+    def state_save(self) -> np.ndarray:
+        """pirrt_state_save into a new host byte array."""
+        size = self.state_size()
+        if size < 0:
+            raise PirrtError(PIRRT_EINVAL, "no state blob for this handle")
+        blob = np.empty(size, np.uint8)
+        self._check(self._lib.pirrt_state_save(self._h, _ptr(blob), size))
+        return blob
+
+    def state_restore(self, blob) -> int:
+        blob = np.ascontiguousarray(blob, np.uint8)
+        return self._check(self._lib.pirrt_state_restore(self._h, _ptr(blob), int(blob.size)))
+
     def adjacency(self):
         ptr = np.empty(self.n + 1, np.int64)
         nbr = np.empty(max(self.nnz, 1), np.int32)
@@ -382,6 +437,24 @@ class Batch:
                                                kind, ctypes.byref(idx))
         self._check(rc)
         return int(idx.value)
+
+    def problem_offset(self, problem: int) -> int:
+        return int(self._lib.pirrt_batch_problem_offset(self._h, int(problem)))
+
+    def insert(self, problems, n_new, row_ptr, col, cost) -> int:
+        """pirrt_batch_insert: grows problems[k] by n_new[k] vertices; the rows of all
+        blocks are concatenated in that order, in each problem's local ids."""
+        problems = np.ascontiguousarray(problems, np.int32)
+        n_new = np.ascontiguousarray(n_new, np.int32)
+        if problems.shape != n_new.shape or problems.ndim != 1:
+            raise ValueError("problems and n_new need one entry per block")
+        row_ptr = _check_dtype(row_ptr, np.int64, "int64")
+        col = _check_dtype(col, np.int32, "int32")
+        cost = _check_dtype(cost, np.float32, "float32")
+        kind = _mem_kind(row_ptr, col, cost)
+        rc = self._lib.pirrt_batch_insert(self._h, int(problems.size), _ptr(problems), _ptr(n_new), _ptr(row_ptr),
+                                          _ptr(col) if len(col) else None, _ptr(cost) if len(cost) else None, kind)
+        return self._check(rc)
 
     def replan(self, roots, goals, h=None, prune: bool = True, timing: bool = False, g_out=None,
                parent_out=None, allow_not_converged: bool = False, lookahead: bool = False):

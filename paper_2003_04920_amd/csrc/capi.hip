@@ -68,7 +68,16 @@ struct LoopKey {
 
 }  // namespace
 
+// Device memory source of a handle: the caller's allocator callbacks (called with the
+// handle's device current) or hipMalloc / hipFree.
+struct DevAlloc {
+  void* (*alloc)(size_t bytes, void* ctx) = nullptr;
+  void (*free)(void* ptr, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+
 struct pirrt_graph {
+  DevAlloc A;
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture loop bodies
@@ -123,6 +132,8 @@ struct pirrt_graph {
   std::vector<int64_t> pbase{0, 0};
   int32_t* prob = nullptr;  // problem of each slot (used by batches only)
   int64_t* dbase = nullptr;  // device copy of pbase
+  char* dgrow = nullptr;     // growing problems: block table and the new bases
+  int64_t dgrow_cap = 0;     // bytes
   int64_t dbase_cap = 0;
   // per-problem Replan state
   ProblemState* ps = nullptr;
@@ -207,21 +218,34 @@ int fail_device(pirrt_graph* G, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return fail_device(G, e_, #expr); \
   } while (0)
 
-template <class T>
-bool dalloc(T** p, int64_t count) {
-  *p = nullptr;
-  if (count <= 0) count = 1;
-  if (hipMalloc((void**)p, sizeof(T) * (size_t)count) != hipSuccess) {
+void* raw_alloc(const DevAlloc& A, size_t bytes) {
+  if (A.alloc) return A.alloc(bytes, A.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    *p = nullptr;
-    return false;
+    return nullptr;
   }
-  return true;
+  return p;
+}
+
+void raw_free(const DevAlloc& A, void* p) {
+  if (!p) return;
+  if (A.free)
+    A.free(p, A.ctx);
+  else
+    (void)hipFree(p);
 }
 
 template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+bool dalloc(const DevAlloc& A, T** p, int64_t count) {
+  if (count <= 0) count = 1;
+  *p = static_cast<T*>(raw_alloc(A, sizeof(T) * (size_t)count));
+  return *p != nullptr;
+}
+
+template <class T>
+void dfree(const DevAlloc& A, T*& p) {
+  raw_free(A, p);
   p = nullptr;
 }
 
@@ -240,12 +264,9 @@ hipMemcpyKind in_kind(int mem_kind) {
 int ensure_scan(pirrt_graph* G, int64_t n) {
   size_t need = scan_scratch_bytes(n);
   if (need <= G->scan_bytes) return PIRRT_OK;
-  void* p = nullptr;
-  if (hipMalloc(&p, need) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(G, PIRRT_ENOMEM, "device allocation of scan scratch failed");
-  }
-  if (G->scan_scratch) (void)hipFree(G->scan_scratch);
+  void* p = raw_alloc(G->A, need);
+  if (!p) return fail(G, PIRRT_ENOMEM, "device allocation of scan scratch failed");
+  raw_free(G->A, G->scan_scratch);
   G->scan_scratch = p;
   G->scan_bytes = need;
   return PIRRT_OK;
@@ -260,11 +281,11 @@ void drop_loops(pirrt_graph* G) {
 }
 
 void free_vertex_arrays(pirrt_graph* G) {
-  dfree(G->rp); dfree(G->rp2); dfree(G->g); dfree(G->parent); dfree(G->pcost); dfree(G->child_cnt);
-  dfree(G->child_ptr); dfree(G->child); dfree(G->fr0); dfree(G->fr1); dfree(G->lvl); dfree(G->stamp);
-  dfree(G->add); dfree(G->deg); dfree(G->pending); dfree(G->hbuf); dfree(G->ext_of); dfree(G->slot_of);
-  dfree(G->g2); dfree(G->parent2); dfree(G->pcost2); dfree(G->ext2); dfree(G->word); dfree(G->prob);
-  dfree(G->dlist); dfree(G->tiles);
+  dfree(G->A, G->rp); dfree(G->A, G->rp2); dfree(G->A, G->g); dfree(G->A, G->parent); dfree(G->A, G->pcost); dfree(G->A, G->child_cnt);
+  dfree(G->A, G->child_ptr); dfree(G->A, G->child); dfree(G->A, G->fr0); dfree(G->A, G->fr1); dfree(G->A, G->lvl); dfree(G->A, G->stamp);
+  dfree(G->A, G->add); dfree(G->A, G->deg); dfree(G->A, G->pending); dfree(G->A, G->hbuf); dfree(G->A, G->ext_of); dfree(G->A, G->slot_of);
+  dfree(G->A, G->g2); dfree(G->A, G->parent2); dfree(G->A, G->pcost2); dfree(G->A, G->ext2); dfree(G->A, G->word); dfree(G->A, G->prob);
+  dfree(G->A, G->dlist); dfree(G->A, G->tiles);
 }
 
 void forget_vertex_arrays(pirrt_graph* T) {
@@ -290,14 +311,15 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   if (cap < need) cap = need;
   if (cap < kMinVertexCap) cap = kMinVertexCap;
   pirrt_graph T;  // holds the new arrays until all allocations succeeded
-  bool ok = dalloc(&T.rp, cap + 1) && dalloc(&T.rp2, cap + 1) && dalloc(&T.g, cap) && dalloc(&T.parent, cap) &&
-            dalloc(&T.pcost, cap) && dalloc(&T.child_cnt, cap) && dalloc(&T.child_ptr, cap + 1) &&
-            dalloc(&T.child, cap) && dalloc(&T.fr0, cap) && dalloc(&T.fr1, cap) &&
-            dalloc(&T.lvl, cap + kMaxMidLaunches + 8) && dalloc(&T.stamp, cap) && dalloc(&T.add, cap) &&
-            dalloc(&T.deg, cap) && dalloc(&T.pending, cap) && dalloc(&T.hbuf, cap) && dalloc(&T.ext_of, cap) &&
-            dalloc(&T.slot_of, cap) && dalloc(&T.g2, cap) && dalloc(&T.parent2, cap) && dalloc(&T.pcost2, cap) &&
-            dalloc(&T.ext2, cap) && dalloc(&T.word, cap) && dalloc(&T.prob, cap) && dalloc(&T.dlist, cap) &&
-            dalloc(&T.tiles, cap / kTileSlots + 2);
+  T.A = G->A;
+  bool ok = dalloc(G->A, &T.rp, cap + 1) && dalloc(G->A, &T.rp2, cap + 1) && dalloc(G->A, &T.g, cap) && dalloc(G->A, &T.parent, cap) &&
+            dalloc(G->A, &T.pcost, cap) && dalloc(G->A, &T.child_cnt, cap) && dalloc(G->A, &T.child_ptr, cap + 1) &&
+            dalloc(G->A, &T.child, cap) && dalloc(G->A, &T.fr0, cap) && dalloc(G->A, &T.fr1, cap) &&
+            dalloc(G->A, &T.lvl, cap + kMaxMidLaunches + 8) && dalloc(G->A, &T.stamp, cap) && dalloc(G->A, &T.add, cap) &&
+            dalloc(G->A, &T.deg, cap) && dalloc(G->A, &T.pending, cap) && dalloc(G->A, &T.hbuf, cap) && dalloc(G->A, &T.ext_of, cap) &&
+            dalloc(G->A, &T.slot_of, cap) && dalloc(G->A, &T.g2, cap) && dalloc(G->A, &T.parent2, cap) && dalloc(G->A, &T.pcost2, cap) &&
+            dalloc(G->A, &T.ext2, cap) && dalloc(G->A, &T.word, cap) && dalloc(G->A, &T.prob, cap) && dalloc(G->A, &T.dlist, cap) &&
+            dalloc(G->A, &T.tiles, cap / kTileSlots + 2);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -341,20 +363,20 @@ int ensure_pcap(pirrt_graph* G, int64_t need) {
   int32_t* roots = nullptr;
   ProblemState* hps = nullptr;
   int32_t* pst = nullptr;
-  bool ok = dalloc(&ps, cap) && dalloc(&ctr, cap * kCounterSlots) && dalloc(&scr, cap) && dalloc(&roots, cap) &&
-            dalloc(&pst, cap);
+  bool ok = dalloc(G->A, &ps, cap) && dalloc(G->A, &ctr, cap * kCounterSlots) && dalloc(G->A, &scr, cap) && dalloc(G->A, &roots, cap) &&
+            dalloc(G->A, &pst, cap);
   if (ok && hipHostMalloc((void**)&hps, sizeof(ProblemState) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     hps = nullptr;
     ok = false;
   }
   if (!ok) {
-    dfree(ps); dfree(ctr); dfree(scr); dfree(roots); dfree(pst);
+    dfree(G->A, ps); dfree(G->A, ctr); dfree(G->A, scr); dfree(G->A, roots); dfree(G->A, pst);
     return fail(G, PIRRT_ENOMEM, "allocation of per-problem state failed");
   }
   if (G->nroots > 0)
     HIP_OR_FAIL(G, hipMemcpy(roots, G->droots, sizeof(int32_t) * (size_t)G->nroots, hipMemcpyDeviceToDevice));
-  dfree(G->ps); dfree(G->ctr); dfree(G->pscratch); dfree(G->droots); dfree(G->pstart);
+  dfree(G->A, G->ps); dfree(G->A, G->ctr); dfree(G->A, G->pscratch); dfree(G->A, G->droots); dfree(G->A, G->pstart);
   if (G->hps) (void)hipHostFree(G->hps);
   G->ps = ps; G->ctr = ctr; G->pscratch = scr; G->droots = roots; G->hps = hps; G->pstart = pst;
   G->pcap = cap;
@@ -367,8 +389,8 @@ int upload_bases(pirrt_graph* G) {
   if (m > G->dbase_cap) {
     int64_t* p = nullptr;
     int64_t cap = m * 2 > 64 ? m * 2 : 64;
-    if (!dalloc(&p, cap)) return fail(G, PIRRT_ENOMEM, "allocation of problem table failed");
-    dfree(G->dbase);
+    if (!dalloc(G->A, &p, cap)) return fail(G, PIRRT_ENOMEM, "allocation of problem table failed");
+    dfree(G->A, G->dbase);
     G->dbase = p;
     G->dbase_cap = cap;
     drop_loops(G);
@@ -387,13 +409,13 @@ int ensure_spare(pirrt_graph* G, int64_t need) {
   if (cap < kMinEdgeCap) cap = kMinEdgeCap;
   int32_t* c = nullptr;
   float* w = nullptr;
-  if (!dalloc(&c, cap + kAdjSlack) || !dalloc(&w, cap + kAdjSlack)) {
-    dfree(c);
-    dfree(w);
+  if (!dalloc(G->A, &c, cap + kAdjSlack) || !dalloc(G->A, &w, cap + kAdjSlack)) {
+    dfree(G->A, c);
+    dfree(G->A, w);
     return fail(G, PIRRT_ENOMEM, "device allocation for adjacency failed");
   }
-  dfree(G->col2);
-  dfree(G->cst2);
+  dfree(G->A, G->col2);
+  dfree(G->A, G->cst2);
   G->col2 = c;
   G->cst2 = w;
   G->ecap2 = cap;
@@ -408,9 +430,9 @@ int ensure_adjacency(pirrt_graph* G, int64_t need) {
   if (cap < kMinEdgeCap) cap = kMinEdgeCap;
   int32_t* c = nullptr;
   float* w = nullptr;
-  if (!dalloc(&c, cap + kAdjSlack) || !dalloc(&w, cap + kAdjSlack)) {
-    dfree(c);
-    dfree(w);
+  if (!dalloc(G->A, &c, cap + kAdjSlack) || !dalloc(G->A, &w, cap + kAdjSlack)) {
+    dfree(G->A, c);
+    dfree(G->A, w);
     return fail(G, PIRRT_ENOMEM, "device allocation for adjacency failed");
   }
   if (G->nnz > 0) {
@@ -418,8 +440,8 @@ int ensure_adjacency(pirrt_graph* G, int64_t need) {
     HIP_OR_FAIL(G, hipMemcpyAsync(w, G->cst, sizeof(float) * (size_t)G->nnz, hipMemcpyDeviceToDevice, G->stream));
   }
   HIP_OR_FAIL(G, hipStreamSynchronize(G->stream));
-  dfree(G->col);
-  dfree(G->cst);
+  dfree(G->A, G->col);
+  dfree(G->A, G->cst);
   G->col = c;
   G->cst = w;
   G->ecap = cap;
@@ -431,8 +453,8 @@ int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
   if (rows + 1 > G->brows_cap) {
     int64_t* p = nullptr;
     int64_t cap = rows + 1 > 1024 ? rows + 1 : 1024;
-    if (!dalloc(&p, cap)) return fail(G, PIRRT_ENOMEM, "device allocation for batch staging failed");
-    dfree(G->brp);
+    if (!dalloc(G->A, &p, cap)) return fail(G, PIRRT_ENOMEM, "device allocation for batch staging failed");
+    dfree(G->A, G->brp);
     G->brp = p;
     G->brows_cap = cap;
   }
@@ -441,15 +463,15 @@ int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
     int32_t* t = nullptr;
     float* w = nullptr;
     int64_t cap = nnz > 4096 ? nnz : 4096;
-    if (!dalloc(&c, cap) || !dalloc(&t, cap) || !dalloc(&w, cap)) {
-      dfree(c);
-      dfree(t);
-      dfree(w);
+    if (!dalloc(G->A, &c, cap) || !dalloc(G->A, &t, cap) || !dalloc(G->A, &w, cap)) {
+      dfree(G->A, c);
+      dfree(G->A, t);
+      dfree(G->A, w);
       return fail(G, PIRRT_ENOMEM, "device allocation for batch staging failed");
     }
-    dfree(G->bcol);
-    dfree(G->bslot);
-    dfree(G->bcost);
+    dfree(G->A, G->bcol);
+    dfree(G->A, G->bslot);
+    dfree(G->A, G->bcost);
     G->bcol = c;
     G->bslot = t;
     G->bcost = w;
@@ -461,15 +483,15 @@ int ensure_staging(pirrt_graph* G, int64_t rows, int64_t nnz) {
 void release_all(pirrt_graph* G) {
   drop_loops(G);
   free_vertex_arrays(G);
-  dfree(G->col); dfree(G->cst); dfree(G->col2); dfree(G->cst2);
-  dfree(G->sg); dfree(G->sparent); dfree(G->spcost);
-  dfree(G->brp); dfree(G->bcol); dfree(G->bslot); dfree(G->bcost);
-  dfree(G->info); dfree(G->dflag); dfree(G->dcount); dfree(G->dhops);
-  dfree(G->ps); dfree(G->ctr); dfree(G->ctl); dfree(G->pscratch); dfree(G->droots); dfree(G->dbase);
-  dfree(G->pstart);
+  dfree(G->A, G->col); dfree(G->A, G->cst); dfree(G->A, G->col2); dfree(G->A, G->cst2);
+  dfree(G->A, G->sg); dfree(G->A, G->sparent); dfree(G->A, G->spcost);
+  dfree(G->A, G->brp); dfree(G->A, G->bcol); dfree(G->A, G->bslot); dfree(G->A, G->bcost);
+  dfree(G->A, G->info); dfree(G->A, G->dflag); dfree(G->A, G->dcount); dfree(G->A, G->dhops);
+  dfree(G->A, G->ps); dfree(G->A, G->ctr); dfree(G->A, G->ctl); dfree(G->A, G->pscratch); dfree(G->A, G->droots); dfree(G->A, G->dbase);
+  dfree(G->A, G->pstart); dfree(G->A, G->dgrow);
   if (G->hps) (void)hipHostFree(G->hps);
   G->hps = nullptr;
-  if (G->scan_scratch) (void)hipFree(G->scan_scratch);
+  raw_free(G->A, G->scan_scratch);
   G->scan_scratch = nullptr;
   if (G->host) (void)hipHostFree(G->host);
   G->host = nullptr;
@@ -629,6 +651,9 @@ int renumber(pirrt_graph* G) {
   std::swap(G->parent, G->parent2);
   std::swap(G->pcost, G->pcost2);
   std::swap(G->ext_of, G->ext2);
+  // every problem now fills its slot range (grown problems held slots past it before)
+  if (G->batched) launch_problem_map(n, P, G->dbase, G->prob, s);
+  HIP_OR_FAIL(G, hipGetLastError());
   G->hslot.resize((size_t)n);
   HIP_OR_FAIL(G, hipMemcpyAsync(G->hslot.data(), G->slot_of, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
@@ -636,6 +661,37 @@ int renumber(pirrt_graph* G) {
   G->renumber_pending = false;
   G->snap_n = -1;  // a snapshot in the old order is no longer valid
   drop_loops(G);
+  return PIRRT_OK;
+}
+
+// Insertion-time policy of the n_new vertices appended after slot n_old, one
+// dependency level at a time (staged rows in brp / bcol / bslot / bcost, the new
+// adjacency built).  insert_root: the slot that becomes a root (g = 0), or -1.
+int insert_levels(pirrt_graph* G, int32_t n_new, int64_t n_old, int32_t insert_root) {
+  hipStream_t s = G->stream;
+  // dcount[0] / dcount[1]: the frontier sizes of alternate levels; dcount[2]: vertices
+  // placed.  Levels go out kLevelsPerCheck at a time (a level past the last one finds
+  // an empty frontier and does nothing), then one read-back tells whether more remain.
+  constexpr int kLevelsPerCheck = 4;
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 3 * sizeof(int32_t), s));
+  launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  for (int64_t level = 0;;) {
+    for (int i = 0; i < kLevelsPerCheck; ++i, ++level) {
+      const int cur = (int)(level & 1), nxt = cur ^ 1;
+      HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
+      launch_insert_level(n_new, &G->dcount[cur], &G->dcount[2], cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp,
+                          G->bcol, G->bslot, G->bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending,
+                          nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
+      HIP_OR_FAIL(G, hipGetLastError());
+    }
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->count, G->dcount, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    if (G->host->count[level & 1] == 0) break;  // the next level's frontier is empty
+    if (G->host->count[2] > n_new || level > (int64_t)n_new + kLevelsPerCheck)
+      return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
+  }
+  if (G->host->count[2] != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
   return PIRRT_OK;
 }
 
@@ -716,36 +772,151 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
   else
     G->pbase.back() = n1;
   drop_loops(G);
-  // insertion-time policy, one dependency level at a time
   const int32_t insert_root = new_problem ? (int32_t)n_old : (n_old == 0 ? 0 : -1);
-  // dcount[0] / dcount[1]: the frontier sizes of alternate levels; dcount[2]: vertices
-  // placed.  Levels go out kLevelsPerCheck at a time (a level past the last one finds
-  // an empty frontier and does nothing), then one read-back tells whether more remain.
-  constexpr int kLevelsPerCheck = 4;
-  HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 3 * sizeof(int32_t), s));
-  launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  for (int64_t level = 0;;) {
-    for (int i = 0; i < kLevelsPerCheck; ++i, ++level) {
-      const int cur = (int)(level & 1), nxt = cur ^ 1;
-      HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
-      launch_insert_level(n_new, &G->dcount[cur], &G->dcount[2], cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp,
-                          G->bcol, G->bslot, G->bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending,
-                          nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
-      HIP_OR_FAIL(G, hipGetLastError());
-    }
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->count, G->dcount, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(G, hipStreamSynchronize(s));
-    if (G->host->count[level & 1] == 0) break;  // the next level's frontier is empty
-    if (G->host->count[2] > n_new || level > (int64_t)n_new + kLevelsPerCheck)
-      return fail_device(G, hipErrorUnknown, "insertion levels exceed the batch");
-  }
-  if (G->host->count[2] != n_new) return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
+  if ((rc = insert_levels(G, n_new, n_old, insert_root))) return rc;
   if (new_problem) {
     G->renumber_pending = true;
   } else if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
     if ((rc = renumber(G))) return rc;
   }
+  return PIRRT_OK;
+}
+
+// Grows problems of a batch: block k appends n_new[k] vertices (forward rows in the
+// problem's local ids) to problem problems[k].  The new vertices are first appended
+// after every existing slot with temporary "append ids", the adjacency rebuilt and
+// their insertion-time policy computed exactly as for a single graph (the
+// tie-breaking order inside each problem is the order of its local ids under both id
+// sets); then every vertex takes its final caller id, the problems' bases move, and
+// the next Replan renumbers the slots (the layout is no longer one range per problem).
+int grow_problems(pirrt_graph* G, int32_t count, const int32_t* problems, const int32_t* n_new,
+                  const int64_t* row_ptr, const int32_t* col, const float* cost, int mem_kind) {
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if (count < 0) return fail(G, PIRRT_EINVAL, "count < 0");
+  if (count == 0) return PIRRT_OK;
+  if (!problems || !n_new) return fail(G, PIRRT_EINVAL, "problems or n_new is NULL");
+  const int32_t P = (int32_t)G->pbase.size() - 1;
+  std::vector<int64_t> grow((size_t)P, 0);
+  int64_t total = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    const int32_t p = problems[k];
+    if (p < 0 || p >= P) return fail(G, PIRRT_EINVAL, "problem index out of range");
+    if (n_new[k] < 0) return fail(G, PIRRT_EINVAL, "n_new < 0");
+    for (int32_t j = 0; j < k; ++j)
+      if (problems[j] == p) return fail(G, PIRRT_EINVAL, "a problem is listed twice");
+    grow[(size_t)p] = n_new[k];
+    total += n_new[k];
+  }
+  if (total == 0) return PIRRT_OK;
+  if (!row_ptr) return fail(G, PIRRT_EINVAL, "row_ptr is NULL");
+  if (G->n + total > (int64_t)INT32_MAX - 1) return fail(G, PIRRT_EINVAL, "vertex ids beyond INT32_MAX");
+  hipStream_t s = G->stream;
+  int rc;
+  const int32_t tot = (int32_t)total;
+  int64_t nnz_b = 0;
+  if (mem_kind == PIRRT_MEM_HOST) {
+    nnz_b = row_ptr[tot];
+  } else {
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->word, row_ptr + tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    nnz_b = G->host->word;
+  }
+  if (nnz_b < 0 || nnz_b > ((int64_t)1 << 40)) return fail(G, PIRRT_EINVAL, "row_ptr[total] out of range");
+  if (nnz_b > 0 && (!col || !cost)) return fail(G, PIRRT_EINVAL, "col or cost is NULL");
+  // the block table (non-empty blocks in row order) and the new bases
+  const int64_t n_old = G->n, n1 = n_old + total;
+  std::vector<BatchBlock> blk;
+  int64_t r = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    if (n_new[k] == 0) continue;
+    const int32_t p = problems[k];
+    BatchBlock b;
+    b.row_begin = r;
+    b.base_old = G->pbase[(size_t)p];
+    b.app_base = n_old + r;
+    b.problem = p;
+    b.n_old = (int32_t)(G->pbase[(size_t)p + 1] - G->pbase[(size_t)p]);
+    blk.push_back(b);
+    r += n_new[k];
+  }
+  std::vector<int64_t> pbase_new((size_t)P + 1);
+  pbase_new[0] = 0;
+  for (int32_t p = 0; p < P; ++p)
+    pbase_new[(size_t)p + 1] = pbase_new[(size_t)p] + (G->pbase[(size_t)p + 1] - G->pbase[(size_t)p]) + grow[(size_t)p];
+  const int32_t nblk = (int32_t)blk.size();
+  const int64_t blk_bytes = (int64_t)sizeof(BatchBlock) * nblk;
+  const int64_t need = (blk_bytes + 255) / 256 * 256 + 8 * (int64_t)(P + 1);
+  if (need > G->dgrow_cap) {
+    char* q = nullptr;
+    if (!dalloc(G->A, &q, need)) return fail(G, PIRRT_ENOMEM, "device allocation of the block table failed");
+    dfree(G->A, G->dgrow);
+    G->dgrow = q;
+    G->dgrow_cap = need;
+  }
+  BatchBlock* dblk = reinterpret_cast<BatchBlock*>(G->dgrow);
+  int64_t* dbase_new = reinterpret_cast<int64_t*>(G->dgrow + (blk_bytes + 255) / 256 * 256);
+  if ((rc = upload_bases(G))) return rc;  // dbase = the old bases
+  if ((rc = ensure_staging(G, tot, nnz_b))) return rc;
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->brp, row_ptr, sizeof(int64_t) * (size_t)(tot + 1), in_kind(mem_kind), s));
+  if (nnz_b > 0) {
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcol, col, sizeof(int32_t) * (size_t)nnz_b, in_kind(mem_kind), s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcost, cost, sizeof(float) * (size_t)nnz_b, in_kind(mem_kind), s));
+  }
+  HIP_OR_FAIL(G, hipMemcpyAsync(dblk, blk.data(), (size_t)blk_bytes, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(dbase_new, pbase_new.data(), sizeof(int64_t) * (size_t)(P + 1), hipMemcpyHostToDevice,
+                                s));
+  // row offsets and costs first (local ids are checked per block below)
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
+  launch_validate_rows(tot, n_old, 0, G->brp, G->bcol, G->bcost, nnz_b, G->dflag, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  int32_t bad = 0;
+  if ((rc = read_flag(G, &bad))) return rc;
+  if (!(bad & 1)) {
+    launch_batch_rows(tot, nblk, dblk, G->brp, G->bcol, G->dflag, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    if ((rc = read_flag(G, &bad))) return rc;
+  }
+  if (bad) {
+    std::string m = "invalid rows:";
+    if (bad & 1) m += " row_ptr not 0-based / non-decreasing / bounded;";
+    if (bad & 2) m += " col outside [0, own local id);";
+    if (bad & 4) m += " cost not finite, negative or -0.0;";
+    return fail(G, PIRRT_EINVAL, m);
+  }
+  if ((rc = ensure_vcap(G, n1))) return rc;
+  if ((rc = ensure_spare(G, G->nnz + 2 * nnz_b))) return rc;
+  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
+  launch_block_problems(n_old, tot, nblk, dblk, G->prob, s);
+  launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
+  launch_rebuild(tot, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
+                 G->deg, G->scan_scratch, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  std::swap(G->rp, G->rp2);
+  std::swap(G->col, G->col2);
+  std::swap(G->cst, G->cst2);
+  std::swap(G->ecap, G->ecap2);
+  G->n = n1;
+  G->nnz += 2 * nnz_b;
+  drop_loops(G);
+  if ((rc = insert_levels(G, tot, n_old, -1))) return rc;
+  // final caller ids, bases and host mirrors
+  launch_reid(n1, n_old, nblk, dblk, G->dbase, dbase_new, G->prob, G->ext_of, G->slot_of, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  G->hslot.resize((size_t)n1);
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->hslot.data(), G->slot_of, sizeof(int32_t) * (size_t)n1, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  auto moved = [&](int32_t id) {  // an old caller id under the new bases
+    const size_t p = (size_t)(std::upper_bound(G->pbase.begin(), G->pbase.end(), (int64_t)id) - G->pbase.begin()) - 1;
+    return (int32_t)(pbase_new[p] + (id - G->pbase[p]));
+  };
+  for (auto& id : G->hroots) id = moved(id);
+  if (G->nroots > 0)
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, G->hroots.data(), sizeof(int32_t) * (size_t)G->nroots,
+                                  hipMemcpyHostToDevice, s));
+  G->pbase = pbase_new;
+  if ((rc = upload_bases(G))) return rc;
+  G->renumber_pending = true;
+  G->snap_n = -1;  // a snapshot holds the old layout
   return PIRRT_OK;
 }
 
@@ -1183,11 +1354,19 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     *rc_out = PIRRT_EINVAL;
     return nullptr;
   }
+  if ((c.alloc == nullptr) != (c.free == nullptr)) {
+    g_create_error = "alloc and free must be given together";
+    *rc_out = PIRRT_EINVAL;
+    return nullptr;
+  }
   pirrt_graph* G = new (std::nothrow) pirrt_graph();
   if (!G) {
     *rc_out = PIRRT_ENOMEM;
     return nullptr;
   }
+  G->A.alloc = c.alloc;
+  G->A.free = c.free;
+  G->A.ctx = c.alloc_ctx;
   int dev = c.device;
   if (dev < 0) {
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -1216,8 +1395,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     *rc_out = PIRRT_EDEVICE;
     return nullptr;
   }
-  bool ok = dalloc(&G->info, 1) && dalloc(&G->dflag, 1) && dalloc(&G->dcount, 3) && dalloc(&G->dhops, 1) &&
-            dalloc(&G->ctl, 1);
+  bool ok = dalloc(G->A, &G->info, 1) && dalloc(G->A, &G->dflag, 1) && dalloc(G->A, &G->dcount, 3) && dalloc(G->A, &G->dhops, 1) &&
+            dalloc(G->A, &G->ctl, 1);
   if (ok && hipHostMalloc((void**)&G->host, sizeof(HostBlock), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     G->host = nullptr;
@@ -1453,15 +1632,15 @@ int pirrt_snapshot_save(pirrt_graph* G) {
     float* a = nullptr;
     int32_t* b = nullptr;
     float* c = nullptr;
-    if (!dalloc(&a, n) || !dalloc(&b, n) || !dalloc(&c, n)) {
-      dfree(a);
-      dfree(b);
-      dfree(c);
+    if (!dalloc(G->A, &a, n) || !dalloc(G->A, &b, n) || !dalloc(G->A, &c, n)) {
+      dfree(G->A, a);
+      dfree(G->A, b);
+      dfree(G->A, c);
       return fail(G, PIRRT_ENOMEM, "device allocation for the snapshot failed");
     }
-    dfree(G->sg);
-    dfree(G->sparent);
-    dfree(G->spcost);
+    dfree(G->A, G->sg);
+    dfree(G->A, G->sparent);
+    dfree(G->A, G->spcost);
     G->sg = a;
     G->sparent = b;
     G->spcost = c;
@@ -1536,6 +1715,103 @@ int pirrt_get_adjacency(pirrt_graph* G, int64_t* ptr, int32_t* nbr, float* cost,
   return PIRRT_OK;
 }
 
+// Checkpoint blob: header, forward rows (each vertex's lower-id neighbours, the
+// pirrt_insert_batch format), then the policy in caller ids.
+namespace {
+constexpr uint64_t kBlobMagic = 0x3154535452524950ull;  // "PIRRTST1"
+struct BlobHeader {
+  uint64_t magic;
+  uint32_t version, header_bytes;
+  int64_t n, m;  // vertices, undirected edges (forward entries)
+  int64_t reserved[2];
+};
+static_assert(sizeof(BlobHeader) == 48, "blob header layout");
+
+int64_t blob_bytes(int64_t n, int64_t m) {
+  return (int64_t)sizeof(BlobHeader) + 8 * (n + 1) + 8 * m + 12 * n;
+}
+}  // namespace
+
+int64_t pirrt_state_size(pirrt_graph* G) {
+  if (!G || G->poisoned || G->batched) return -1;
+  return blob_bytes(G->n, G->nnz / 2);
+}
+
+int pirrt_state_save(pirrt_graph* G, void* blob, int64_t size) {
+  int rc = guard(G);
+  if (rc) return rc;
+  if (G->batched) return fail(G, PIRRT_EINVAL, "a batch has no state blob");
+  const int64_t n = G->n, m = G->nnz / 2;
+  if (!blob || size < blob_bytes(n, m)) return fail(G, PIRRT_EINVAL, "blob is NULL or smaller than pirrt_state_size");
+  std::vector<int64_t> ptr((size_t)n + 1);
+  std::vector<int32_t> nbr((size_t)G->nnz);
+  std::vector<float> cst((size_t)G->nnz);
+  if ((rc = pirrt_get_adjacency(G, ptr.data(), nbr.data(), cst.data(), PIRRT_MEM_HOST))) return rc;
+  char* out = static_cast<char*>(blob);
+  BlobHeader h{};
+  h.magic = kBlobMagic;
+  h.version = 1;
+  h.header_bytes = (uint32_t)sizeof(BlobHeader);
+  h.n = n;
+  h.m = m;
+  memcpy(out, &h, sizeof(h));
+  int64_t* rp = reinterpret_cast<int64_t*>(out + sizeof(BlobHeader));
+  int32_t* col = reinterpret_cast<int32_t*>(rp + n + 1);
+  float* cost = reinterpret_cast<float*>(col + m);
+  float* g = cost + m;
+  int32_t* parent = reinterpret_cast<int32_t*>(g + n);
+  float* pcost = reinterpret_cast<float*>(parent + n);
+  int64_t k = 0;
+  rp[0] = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    for (int64_t j = ptr[(size_t)v]; j < ptr[(size_t)v + 1]; ++j)
+      if (nbr[(size_t)j] < v) {
+        if (k >= m) return fail(G, PIRRT_EDEVICE, "adjacency is not symmetric");
+        col[k] = nbr[(size_t)j];
+        cost[k] = cst[(size_t)j];
+        ++k;
+      }
+    rp[v + 1] = k;
+  }
+  if (k != m) return fail(G, PIRRT_EDEVICE, "adjacency is not symmetric");
+  return pirrt_get_policy(G, g, parent, pcost, PIRRT_MEM_HOST);
+}
+
+int pirrt_state_restore(pirrt_graph* G, const void* blob, int64_t size) {
+  int rc = guard(G);
+  if (rc) return rc;
+  if (G->batched) return fail(G, PIRRT_EINVAL, "a batch has no state blob");
+  BlobHeader h;
+  if (!blob || size < (int64_t)sizeof(h)) return fail(G, PIRRT_EINVAL, "blob is NULL or too small");
+  memcpy(&h, blob, sizeof(h));
+  if (h.magic != kBlobMagic || h.version != 1 || h.header_bytes != sizeof(h) || h.n < 0 || h.m < 0 ||
+      h.n > (int64_t)INT32_MAX - 1 || h.m > ((int64_t)1 << 40) || size < blob_bytes(h.n, h.m))
+    return fail(G, PIRRT_EINVAL, "not a state blob of this library, or truncated");
+  const char* in = static_cast<const char*>(blob);
+  const int64_t* rp = reinterpret_cast<const int64_t*>(in + sizeof(BlobHeader));
+  const int32_t* col = reinterpret_cast<const int32_t*>(rp + h.n + 1);
+  const float* cost = reinterpret_cast<const float*>(col + h.m);
+  const float* g = cost + h.m;
+  const int32_t* parent = reinterpret_cast<const int32_t*>(g + h.n);
+  const float* pcost = reinterpret_cast<const float*>(parent + h.n);
+  if (h.n == 0) return G->n == 0 ? PIRRT_OK : fail(G, PIRRT_EINVAL, "the blob holds an empty graph");
+  // the policy is checked before anything changes (the rows by insert_rows itself)
+  for (int64_t v = 0; v < h.n; ++v) {
+    uint32_t w;
+    memcpy(&w, &pcost[v], 4);
+    if (parent[v] < -1 || parent[v] >= h.n || parent[v] == v || (w >> 31) != 0 || (w & 0x7f800000u) == 0x7f800000u)
+      return fail(G, PIRRT_EINVAL, "blob policy has a bad parent or pcost");
+  }
+  if (G->n == 0) {
+    // a fresh handle: the saved graph, then the saved policy
+    if (rp[h.n] != h.m) return fail(G, PIRRT_EINVAL, "blob row offsets do not match its edge count");
+    if ((rc = insert_rows(G, (int32_t)h.n, rp, col, cost, PIRRT_MEM_HOST, false))) return rc;
+  } else if (G->n != h.n || G->nnz != 2 * h.m) {
+    return fail(G, PIRRT_EINVAL, "the handle holds another graph (vertex or edge count differs)");
+  }
+  return pirrt_set_policy(G, g, parent, pcost, PIRRT_MEM_HOST);
+}
+
 // ---------------------------------------------------------------------------
 // Batches of independent problems.
 
@@ -1575,6 +1851,15 @@ int pirrt_batch_add_problem(pirrt_batch* B, int32_t n, const int64_t* row_ptr, c
   if ((rc = insert_rows(G, n, row_ptr, col, cost, mem_kind, true))) return rc;
   if (index) *index = id;
   return PIRRT_OK;
+}
+
+int pirrt_batch_insert(pirrt_batch* B, int32_t count, const int32_t* problems, const int32_t* n_new,
+                       const int64_t* row_ptr, const int32_t* col, const float* cost, int mem_kind) {
+  if (!B) return PIRRT_EINVAL;
+  pirrt_graph* G = B->G;
+  int rc = guard(G);
+  if (rc) return rc;
+  return grow_problems(G, count, problems, n_new, row_ptr, col, cost, mem_kind);
 }
 
 int32_t pirrt_batch_num_problems(const pirrt_batch* B) { return B ? (int32_t)B->G->pbase.size() - 1 : -1; }

@@ -15,6 +15,20 @@ void scan_i32_to_i32(const int32_t* in, int64_t n, int32_t* out, void* scratch, 
 void launch_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound, const int64_t* rp, const int32_t* col,
                           const float* cost, int64_t nnz, int* err, hipStream_t s);
 void launch_offset_ids(int64_t m, int32_t offset, int32_t* ids, hipStream_t s);
+// Growing problems of a batch: one block of appended rows per grown problem.
+struct BatchBlock {
+  int64_t row_begin;  // first row of the block among all appended rows
+  int64_t base_old;   // the problem's first caller id before the growth
+  int64_t app_base;   // append id of the block's first vertex (n_old + row_begin)
+  int32_t problem;
+  int32_t n_old;      // the problem's vertex count before the growth
+};
+void launch_batch_rows(int32_t total, int32_t nblk, const BatchBlock* blk, const int64_t* brp, int32_t* bcol, int* err,
+                       hipStream_t s);
+void launch_block_problems(int64_t n_old, int32_t total, int32_t nblk, const BatchBlock* blk, int32_t* prob,
+                           hipStream_t s);
+void launch_reid(int64_t n1, int64_t n_old, int32_t nblk, const BatchBlock* blk, const int64_t* pbase_old,
+                 const int64_t* pbase_new, const int32_t* prob, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
 void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
                     const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
                     int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
@@ -63,6 +77,8 @@ struct PermuteArgs {
 void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
 void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s);
 void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStream_t s);
+// prob[s] for s < n from the problems' slot ranges (base: P + 1 device offsets).
+void launch_problem_map(int64_t n, int32_t P, const int64_t* base, int32_t* prob, hipStream_t s);
 void launch_unmark_roots(int32_t m, const int32_t* ids, const int32_t* slot_of, int32_t* parent, hipStream_t s);
 void launch_bfs_init(int32_t P, const int32_t* roots, const int64_t* base, int32_t* order, int32_t* visited,
                      int32_t* pcnt, int32_t* frontier, int32_t* fcount, hipStream_t s);

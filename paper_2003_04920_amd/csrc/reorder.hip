@@ -42,6 +42,19 @@ __global__ void __launch_bounds__(kThreads) k_fill_i32(int64_t lo, int64_t hi, i
   if (s < hi) a[s] = value;
 }
 
+// prob[s] = the problem whose slot range [base[p], base[p + 1]) holds s.
+__global__ void __launch_bounds__(kThreads) k_problem_map(int64_t n, int32_t P, const int64_t* __restrict__ base,
+                                                         int32_t* __restrict__ prob) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int32_t lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  prob[s] = lo;
+}
+
 // parent[slot_of[id]] = -1 for the given caller ids whose parent carries the root
 // mark (the roots of an earlier Replan).
 __global__ void __launch_bounds__(kThreads) k_unmark_roots(int32_t m, const int32_t* __restrict__ ids,
@@ -397,6 +410,10 @@ void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int
 
 void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStream_t s) {
   if (hi > lo) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, value, a);
+}
+
+void launch_problem_map(int64_t n, int32_t P, const int64_t* base, int32_t* prob, hipStream_t s) {
+  if (n > 0 && P > 0) hipLaunchKernelGGL(k_problem_map, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, P, base, prob);
 }
 
 void launch_unmark_roots(int32_t m, const int32_t* ids, const int32_t* slot_of, int32_t* parent, hipStream_t s) {

@@ -271,9 +271,97 @@ void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, 
                      insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
 }
 
+// Growing problems of a batch.  The new vertices of all blocks are appended after
+// every existing slot ("append ids" n_old, n_old + 1, ... in block order) and keep
+// those ids until k_reid gives every vertex its final caller id.
+
+// Block of row r: the last block whose first row is <= r (blocks are non-empty and
+// in row order).
+__device__ __forceinline__ int32_t block_of_row(int32_t nblk, const BatchBlock* __restrict__ blk, int64_t r) {
+  int32_t lo = 0, hi = nblk - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (blk[mid].row_begin <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Local neighbour ids -> the ids the insertion uses: an existing vertex its current
+// caller id (its problem's old base + local id), a vertex of the same block its
+// append id.  Local ids outside [0, own local id) raise kErrCol and are left as they
+// are (the call fails before anything reads them).
+__global__ void __launch_bounds__(kThreads) k_batch_rows(int32_t total, int32_t nblk,
+                                                        const BatchBlock* __restrict__ blk,
+                                                        const int64_t* __restrict__ brp, int32_t* __restrict__ bcol,
+                                                        int* __restrict__ err) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const BatchBlock b = blk[block_of_row(nblk, blk, r)];
+  const int64_t own = (int64_t)b.n_old + (r - b.row_begin);
+  int bad = 0;
+  for (int64_t j = brp[r]; j < brp[r + 1]; ++j) {
+    const int32_t c = bcol[j];
+    if (c < 0 || (int64_t)c >= own) {
+      bad = kErrCol;
+      continue;
+    }
+    bcol[j] = c < b.n_old ? (int32_t)(b.base_old + c) : (int32_t)(b.app_base + (c - b.n_old));
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// prob of the appended slots [n_old, n_old + total).
+__global__ void __launch_bounds__(kThreads) k_block_problems(int64_t n_old, int32_t total, int32_t nblk,
+                                                            const BatchBlock* __restrict__ blk,
+                                                            int32_t* __restrict__ prob) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  prob[n_old + r] = blk[block_of_row(nblk, blk, r)].problem;
+}
+
+// Final caller ids after the growth: problem p's vertices take [pbase_new[p],
+// pbase_new[p + 1]) in local order (old vertices keep their local ids, the block's
+// vertices follow them), so every comparison of ids inside a problem is unchanged.
+__global__ void __launch_bounds__(kThreads) k_reid(int64_t n1, int64_t n_old, int32_t nblk,
+                                                  const BatchBlock* __restrict__ blk,
+                                                  const int64_t* __restrict__ pbase_old,
+                                                  const int64_t* __restrict__ pbase_new,
+                                                  const int32_t* __restrict__ prob, int32_t* __restrict__ ext_of,
+                                                  int32_t* __restrict__ slot_of) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n1) return;
+  const int32_t e = ext_of[s];
+  int64_t e1;
+  if (e < n_old) {
+    const int32_t p = prob[s];
+    e1 = pbase_new[p] + (e - pbase_old[p]);
+  } else {
+    const BatchBlock b = blk[block_of_row(nblk, blk, e - n_old)];
+    e1 = pbase_new[b.problem] + b.n_old + (e - b.app_base);
+  }
+  ext_of[s] = (int32_t)e1;
+  slot_of[e1] = (int32_t)s;
+}
+
 __global__ void __launch_bounds__(kThreads) k_offset_ids(int64_t m, int32_t offset, int32_t* __restrict__ ids) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) ids[j] += offset;
+}
+
+void launch_batch_rows(int32_t total, int32_t nblk, const BatchBlock* blk, const int64_t* brp, int32_t* bcol, int* err,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_rows, dim3(blocks_for(total)), dim3(kThreads), 0, s, total, nblk, blk, brp, bcol, err);
+}
+
+void launch_block_problems(int64_t n_old, int32_t total, int32_t nblk, const BatchBlock* blk, int32_t* prob,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_block_problems, dim3(blocks_for(total)), dim3(kThreads), 0, s, n_old, total, nblk, blk, prob);
+}
+
+void launch_reid(int64_t n1, int64_t n_old, int32_t nblk, const BatchBlock* blk, const int64_t* pbase_old,
+                 const int64_t* pbase_new, const int32_t* prob, int32_t* ext_of, int32_t* slot_of, hipStream_t s) {
+  hipLaunchKernelGGL(k_reid, dim3(blocks_for(n1)), dim3(kThreads), 0, s, n1, n_old, nblk, blk, pbase_old, pbase_new,
+                     prob, ext_of, slot_of);
 }
 
 void launch_offset_ids(int64_t m, int32_t offset, int32_t* ids, hipStream_t s) {
