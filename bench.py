@@ -347,21 +347,14 @@ def bench_learned(args):
 
     import paper_2003_04920_amd as P
     import workloads as W
+    from paper_2003_04920_amd import learned as L
+    from paper_2003_04920_amd import planner as PL
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream().cuda_stream
     d, n_train = 6, 200_000
-    root_goal = np.stack([np.full(d, 0.05), np.full(d, 0.95)])
-
-    def build(seed, n):
-        obs = W.make_obstacles(d, 40, "sphere", seed)
-        R = P.Rrg(d, obs, stream=stream, point_capacity=n)
-        R.add_points(root_goal)
-        R.sample(seed + 1, 0, 0, n - 2)
-        G = P.Graph(stream=stream, vertex_capacity=n)
-        R.connect(0, W.radius(n, d), G)
-        return obs, R, G
+    root_goal = PL.root_goal(d)
 
     # ---- exploration support on its own: one 200k-vertex 6D graph, the radius search
     # (two passes over every pair u < v, binary64 squared distance: 3d - 1 = 17 flops
@@ -384,64 +377,23 @@ def bench_learned(args):
     log("exploration: %s" % json.dumps(explore))
     del R0, G0
 
-    # ---- training data
-    t0 = time.perf_counter()
-    xs, ys = [], []
-    rng = np.random.default_rng(7)
-    pos_total = 0
-    for i in range(args.layouts):
-        obs, R, G = build(20_000 + 10 * i, n_train)
-        g_r, _, _ = G.replan(0, 1, None, False)
-        g_t, _, _ = G.replan(1, 0, None, False)
-        best = float(g_r[1])
-        tot = g_r.astype(np.float64) + g_t.astype(np.float64)
-        lab = (np.isfinite(tot) & (tot <= 1.05 * best)).astype(np.float32)
-        pos = np.nonzero(lab > 0)[0]
-        neg = np.nonzero(lab == 0)[0]
-        k_pos = min(len(pos), args.per_layout // 2)
-        pick = np.concatenate([rng.choice(pos, k_pos, replace=False),
-                               rng.choice(neg, args.per_layout - k_pos, replace=False)])
-        pts = R.points()[pick].astype(np.float32)
-        enc = W.sphere_encoding(obs)
-        xs.append(np.concatenate([pts, np.broadcast_to(enc, (len(pick), len(enc)))], axis=1))
-        ys.append(lab[pick])
-        pos_total += int(lab.sum())
-        del R, G
-        if (i + 1) % 100 == 0:
-            log("training data: %d of %d layouts (%.1f s)" % (i + 1, args.layouts, time.perf_counter() - t0))
-    X = torch.from_numpy(np.ascontiguousarray(np.concatenate(xs), np.float32)).to(dev)
-    Y = torch.from_numpy(np.concatenate(ys)).to(dev)
-    data_s = time.perf_counter() - t0
-    log("training data: %d layouts, %d samples (%.1f%% positive), %.1f s; positives per layout %.0f" %
-        (args.layouts, len(Y), 100.0 * float(Y.mean()), data_s, pos_total / max(1, args.layouts)))
+    # ---- training data and training on the device (paper_2003_04920_amd.learned)
+    def scene(seed):
+        return W.make_obstacles(d, 40, "sphere", seed)
 
-    # ---- training on the device
-    in_dim = X.shape[1]
-    net = P.Mlp(in_dim, 8192, lr=1e-3, stream=stream)
-    init = np.zeros(net.num_params, np.float32)
-    r2 = np.random.default_rng(11)
-    o = 0
-    init[o:o + in_dim * 256] = (r2.standard_normal((in_dim, 256)) * np.sqrt(2.0 / in_dim)).ravel()
-    o = 288 * 256 + 256
-    init[o:o + 256 * 256] = (r2.standard_normal(256 * 256) * np.sqrt(2.0 / 256))
-    o += 256 * 256 + 256
-    init[o:o + 256] = r2.standard_normal(256) * np.sqrt(1.0 / 256)
-    net.set_params(init)
-    nval = len(Y) // 10
-    perm = torch.from_numpy(np.random.default_rng(3).permutation(len(Y))).to(dev)
-    Xv, Yv, Xt, Yt = X[perm[:nval]], Y[perm[:nval]], X[perm[nval:]].contiguous(), Y[perm[nval:]].contiguous()
-    bs = 4096
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses, steps = [], 0
-    for ep in range(args.epochs):
-        order = torch.randperm(len(Yt), device=dev)
-        for i in range(0, len(Yt) - bs + 1, bs):
-            idx = order[i:i + bs]
-            losses.append(net.train_step(Xt[idx].contiguous(), Yt[idx].contiguous()))
-            steps += 1
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    net, trec = L.build_and_train(d, scene, [20_000 + 10 * i for i in range(args.layouts)], n_train, args.per_layout,
+                                  args.epochs, stream=stream, log=log)
+    data_s, train_s, steps, bs = trec["data_seconds"], trec["train_seconds"], trec["steps"], trec["batch"]
+    log("training data: %d layouts, %d samples (%.1f%% positive), %.1f s" %
+        (args.layouts, trec["samples"], 100.0 * trec["positive_share"], data_s))
+    # held-out accuracy on fresh layouts (features and labels as in training)
+    rng = np.random.default_rng(8)
+    xv, yv = zip(*[L.layout_samples(d, scene(25_000 + 10 * i), 25_001 + 10 * i, n_train, args.per_layout, rng,
+                                    stream=stream) for i in range(max(1, args.layouts // 10))])
+    Xv = torch.from_numpy(np.ascontiguousarray(np.concatenate(xv), np.float32)).to(dev)
+    Yv = torch.from_numpy(np.concatenate(yv)).to(dev)
+    in_dim = Xv.shape[1]
+    nval = len(Yv)
     zv = torch.cat([net.forward(Xv[i:i + 8192].contiguous()) for i in range(0, nval, 8192)])
     pred = zv > 0
     acc = float((pred == (Yv > 0)).float().mean())
@@ -449,7 +401,9 @@ def bench_learned(args):
     precision = float((pred & (Yv > 0)).float().sum() / pred.float().sum().clamp(min=1))
     log("training: %d steps of %d in %.2f s (%.0f samples/s); loss %.4f -> %.4f; held-out accuracy %.3f, "
         "recall %.3f, precision %.3f" % (steps, bs, train_s, steps * bs / max(train_s, 1e-9),
-                                         np.mean(losses[:20]), np.mean(losses[-20:]), acc, recall, precision))
+                                         trec["loss_first"], trec["loss_last"], acc, recall, precision))
+    Xt, Yt = Xv, Yv  # resident batches for the timing probes below
+    init = L.init_params(in_dim, 11)
     xb = Xt[:8192].contiguous()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -504,32 +458,13 @@ def bench_learned(args):
         cpu.update(host_fields())
         log("cpu baseline: %s" % json.dumps(cpu))
 
-    # ---- planner comparison on held-out layouts
+    # ---- planner comparison on held-out layouts (paper_2003_04920_amd.planner)
     def plan(seed, learned):
-        obs = W.make_obstacles(d, 40, "sphere", seed)
-        enc = W.sphere_encoding(obs)
-        R = P.Rrg(d, obs, stream=stream, point_capacity=args.plan_n + args.batch)
-        R.add_points(root_goal)
-        G = P.Graph(stream=stream, vertex_capacity=args.plan_n + args.batch)
-        R.connect(0, W.radius(2, d), G)
-        cu, cl, n_old, hist = 0, 0, 2, []
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        while R.n < args.plan_n:
-            if learned:
-                cl = R.sample_learned(net, enc, seed + 1, 1, cl, 8192, args.batch // 2)
-                cu = R.sample(seed + 1, 0, cu, args.batch - args.batch // 2)
-            else:
-                cu = R.sample(seed + 1, 0, cu, args.batch)
-            n = R.n
-            R.connect(n_old, W.radius(n, d), G)
-            h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
-            gout = torch.empty(n, dtype=torch.float32, device=dev)
-            pout = torch.empty(n, dtype=torch.int32, device=dev)
-            G.replan(0, 1, h, True, g_out=gout, parent_out=pout)
-            hist.append((time.perf_counter() - t_start, n, float(gout[1].item())))
-            n_old = n
-        return hist
+        obs = scene(seed)
+        pl = PL.Planner(d, obs, seed + 1, args.plan_n + args.batch + 2, stream=torch.cuda.current_stream(),
+                        trigger=False, net=net if learned else None,
+                        enc=L.sphere_encoding(obs) if learned else None)
+        return [(r["seconds"], r["n"], r["cost"]) for r in pl.run(args.plan_n, args.batch)]
 
     rows = []
     for j in range(args.heldout):
@@ -559,8 +494,8 @@ def bench_learned(args):
                                "learned = half of each batch the best of 8192 scored candidates" %
                                (args.layouts, n_train, args.per_layout, args.plan_n, args.batch)},
         "training": {"steps": steps, "batch": bs, "seconds": round(train_s, 3),
-                     "samples_per_s": round(steps * bs / max(train_s, 1e-9)), "loss_first": round(float(np.mean(losses[:20])), 4),
-                     "loss_last": round(float(np.mean(losses[-20:])), 4), "heldout_accuracy": round(acc, 4),
+                     "samples_per_s": round(steps * bs / max(train_s, 1e-9)), "loss_first": round(trec["loss_first"], 4),
+                     "loss_last": round(trec["loss_last"], 4), "heldout_accuracy": round(acc, 4),
                      "heldout_recall": round(recall, 4), "heldout_precision": round(precision, 4),
                      "data_seconds": round(data_s, 2)},
         "inference_us_per_8192": round(infer_us, 1),
@@ -585,28 +520,31 @@ def bench_sweep(args):
 
     import paper_2003_04920_amd as P
     import workloads as W
+    from paper_2003_04920_amd import planner as PL
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream().cuda_stream
     d = 2
-    root_goal = np.array([[0.05, 0.05], [0.95, 0.95]])
+    root_goal = PL.root_goal(d)
     Ns = [int(x) for x in args.sweep_n.split(",")]
     Ss = [int(x) for x in args.sweep_s.split(",")]
 
     def plan(N, S, seed, cpu):
         obs = W.make_obstacles(d, 8, "box", seed)
+        if not cpu:  # the package's BERRT# planner (replan test on the device)
+            pl = PL.Planner(d, obs, seed + 1, N + 2, stream=torch.cuda.current_stream(), trigger=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hist = pl.run(N, S)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, pl.replans, hist[-1]["cost"]
         R = P.Rrg(d, obs, stream=stream, point_capacity=N + 2)
         R.add_points(root_goal)
-        G = P.Graph(stream=stream, vertex_capacity=N + 2)
-        O = None
-        if cpu:
-            import oracle
-            O = oracle.Graph()
-            rp_, col_, cost_ = R.rows(0, W.radius(2, d))
-            assert O.insert(rp_, col_, cost_) == 0
-        else:
-            R.connect(0, W.radius(2, d), G)
+        import oracle
+        O = oracle.Graph()
+        rp_, col_, cost_ = R.rows(0, W.radius(2, d))
+        assert O.insert(rp_, col_, cost_) == 0
         counter, n_old, replans = 0, 2, 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -615,26 +553,18 @@ def bench_sweep(args):
             n = R.n
             r = W.radius(n, d)
             h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
-            if cpu:
-                rp_, col_, cost_ = R.rows(n_old, r)
-                assert O.insert(rp_, col_, cost_) == 0
-                g = O.state().g
-                hh = h.cpu().numpy()
-                if bool(((g[n_old:] + hh[n_old:]) < g[1]).any()):
-                    rc, _ = O.replan(0, 1, hh, True)
-                    assert rc == 0
-                    replans += 1
-            else:
-                R.connect(n_old, r, G)
-                g, _, _ = G.get_policy(device=dev)
-                if bool(((g[n_old:] + h[n_old:]) < g[1]).any().item()):
-                    G.replan(0, 1, h, True, g_out=g, parent_out=torch.empty(n, dtype=torch.int32, device=dev))
-                    replans += 1
+            rp_, col_, cost_ = R.rows(n_old, r)
+            assert O.insert(rp_, col_, cost_) == 0
+            g = O.state().g
+            hh = h.cpu().numpy()
+            if bool(((g[n_old:] + hh[n_old:]) < g[1]).any()):  # the same replan test on the oracle's state
+                rc, _ = O.replan(0, 1, hh, True)
+                assert rc == 0
+                replans += 1
             n_old = n
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        cost = float(O.state().g[1]) if cpu else float(G.get_policy()[0][1])
-        return t, replans, cost
+        return t, replans, float(O.state().g[1])
 
     rows = []
     for N in Ns:
@@ -683,98 +613,32 @@ def bench_async(args):
     overlap the Replan of earlier ones.  Against the same loop run in lockstep (sample,
     connect, Replan per batch).  The two build the same graph; the exploiter replans
     less often (once per drained queue)."""
-    import queue
-    import threading
-
-    import numpy as np
     import torch
 
-    import paper_2003_04920_amd as P
     import workloads as W
+    from paper_2003_04920_amd import planner as PL
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d, N, S = 6, args.async_n, args.async_s
     obs = W.make_obstacles(d, 40, "sphere", 100)
-    root_goal = np.stack([np.full(d, 0.05), np.full(d, 0.95)])
 
     def lockstep():
         st = torch.cuda.Stream()
-        R = P.Rrg(d, obs, stream=st.cuda_stream, point_capacity=N + 2)
-        R.add_points(root_goal)
-        G = P.Graph(stream=st.cuda_stream, vertex_capacity=N + 2)
-        R.connect(0, W.radius(2, d), G)
-        counter, n_old, replans = 0, 2, 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         with torch.cuda.stream(st):
-            while R.n - 2 < N:
-                counter = R.sample(101, 0, counter, min(S, N - (R.n - 2)))
-                n = R.n
-                R.connect(n_old, W.radius(n, d), G)
-                h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
-                g, _, _ = G.replan(0, 1, h, True)
-                replans += 1
-                n_old = n
+            pl = PL.Planner(d, obs, 101, N + 2, stream=st, trigger=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hist = pl.run(N, S)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, replans, float(g[1].item()), G.n, G.nnz
+        return time.perf_counter() - t0, pl.replans, hist[-1]["cost"], pl.graph.n, pl.graph.nnz
 
     def concurrent():
-        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
-        R = P.Rrg(d, obs, stream=sa.cuda_stream, point_capacity=N + 2)
-        R.add_points(root_goal)
-        G = P.Graph(stream=sb.cuda_stream, vertex_capacity=N + 2)
-        rp0, c0, w0 = R.rows(0, W.radius(2, d), device=dev)
-        sa.synchronize()
-        with torch.cuda.stream(sb):
-            G.insert_batch(rp0, c0, w0)
-        q = queue.Queue()
-        err = []
-
-        def explorer():
-            try:
-                with torch.cuda.stream(sa):
-                    counter, n_old = 0, 2
-                    while R.n - 2 < N:
-                        counter = R.sample(101, 0, counter, min(S, N - (R.n - 2)))
-                        n = R.n
-                        rp, col, cost = R.rows(n_old, W.radius(n, d), device=dev)
-                        h = R.heuristic(1, out=torch.empty(n, dtype=torch.float32, device=dev))
-                        sa.synchronize()
-                        q.put((rp, col, cost, h))
-                        n_old = n
-            except Exception as e:  # reported by the exploiter
-                err.append(e)
-            q.put(None)
-
-        replans, done, g = 0, False, None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        th = threading.Thread(target=explorer)
-        th.start()
-        with torch.cuda.stream(sb):
-            while not done:
-                items = [q.get()]
-                while True:
-                    try:
-                        items.append(q.get_nowait())
-                    except queue.Empty:
-                        break
-                h = None
-                for it in items:
-                    if it is None:
-                        done = True
-                        continue
-                    rp, col, cost, h = it
-                    G.insert_batch(rp, col, cost)
-                if h is not None:
-                    g, _, _ = G.replan(0, 1, h, True)
-                    replans += 1
-        th.join()
-        torch.cuda.synchronize()
-        if err:
-            raise err[0]
-        return time.perf_counter() - t0, replans, float(g[1].item()), G.n, G.nnz
+        G, R, replans, _ = PL.plan_concurrent(d, obs, 101, N, S)
+        t = time.perf_counter() - t0
+        return t, replans, float(G.get_policy()[0][1]), G.n, G.nnz
 
     lockstep()  # warm-up (kernel loading, allocations)
     t_l, r_l, c_l, n_l, m_l = lockstep()

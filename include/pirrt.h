@@ -208,6 +208,19 @@ int pirrt_set_policy(pirrt_graph* g, const float* g_in, const int32_t* parent_in
 int pirrt_snapshot_save(pirrt_graph* g);
 int pirrt_snapshot_restore(pirrt_graph* g);
 
+/*
+ * Alg. 3's replan test |B'| > |B|: after an Extend batch, the number of vertices among
+ * ids [first, first + count) that are promising under the stored policy (their
+ * insertion-time g), i.e. fl(g(v) + h(v)) < g(goal) with the stored g(goal) (an
+ * unreachable goal, g = +inf, makes every reachable vertex promising).  Replan is due
+ * when it is nonzero.  h: float[n] over all vertices in caller ids at mem_kind, or
+ * NULL (h = 0); only [first, first + count) is read (and, from host memory, checked:
+ * >= 0, not NaN).  *out: host int64.  EINVAL for a batch's graph, a goal or range
+ * outside the graph.  Synchronous.
+ */
+int pirrt_promising_count(pirrt_graph* g, int32_t goal, const float* h, int64_t first, int64_t count, int mem_kind,
+                          int64_t* out);
+
 /* Copies the adjacency out as CSR: ptr int64[n+1], nbr int32[nnz], cost float[nnz]
    (any may be NULL).  The order of entries inside a row is unspecified. */
 int pirrt_get_adjacency(pirrt_graph* g, int64_t* ptr, int32_t* nbr, float* cost, int mem_kind);

@@ -37,7 +37,7 @@ EXPORTS = [
     "pirrt_mlp_forward", "pirrt_mlp_gradients", "pirrt_mlp_train_step", "pirrt_mlp_last_error",
     "pirrt_mlp_in_dim", "pirrt_rrg_sample_learned", "pirrt_tune", "pirrt_batch_tune",
     "pirrt_mlp_forward_noalloc", "pirrt_batch_insert", "pirrt_state_size", "pirrt_state_save",
-    "pirrt_state_restore",
+    "pirrt_state_restore", "pirrt_promising_count",
 ]
 
 
@@ -131,6 +131,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "pirrt_snapshot_restore": (cint, [vp]),
         "pirrt_get_adjacency": (cint, [vp, vp, vp, vp, cint]),
         "pirrt_state_size": (i64, [vp]),
+        "pirrt_promising_count": (cint, [vp, i32, vp, i64, i64, cint, ctypes.POINTER(i64)]),
         "pirrt_state_save": (cint, [vp, vp, i64]),
         "pirrt_state_restore": (cint, [vp, vp, i64]),
         "pirrt_num_vertices": (i64, [vp]),
@@ -349,6 +350,16 @@ class Graph:
 
     def snapshot_restore(self) -> int:
         return self._check(self._lib.pirrt_snapshot_restore(self._h))
+
+    def promising_count(self, goal: int, h=None, first: int = 0, count: Optional[int] = None) -> int:
+        """pirrt_promising_count: promising vertices among ids [first, first + count)."""
+        h = _check_dtype(h, np.float32, "float32")
+        if count is None:
+            count = self.n - first
+        out = ctypes.c_int64(0)
+        self._check(self._lib.pirrt_promising_count(self._h, int(goal), _ptr(h), int(first), int(count),
+                                                    _mem_kind(h), ctypes.byref(out)))
+        return int(out.value)
 
     def state_size(self) -> int:
         return int(self._lib.pirrt_state_size(self._h))

@@ -1681,6 +1681,39 @@ int pirrt_snapshot_restore(pirrt_graph* G) {
   return PIRRT_OK;
 }
 
+int pirrt_promising_count(pirrt_graph* G, int32_t goal, const float* h, int64_t first, int64_t count, int mem_kind,
+                          int64_t* out) {
+  int rc = guard(G);
+  if (rc) return rc;
+  if (G->batched) return fail(G, PIRRT_EINVAL, "pirrt_promising_count takes a single graph");
+  if (mem_kind != PIRRT_MEM_HOST && mem_kind != PIRRT_MEM_DEVICE) return fail(G, PIRRT_EINVAL, "bad mem_kind");
+  if (!out) return fail(G, PIRRT_EINVAL, "out is NULL");
+  const int64_t n = G->n;
+  if (goal < 0 || goal >= n) return fail(G, PIRRT_EINVAL, "goal out of range");
+  if (first < 0 || count < 0 || first + count > n) return fail(G, PIRRT_EINVAL, "id range outside the graph");
+  *out = 0;
+  if (count == 0) return PIRRT_OK;
+  hipStream_t s = G->stream;
+  const float* hd = nullptr;
+  if (h) {
+    if (mem_kind == PIRRT_MEM_HOST) {
+      for (int64_t i = first; i < first + count; ++i)
+        if (!(h[i] >= 0.0f)) return fail(G, PIRRT_EINVAL, "h must be >= 0 and not NaN");
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->hbuf, h + first, sizeof(float) * (size_t)count, hipMemcpyHostToDevice, s));
+      hd = G->hbuf;
+    } else {
+      hd = h + first;
+    }
+  }
+  HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
+  launch_count_promising(first, count, G->hslot[(size_t)goal], G->slot_of, G->g, hd, G->dhops, s);
+  HIP_OR_FAIL(G, hipGetLastError());
+  HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->hops, G->dhops, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  *out = (int64_t)G->host->hops;
+  return PIRRT_OK;
+}
+
 int pirrt_get_adjacency(pirrt_graph* G, int64_t* ptr, int32_t* nbr, float* cost, int mem_kind) {
   int rc = guard(G);
   if (rc) return rc;

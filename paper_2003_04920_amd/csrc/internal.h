@@ -214,6 +214,10 @@ void launch_mark(const StepArgs& a, int variant, hipStream_t s);
 // Compacts the stamped slots into dlist / ctl->ndomain (and clears every stamp when
 // the next mark epoch wraps its low byte).
 void launch_domain_list(const StepArgs& a, hipStream_t s);
+// out += number of ids in [first, first + count) with fl(g + h) < g(goal); h is indexed
+// from `first` (nullable).
+void launch_count_promising(int64_t first, int64_t count, int32_t goal_slot, const int32_t* slot_of, const float* g,
+                            const float* h, unsigned long long* out, hipStream_t s);
 void launch_improve(const StepArgs& a, int variant, hipStream_t s);
 
 }  // namespace pirrt

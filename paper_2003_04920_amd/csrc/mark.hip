@@ -412,7 +412,29 @@ void launch_mark_b(const StepArgs& a, hipStream_t s) {
   if (a.prob) launch_mark_t<GW, U, true>(a, s); else launch_mark_t<GW, U, false>(a, s);
 }
 
+// Alg. 3's test |B'| > |B| after an Extend batch: how many of the caller ids
+// [first, first + count) are promising under the stored policy, fl(g + h) < g(goal)
+// (h indexed from `first`; NULL = 0).  One atomic per wave.
+__global__ void __launch_bounds__(kThreads) k_count_promising(int64_t first, int64_t count, int32_t goal_slot,
+                                                             const int32_t* __restrict__ slot_of,
+                                                             const float* __restrict__ g,
+                                                             const float* __restrict__ h,
+                                                             unsigned long long* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool p = false;
+  if (i < count) p = add_rn(g[slot_of[first + i]], h ? h[i] : 0.0f) < g[goal_slot];
+  const unsigned long long b = __ballot(p);
+  if ((threadIdx.x & (kWave - 1)) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+}
+
 }  // namespace
+
+void launch_count_promising(int64_t first, int64_t count, int32_t goal_slot, const int32_t* slot_of, const float* g,
+                            const float* h, unsigned long long* out, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_count_promising, dim3((unsigned)((count + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       first, count, goal_slot, slot_of, g, h, out);
+}
 
 void launch_domain_list(const StepArgs& a, hipStream_t s) {
   const int64_t per_block = (int64_t)kThreads * kListPer;
