@@ -83,6 +83,27 @@ def improve_bytes(edges: int, sum_d: int, n: int, launches: int) -> int:
     return 8 * edges + 24 * sum_d
 
 
+def replan_bytes(st: dict, n: int) -> dict:
+    """Algorithmic HBM bytes of one whole Replan, by phase, from its counters:
+    - Evaluate walk: 28 B per vertex and call (stamp word read 8, parent and cost 8,
+      stamp word and g written 12);
+    - promising list: 8 B per vertex and iteration (g, h) + 5 B per promising vertex
+      (its list entry and stamp);
+    - mark: 20 B per promising vertex (list entry, two row offsets) + 5 B per entry of
+      a promising row (neighbour read 4, stamp written 1);
+    - domain list: 1 B per vertex and iteration (stamps) + 4 B per domain vertex;
+    - Improve: 8 B per examined edge + 24 B per domain vertex.
+    The g gathers of Improve (L2 / MALL resident) are not counted."""
+    it, calls = st["iterations"], st["iterations"]  # one Evaluate before each Improve
+    parts = {"evaluate": 28 * n * calls,
+             "promising_list": 8 * n * it + 5 * st["sum_P"],
+             "mark": 20 * st["sum_P"] + 5 * st["mark_edges"],
+             "domain_list": 1 * n * it + 4 * st["sum_D"],
+             "improve": 8 * st["edges_examined"] + 24 * st["sum_D"]}
+    parts["total"] = sum(parts.values())
+    return parts
+
+
 def source_digest() -> str:
     """Digest of the Improve kernel's sources (its file and the shared row-pass header)."""
     h = hashlib.sha256()
@@ -1099,7 +1120,7 @@ def main():
         bad_p = int(np.count_nonzero(p_timed != ref.parent))
         if bad_g or bad_p:
             raise SystemExit("timed Replan differs from the oracle: %d g values, %d parents" % (bad_g, bad_p))
-        for k in ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total"):
+        for k in ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total", "mark_edges"):
             if so[k] != st[k]:
                 raise SystemExit("timed Replan differs from the oracle in %s: %d against %d" % (k, st[k], so[k]))
         cpu = {"value": round(so["edges_examined"] / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
@@ -1118,6 +1139,13 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
 
+    rb = replan_bytes(st, n)
+    replan_hbm = {"bytes_per_replan": rb["total"], "by_phase": {k: v for k, v in rb.items() if k != "total"},
+                  "achieved": round(rb["total"] / (ms_per_step * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(rb["total"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "note": "the whole Replan's algorithmic bytes (every phase, counters of the timed call) over "
+                          "the timed ms per Replan"}
+    log("replan HBM: %s" % json.dumps(replan_hbm))
     out = {
         "metric": "Replan GTEPS + ms/replan (6D 1M-vertex RRG), HBM % peak; plain vs learned",
         "value": round(gteps, 3),
@@ -1139,6 +1167,7 @@ def main():
                    "autotuned_config": tuned, "parallelism": "single GPU"},
         "phases_ms": {k: round(tst[k], 4) for k in ("ms_evaluate", "ms_mark", "ms_improve")},
         "roofline": roofline,
+        "replan_hbm": replan_hbm,
         "evaluate": evaluate,
         "cpu_baseline": cpu,
         "extra_batch": extra,

@@ -126,6 +126,8 @@ typedef struct {
   int32_t mark_launches;
   int32_t evaluate_calls;
   int32_t reserved;
+  int64_t mark_edges;     /* sum over iterations of the promising set's degrees (the rows
+                             streamed to mark the Improve domain) */
 } pirrt_stats;
 
 /* Fills *cfg with defaults (capacities 0, NULL stream, cap 0, device -1, no allocator

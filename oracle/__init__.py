@@ -42,7 +42,7 @@ def build(force: bool = False, defines=(), out: Optional[str] = None) -> str:
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("edges_examined", ctypes.c_int64),
                 ("sum_P", ctypes.c_int64), ("sum_D", ctypes.c_int64),
-                ("changed_total", ctypes.c_int64)]
+                ("changed_total", ctypes.c_int64), ("mark_edges", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

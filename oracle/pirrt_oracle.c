@@ -54,6 +54,8 @@ typedef struct {
   int64_t sum_P;          /* sum over iterations of |promising set| */
   int64_t sum_D;          /* sum over iterations of |Improve domain| */
   int64_t changed_total;  /* sum over iterations of parents switched */
+  int64_t mark_edges;     /* sum over iterations of the degrees of the promising set
+                             (the rows walked to build D = P u N(P)) */
 } orc_stats;
 
 typedef struct {
@@ -372,7 +374,7 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
     evaluate(G, root, child_ptr, child, queue, depth);
   for (;;) {
     float thr = prune ? G->g[goal] : INFINITY;
-    int64_t np = 0, nd = 0, ex = 0, nchg = 0;
+    int64_t np = 0, nd = 0, ex = 0, nchg = 0, pe = 0;
     if (truncated) {
       np = nb;
       for (int64_t v = 0; v < n; ++v) inD[v] = 0;
@@ -388,6 +390,7 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
     for (int64_t v = 0; v < n; ++v) {
       if (!inP[v]) continue;
       inD[v] = 1;
+      pe += G->deg[v];
       for (int32_t j = 0; j < G->deg[v]; ++j) {
         int32_t w = G->nbr[v][j];
         if (lookahead) {
@@ -430,6 +433,7 @@ int orc_replan_mode(orc_graph* G, int32_t root, int32_t goal, const float* h, in
     st->sum_P += np;
     st->sum_D += nd;
     st->changed_total += nchg;
+    st->mark_edges += pe;
     if (nchg == 0) break;
     memcpy(G->parent, newpar, sizeof(int32_t) * (size_t)n);
     memcpy(G->pcost, newpc, sizeof(float) * (size_t)n);

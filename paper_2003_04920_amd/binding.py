@@ -93,7 +93,7 @@ class pirrt_stats(ctypes.Structure):
                 ("changed_total", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_evaluate", ctypes.c_double), ("ms_mark", ctypes.c_double), ("ms_improve", ctypes.c_double),
                 ("improve_launches", ctypes.c_int32), ("mark_launches", ctypes.c_int32),
-                ("evaluate_calls", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("evaluate_calls", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mark_edges", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}

@@ -1135,6 +1135,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
       st.sum_P = (int64_t)q.sum_P;
       st.sum_D = (int64_t)q.sum_D;
       st.changed_total = (int64_t)q.changed_total;
+      st.mark_edges = (int64_t)q.mark_edges;
       st.evaluate_calls = q.iterations;
       st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
@@ -1246,6 +1247,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
       st.sum_P = (int64_t)q.sum_P;
       st.sum_D = (int64_t)q.sum_D;
       st.changed_total = (int64_t)q.changed_total;
+      st.mark_edges = (int64_t)q.mark_edges;
       st.ms_total = ms;
       st.evaluate_calls = timing ? agg.evaluate_calls : q.iterations;
       // the phases of a batch serve all of its problems at once

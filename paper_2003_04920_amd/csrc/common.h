@@ -20,7 +20,7 @@ struct IterCounters {
   int32_t changed;           // parents switched by Improve
   int32_t nP;                // |promising set|
   int32_t nD;                // |Improve domain|
-  int32_t pad;
+  int32_t pedges;            // sum of the degrees over the promising set (the rows marked)
   unsigned long long edges;  // sum of the degrees over the Improve domain
 };
 
@@ -35,6 +35,7 @@ struct ProblemState {
   int32_t status;      // 0 running / converged, 1 iteration cap reached
   int32_t cap;         // iteration cap
   unsigned long long edges, sum_P, sum_D, changed_total;
+  unsigned long long mark_edges;  // sum over iterations of the promising rows' degrees
 };
 
 // Device-side loop control shared by the kernels of one Replan.

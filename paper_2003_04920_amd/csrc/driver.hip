@@ -26,6 +26,7 @@ __global__ void k_replan_init(int32_t P, ProblemState* __restrict__ ps, int32_t*
     c.changed = 0;
     c.nP = 0;
     c.nD = 0;
+    c.pedges = 0;
     c.edges = 0ull;
   }
   if (t < P) {
@@ -59,6 +60,7 @@ __global__ void __launch_bounds__(kCounterSlots) k_replan_init_single(
   c.changed = 0;
   c.nP = 0;
   c.nD = 0;
+  c.pedges = 0;
   c.edges = 0ull;
   if (t == 0) {
     for (int32_t i = 0; i < nold; ++i) {  // in order, before the new mark (a root may repeat)
@@ -96,10 +98,12 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
   const int32_t i = blockIdx.x;
   const int t = threadIdx.x;
   IterCounters& c = ctr[(int64_t)i * kCounterSlots + t];
-  unsigned long long ch = (unsigned)c.changed, np = (unsigned)c.nP, nd = (unsigned)c.nD, ed = c.edges;
+  unsigned long long ch = (unsigned)c.changed, np = (unsigned)c.nP, nd = (unsigned)c.nD, ed = c.edges,
+                     pe = (unsigned)c.pedges;
   c.changed = 0;
   c.nP = 0;
   c.nD = 0;
+  c.pedges = 0;
   c.edges = 0ull;
 #pragma unroll
   for (int off = kCounterSlots / 2; off > 0; off >>= 1) {
@@ -107,6 +111,7 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
     np += __shfl_xor(np, off, kCounterSlots);
     nd += __shfl_xor(nd, off, kCounterSlots);
     ed += __shfl_xor(ed, off, kCounterSlots);
+    pe += __shfl_xor(pe, off, kCounterSlots);
   }
   if (t == 0) {
     ProblemState& s = ps[i];
@@ -116,6 +121,7 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
       s.sum_P += np;
       s.sum_D += nd;
       s.changed_total += ch;
+      s.mark_edges += pe;
       if (ch == 0) {  // no parent switched: fixed point (dJ = 0)
         s.active = 0;
         s.needs_eval = 0;

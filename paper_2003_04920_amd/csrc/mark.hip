@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
       }
     }
   }
-  flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0);
+  flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0, in ? (int)(rb - ra) : 0);
   }
 }
 
@@ -194,7 +194,8 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
                                                             const float* __restrict__ h,
                                                             uint8_t* __restrict__ stamp, int32_t* __restrict__ plist,
                                                             IterCounters* __restrict__ ctr,
-                                                            const unsigned long long* __restrict__ word, int prune) {
+                                                            const unsigned long long* __restrict__ word, int prune,
+                                                            const int64_t* __restrict__ rp) {
   const bool active = ps[0].active != 0;
   const float G = active ? (prune ? g[ps[0].goal] : pos_inf()) : -pos_inf();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -231,7 +232,14 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
     for (int i = 0; i < kListPer && v0 + i < n; ++i)
       if (add_rn(g[v0 + i], h ? h[v0 + i] : 0.0f) < G) mask |= 1u << i;
   }
+  // the degrees of the listed rows (the rows the mark walks), for the counters
+  int pe = 0;
+  for (uint32_t m = mask; m; m &= m - 1) {
+    const int64_t v = v0 + __ffs(m) - 1;
+    pe += (int)(rp[v + 1] - rp[v]);
+  }
   __shared__ int wsum[kThreads / kWave];
+  __shared__ int wpe[kThreads / kWave];
   __shared__ int base;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int c = __popc(mask);
@@ -241,17 +249,22 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
     const int y = __shfl_up(incl, off, kWave);
     if (lane >= off) incl += y;
   }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) pe += __shfl_xor(pe, off, kWave);
   if (lane == kWave - 1) wsum[wid] = incl;
+  if (lane == 0) wpe[wid] = pe;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int t = 0;
+    int t = 0, e = 0;
     for (int w = 0; w < kThreads / kWave; ++w) {
       const int x = wsum[w];
       wsum[w] = t;
       t += x;
+      e += wpe[w];
     }
     base = t ? atomicAdd(&ctl->npromising, t) : 0;
     if (t) atomicAdd(&ctr[blockIdx.x % kCounterSlots].nP, t);
+    if (e) atomicAdd(&ctr[blockIdx.x % kCounterSlots].pedges, e);
   }
   __syncthreads();
   int pos = base + wsum[wid] + incl - c;
@@ -379,10 +392,10 @@ void launch_mark_t(const StepArgs& a, hipStream_t s) {
     const dim3 pgrid((unsigned)((a.n + per_block - 1) / per_block));
     if (a.truncated)
       hipLaunchKernelGGL(k_promising_list<true>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
-                         a.plist, a.ctr, a.word, a.prune);
+                         a.plist, a.ctr, a.word, a.prune, a.rp);
     else
       hipLaunchKernelGGL(k_promising_list<false>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
-                         a.plist, a.ctr, a.word, a.prune);
+                         a.plist, a.ctr, a.word, a.prune, a.rp);
     const bool narrow = a.nnz < ((int64_t)1 << 32) - 64 * GW;
 #define PIRRT_MARK_ROWS(I, L)                                                                                   \
   hipLaunchKernelGGL((k_mark_rows<GW, U, I, L>), grid_for(a.n, GW), dim3(kThreads), 0, s, a.ps, a.ctl, a.plist, \

@@ -12,53 +12,58 @@ constexpr int kThreads = 256;
 // one atomic per counter and workgroup when the workgroup lies in one problem,
 // one per vertex otherwise.
 __device__ __forceinline__ void flush_counters(IterCounters* ctr, int p, bool leader, int nP, int nD,
-                                               unsigned long long edges, int changed) {
+                                               unsigned long long edges, int changed, int pedges = 0) {
   __shared__ int block_p, mixed;
-  __shared__ unsigned long long red[4];
+  __shared__ unsigned long long red[5];
   __syncthreads();  // a previous call of this workgroup may still read red
   if (threadIdx.x == 0) {
     block_p = p;
     mixed = 0;
-    red[0] = red[1] = red[2] = red[3] = 0ull;
+    red[0] = red[1] = red[2] = red[3] = red[4] = 0ull;
   }
   __syncthreads();
   if (leader && p != block_p) mixed = 1;
   __syncthreads();
   const int slot = blockIdx.x % kCounterSlots;
   if (mixed) {
-    if (leader && (nP | nD | changed)) {
+    if (leader && (nP | nD | changed | pedges)) {
       IterCounters& C = ctr[(int64_t)p * kCounterSlots + slot];
       if (nP) atomicAdd(&C.nP, nP);
       if (nD) atomicAdd(&C.nD, nD);
       if (edges) atomicAdd(&C.edges, edges);
       if (changed) atomicAdd(&C.changed, changed);
+      if (pedges) atomicAdd(&C.pedges, pedges);
     }
     return;
   }
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long a = leader ? (unsigned long long)nP : 0ull, b = leader ? (unsigned long long)nD : 0ull,
-                     c = leader ? edges : 0ull, d = leader ? (unsigned long long)changed : 0ull;
+                     c = leader ? edges : 0ull, d = leader ? (unsigned long long)changed : 0ull,
+                     e = leader ? (unsigned long long)pedges : 0ull;
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
     a += __shfl_xor(a, off, kWave);
     b += __shfl_xor(b, off, kWave);
     c += __shfl_xor(c, off, kWave);
     d += __shfl_xor(d, off, kWave);
+    e += __shfl_xor(e, off, kWave);
   }
   if (lane == 0) {
     if (a) atomicAdd(&red[0], a);
     if (b) atomicAdd(&red[1], b);
     if (c) atomicAdd(&red[2], c);
     if (d) atomicAdd(&red[3], d);
+    if (e) atomicAdd(&red[4], e);
   }
   __syncthreads();
-  if (threadIdx.x < 4 && red[threadIdx.x]) {
+  if (threadIdx.x < 5 && red[threadIdx.x]) {
     IterCounters& C = ctr[(int64_t)block_p * kCounterSlots + slot];
     const unsigned long long t = red[threadIdx.x];
     if (threadIdx.x == 0) atomicAdd(&C.nP, (int)t);
     if (threadIdx.x == 1) atomicAdd(&C.nD, (int)t);
     if (threadIdx.x == 2) atomicAdd(&C.edges, t);
     if (threadIdx.x == 3) atomicAdd(&C.changed, (int)t);
+    if (threadIdx.x == 4) atomicAdd(&C.pedges, (int)t);
   }
 }
 

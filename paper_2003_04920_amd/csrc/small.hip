@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_replan_small(int32_t n, const
 
   evaluate();
   int32_t iters = 0;
-  unsigned long long edges_sum = 0, p_sum = 0, d_sum = 0, chg_sum = 0;
+  unsigned long long edges_sum = 0, p_sum = 0, d_sum = 0, chg_sum = 0, pe_sum = 0;
   int32_t status = 0;
   for (;;) {
     const float G = prune ? g[goal] : __int_as_float(0x7f800000);
@@ -157,10 +157,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_replan_small(int32_t n, const
     }
     __syncthreads();
     // their neighbours
+    int pe = 0;
     for (int u = t; u < n; u += kSmallThreads) {
       if (!inP[u]) continue;
       const float gu = g[u];
       const int64_t a = rp[u], b = rp[u + 1];
+      pe += (int)(b - a);
       for (int64_t j0 = a; j0 < b; j0 += kRowChunk) {
         int32_t w[kRowChunk];
         float c[kRowChunk];
@@ -192,6 +194,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_replan_small(int32_t n, const
       if (inD[v]) fa[pos++] = v;
     int np_total;
     (void)block_exclusive_sum(np, wsum, &np_total);  // also a barrier after the list
+    int pe_total;
+    (void)block_exclusive_sum(pe, wsum, &pe_total);
     if (t == 0) {
       red_chg = 0;
       red_edges = 0ull;
@@ -250,6 +254,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_replan_small(int32_t n, const
     p_sum += (unsigned long long)np_total;
     d_sum += (unsigned long long)nd;
     chg_sum += (unsigned long long)changed;
+    pe_sum += (unsigned long long)pe_total;
     __syncthreads();  // every thread has read red_* before the next pass clears them
     if (changed == 0) break;
     evaluate();
@@ -276,6 +281,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_replan_small(int32_t n, const
     q.sum_P = p_sum;
     q.sum_D = d_sum;
     q.changed_total = chg_sum;
+    q.mark_edges = pe_sum;
   }
 }
 

@@ -470,7 +470,9 @@ def lookahead_example():
     P = {0, 2, 3}; the full domain is again {1, 2, 3, 4}; from 3 the offers are
     1 + 1 = 2 to 0 and 3.5 to 1, so the narrowed domain stays {2, 3}; nothing
     changes.  Totals (iterations, sum_P, sum_D, edges, changed): full mode
-    (2, 5, 8, 16, 1), narrowed (2, 5, 4, 10, 1); final g = (0, 2, 1, 0.5, 1.5)."""
+    (2, 5, 8, 16, 1), narrowed (2, 5, 4, 10, 1); final g = (0, 2, 1, 0.5, 1.5).
+    The promising rows walked to build the domain are the same in both modes:
+    deg 0 + deg 2 = 5 entries, then deg 0 + deg 2 + deg 3 = 7, so mark_edges = 12."""
     edges = [(0, 2, 1.0), (2, 1, 1.0), (0, 3, 0.5), (3, 1, 3.0), (2, 4, 0.5)]
     h = np.array([1.0, 0.0, 0.5, 1.2, 1.0], np.float32)
     parent = np.array([-1, 2, 0, 1, 2], np.int32)
@@ -488,6 +490,7 @@ def pin_lookahead_worked_example(lib):
         assert rc == 0
         got = (st["iterations"], st["sum_P"], st["sum_D"], st["edges_examined"], st["changed_total"])
         assert got == want[look], (look, got)
+        assert st["mark_edges"] == 12, (look, st["mark_edges"])
         fin = G.state()
         assert np.array_equal(fin.g, np.array([0, 2, 1, 0.5, 1.5], np.float32))
         assert np.array_equal(fin.parent, np.array([-1, 2, 0, 0, 2], np.int32))
@@ -589,7 +592,9 @@ def pin_truncated_properties(lib):
         rc1, s1 = G.replan(0, 1, h, False, truncated=True)
         rc2, s2 = H.replan(0, 1, h, False)
         assert rc1 == rc2 == 0
-        s2 = dict(s2, sum_P=s2["sum_P"] - s2["iterations"])  # the root is in every full-mode P
+        # the root is in every full-mode P (and its row is walked for the domain)
+        deg0 = int(np.diff(H.adjacency()[0])[0])
+        s2 = dict(s2, sum_P=s2["sum_P"] - s2["iterations"], mark_edges=s2["mark_edges"] - s2["iterations"] * deg0)
         assert s1 == s2, (wl.name, s1, s2)
         a, b = G.state(), H.state()
         assert np.array_equal(a.g.view(np.uint32), b.g.view(np.uint32)) and np.array_equal(a.parent, b.parent)
@@ -637,7 +642,32 @@ def pin_row_order(lib):
             assert (x == y) if isinstance(x, dict) else np.array_equal(x, y), wl.name
 
 
+def pin_mark_edges(lib):
+    """mark_edges by brute force: iteration k's promising set recomputed from the
+    state after k - 1 iterations (a Replan capped there, or the first Evaluate), in
+    binary32, and its rows' degrees summed from the adjacency."""
+    wl = W.plain_2d(samples=300, seed=3)
+    for prune in (True, False):
+        G = build_graph(lib, wl.batches)
+        h = wl.heuristic()
+        rc, st = G.replan(0, 1, h, prune)
+        assert rc == 0
+        deg = np.diff(G.adjacency()[0])
+        total = 0
+        for k in range(1, st["iterations"] + 1):
+            H = build_graph(lib, wl.batches)
+            if k == 1:
+                assert H.evaluate(0) >= 0  # the tree levels walked
+            else:
+                rc_k, _ = H.replan(0, 1, h, prune, max_iters=k - 1)
+                assert rc_k == O.ENOTCONVERGED
+            g = H.state().g
+            thr = g[1] if prune else np.float32(np.inf)
+            total += int(deg[(g + h) < thr].sum())
+        assert st["mark_edges"] == total, (prune, st["mark_edges"], total)
+
+
 PINS = [pin_golden, pin_path_fold, pin_errors, pin_lattice, pin_complete_graph, pin_insertion_local,
         pin_monotone, pin_invariants, pin_dijkstra, pin_pruned_exactness, pin_any_initial_policy,
         pin_bruteforce_small, pin_lookahead_worked_example, pin_lookahead_properties,
-        pin_truncated_worked_example, pin_truncated_properties, pin_row_order]
+        pin_truncated_worked_example, pin_truncated_properties, pin_row_order, pin_mark_edges]

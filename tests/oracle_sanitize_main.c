@@ -16,7 +16,7 @@
 
 typedef struct {
   int32_t iterations;
-  int64_t edges_examined, sum_P, sum_D, changed_total;
+  int64_t edges_examined, sum_P, sum_D, changed_total, mark_edges;
 } orc_stats;
 typedef struct orc_graph orc_graph;
 

@@ -10,7 +10,7 @@ from oracle_pins import fixtures, load_fixture
 
 pytestmark = pytest.mark.gpu
 
-STAT_KEYS = ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total")
+STAT_KEYS = ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total", "mark_edges")
 
 
 @pytest.fixture(scope="module")

@@ -16,7 +16,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-STAT_KEYS = ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total")
+STAT_KEYS = ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total", "mark_edges")
 
 
 @pytest.fixture(scope="module")

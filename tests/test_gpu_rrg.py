@@ -88,7 +88,7 @@ def test_connect_and_replan_in_batches(P):
         st = orc.state()
         assert rc == 0 and np.array_equal(gg.view(np.uint32), st.g.view(np.uint32))
         assert np.array_equal(pp, st.parent)
-        for k in ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total"):
+        for k in ("iterations", "edges_examined", "sum_P", "sum_D", "changed_total", "mark_edges"):
             assert sg[k] == so[k], (b, k)
         n_old = n
     assert np.array_equal(G.points(), opts)
