@@ -125,6 +125,9 @@ struct pirrt_graph {
   std::vector<int32_t> hslot;
   int64_t reorder_n = 0;          // vertex count at the last renumbering
   double reorder_growth = 1.25;   // renumber when n grows by this factor (0 = never)
+  // ... and only from this many vertices on: below it a Replan is bound by launch
+  // latency, not by where its rows and g values lie (PIRRT_REORDER_MIN)
+  int64_t reorder_min = 131072;
   bool clustered_order = true;    // seed clusters on top of the breadth-first order
   bool renumber_pending = false;  // batch problems added since the last renumbering
   // problems: problem i holds caller ids [pbase[i], pbase[i+1]) and the same slots
@@ -149,6 +152,7 @@ struct pirrt_graph {
   int64_t pcap = 0;
   // insertion / renumbering / translation scratch
   int32_t* add = nullptr;
+  int32_t* add0 = nullptr;  // per-slot counts of an insert's new entries (zero between inserts)
   int32_t* deg = nullptr;
   int32_t* pending = nullptr;
   float* hbuf = nullptr;
@@ -285,7 +289,7 @@ void free_vertex_arrays(pirrt_graph* G) {
   dfree(G->A, G->child_ptr); dfree(G->A, G->child); dfree(G->A, G->fr0); dfree(G->A, G->fr1); dfree(G->A, G->lvl); dfree(G->A, G->stamp);
   dfree(G->A, G->add); dfree(G->A, G->deg); dfree(G->A, G->pending); dfree(G->A, G->hbuf); dfree(G->A, G->ext_of); dfree(G->A, G->slot_of);
   dfree(G->A, G->g2); dfree(G->A, G->parent2); dfree(G->A, G->pcost2); dfree(G->A, G->ext2); dfree(G->A, G->word); dfree(G->A, G->prob);
-  dfree(G->A, G->dlist); dfree(G->A, G->tiles);
+  dfree(G->A, G->dlist); dfree(G->A, G->tiles); dfree(G->A, G->add0);
 }
 
 void forget_vertex_arrays(pirrt_graph* T) {
@@ -296,6 +300,7 @@ void forget_vertex_arrays(pirrt_graph* T) {
   T->stamp = nullptr;
   T->dlist = nullptr;
   T->tiles = nullptr;
+  T->add0 = nullptr;
   T->word = nullptr;
 }
 
@@ -319,7 +324,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(G->A, &T.deg, cap) && dalloc(G->A, &T.pending, cap) && dalloc(G->A, &T.hbuf, cap) && dalloc(G->A, &T.ext_of, cap) &&
             dalloc(G->A, &T.slot_of, cap) && dalloc(G->A, &T.g2, cap) && dalloc(G->A, &T.parent2, cap) && dalloc(G->A, &T.pcost2, cap) &&
             dalloc(G->A, &T.ext2, cap) && dalloc(G->A, &T.word, cap) && dalloc(G->A, &T.prob, cap) && dalloc(G->A, &T.dlist, cap) &&
-            dalloc(G->A, &T.tiles, cap / kTileSlots + 2);
+            dalloc(G->A, &T.tiles, cap / kTileSlots + 2) && dalloc(G->A, &T.add0, cap);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -327,6 +332,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   hipStream_t s = G->stream;
   HIP_OR_FAIL(G, hipMemsetAsync(T.child_cnt, 0, sizeof(int32_t) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.stamp, 0, (size_t)cap, s));
+  HIP_OR_FAIL(G, hipMemsetAsync(T.add0, 0, sizeof(int32_t) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.word, 0, sizeof(unsigned long long) * (size_t)cap, s));
   HIP_OR_FAIL(G, hipMemsetAsync(T.rp, 0, sizeof(int64_t) * (size_t)(cap + 1), s));
   if (G->n > 0) {
@@ -345,7 +351,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
   G->child_cnt = T.child_cnt; G->child_ptr = T.child_ptr; G->child = T.child; G->fr0 = T.fr0; G->fr1 = T.fr1;
   G->lvl = T.lvl; G->stamp = T.stamp; G->add = T.add; G->deg = T.deg; G->pending = T.pending; G->hbuf = T.hbuf;
   G->ext_of = T.ext_of; G->slot_of = T.slot_of; G->g2 = T.g2; G->parent2 = T.parent2; G->pcost2 = T.pcost2;
-  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob; G->dlist = T.dlist; G->tiles = T.tiles;
+  G->ext2 = T.ext2; G->word = T.word; G->prob = T.prob; G->dlist = T.dlist; G->tiles = T.tiles; G->add0 = T.add0;
   forget_vertex_arrays(&T);
   G->vcap = cap;
   drop_loops(G);
@@ -667,21 +673,32 @@ int renumber(pirrt_graph* G) {
 // Insertion-time policy of the n_new vertices appended after slot n_old, one
 // dependency level at a time (staged rows in brp / bcol / bslot / bcost, the new
 // adjacency built).  insert_root: the slot that becomes a root (g = 0), or -1.
-int insert_levels(pirrt_graph* G, int32_t n_new, int64_t n_old, int32_t insert_root) {
+int insert_levels(pirrt_graph* G, int32_t n_new, int64_t n_old, int32_t insert_root, const int64_t* brp,
+                  const int32_t* bcol, const float* bcost) {
   hipStream_t s = G->stream;
   // dcount[0] / dcount[1]: the frontier sizes of alternate levels; dcount[2]: vertices
   // placed.  Levels go out kLevelsPerCheck at a time (a level past the last one finds
   // an empty frontier and does nothing), then one read-back tells whether more remain.
   constexpr int kLevelsPerCheck = 4;
   HIP_OR_FAIL(G, hipMemsetAsync(G->dcount, 0, 3 * sizeof(int32_t), s));
-  launch_pending(n_new, n_old, G->brp, G->bcol, G->pending, G->fr0, &G->dcount[0], s);
+  launch_pending(n_new, n_old, brp, bcol, G->pending, G->fr0, &G->dcount[0], s);
   HIP_OR_FAIL(G, hipGetLastError());
+  if (n_new <= kInsertBlockMax) {  // a small batch: every level in one single-workgroup launch
+    launch_insert_block(&G->dcount[0], &G->dcount[2], G->fr0, G->fr1, n_old, n_new, insert_root, brp, bcol, G->bslot,
+                        bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->host->count, G->dcount, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipStreamSynchronize(s));
+    if (G->host->count[2] != n_new)
+      return fail_device(G, hipErrorUnknown, "insertion levels did not cover the batch");
+    return PIRRT_OK;
+  }
   for (int64_t level = 0;;) {
     for (int i = 0; i < kLevelsPerCheck; ++i, ++level) {
       const int cur = (int)(level & 1), nxt = cur ^ 1;
       HIP_OR_FAIL(G, hipMemsetAsync(&G->dcount[nxt], 0, sizeof(int32_t), s));
-      launch_insert_level(n_new, &G->dcount[cur], &G->dcount[2], cur ? G->fr1 : G->fr0, n_old, insert_root, G->brp,
-                          G->bcol, G->bslot, G->bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending,
+      launch_insert_level(n_new, &G->dcount[cur], &G->dcount[2], cur ? G->fr1 : G->fr0, n_old, insert_root, brp, bcol,
+                          G->bslot, bcost, G->rp, G->col, G->g, G->parent, G->pcost, G->pending,
                           nxt ? G->fr1 : G->fr0, &G->dcount[nxt], s);
       HIP_OR_FAIL(G, hipGetLastError());
     }
@@ -709,28 +726,52 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
   hipStream_t s = G->stream;
   int rc;
   int64_t nnz_b = 0;
-  if (mem_kind == PIRRT_MEM_HOST) {
-    nnz_b = row_ptr[n_new];
-  } else {
+  const int64_t n_old = G->n, n1 = G->n + n_new;
+  // Device rows of a single graph are read where they are (the call is synchronous):
+  // their entry count and their validation come back in one round trip.
+  const bool direct = mem_kind == PIRRT_MEM_DEVICE && !new_problem && col && cost;
+  const int64_t* brp = G->brp;
+  const int32_t* bcol = G->bcol;
+  const float* bcost = G->bcost;
+  int32_t bad = 0;
+  if (direct) {
+    HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
+    launch_validate_rows(n_new, n_old, 0, row_ptr, col, cost, 0, G->dflag, s, row_ptr + n_new);
+    HIP_OR_FAIL(G, hipGetLastError());
     HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->word, row_ptr + n_new, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->flag, G->dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
     nnz_b = G->host->word;
+    bad = G->host->flag;
+    if (!bad && (rc = ensure_staging(G, n_new, nnz_b))) return rc;  // the slot translation's room
+    brp = row_ptr;
+    bcol = col;
+    bcost = cost;
+  } else {
+    if (mem_kind == PIRRT_MEM_HOST) {
+      nnz_b = row_ptr[n_new];
+    } else {
+      HIP_OR_FAIL(G, hipMemcpyAsync(&G->host->word, row_ptr + n_new, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(G, hipStreamSynchronize(s));
+      nnz_b = G->host->word;
+    }
+    if (nnz_b < 0 || nnz_b > ((int64_t)1 << 40)) return fail(G, PIRRT_EINVAL, "row_ptr[n_new] out of range");
+    if (nnz_b > 0 && (!col || !cost)) return fail(G, PIRRT_EINVAL, "col or cost is NULL");
+    if ((rc = ensure_staging(G, n_new, nnz_b))) return rc;
+    brp = G->brp;
+    bcol = G->bcol;
+    bcost = G->bcost;
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->brp, row_ptr, sizeof(int64_t) * (size_t)(n_new + 1), in_kind(mem_kind), s));
+    if (nnz_b > 0) {
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->bcol, col, sizeof(int32_t) * (size_t)nnz_b, in_kind(mem_kind), s));
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->bcost, cost, sizeof(float) * (size_t)nnz_b, in_kind(mem_kind), s));
+    }
+    if (new_problem) launch_offset_ids(nnz_b, (int32_t)n_old, G->bcol, s);  // local -> global ids
+    HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
+    launch_validate_rows(n_new, n_old, new_problem ? n_old : 0, G->brp, G->bcol, G->bcost, nnz_b, G->dflag, s);
+    HIP_OR_FAIL(G, hipGetLastError());
+    if ((rc = read_flag(G, &bad))) return rc;
   }
-  if (nnz_b < 0 || nnz_b > ((int64_t)1 << 40)) return fail(G, PIRRT_EINVAL, "row_ptr[n_new] out of range");
-  if (nnz_b > 0 && (!col || !cost)) return fail(G, PIRRT_EINVAL, "col or cost is NULL");
-  if ((rc = ensure_staging(G, n_new, nnz_b))) return rc;
-  const int64_t n_old = G->n, n1 = G->n + n_new;
-  HIP_OR_FAIL(G, hipMemcpyAsync(G->brp, row_ptr, sizeof(int64_t) * (size_t)(n_new + 1), in_kind(mem_kind), s));
-  if (nnz_b > 0) {
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcol, col, sizeof(int32_t) * (size_t)nnz_b, in_kind(mem_kind), s));
-    HIP_OR_FAIL(G, hipMemcpyAsync(G->bcost, cost, sizeof(float) * (size_t)nnz_b, in_kind(mem_kind), s));
-  }
-  if (new_problem) launch_offset_ids(nnz_b, (int32_t)n_old, G->bcol, s);  // local -> global ids
-  HIP_OR_FAIL(G, hipMemsetAsync(G->dflag, 0, sizeof(int32_t), s));
-  launch_validate_rows(n_new, n_old, new_problem ? n_old : 0, G->brp, G->bcol, G->bcost, nnz_b, G->dflag, s);
-  HIP_OR_FAIL(G, hipGetLastError());
-  int32_t bad = 0;
-  if ((rc = read_flag(G, &bad))) return rc;
   if (bad) {
     std::string m = "invalid batch:";
     if (bad & 1) m += " row_ptr not 0-based / non-decreasing / bounded;";
@@ -745,9 +786,8 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
     return rc;
   }
   // new vertices take the slots after the existing ones; neighbours to slots
-  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s);
-  launch_fill_i32(n_old, n1, new_problem ? (int32_t)G->pbase.size() - 1 : 0, G->prob, s);
-  launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
+  launch_identity_ids(n_old, n1, G->ext_of, G->slot_of, s, G->prob, new_problem ? (int32_t)G->pbase.size() - 1 : 0);
+  launch_translate(nnz_b, bcol, G->slot_of, G->bslot, s);
   if (new_problem) {
     // a new problem shares no edge with the older ones: its rows are appended
     launch_append(n_new, n_old, G->nnz, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->add, G->deg, G->rp2,
@@ -755,8 +795,8 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
     HIP_OR_FAIL(G, hipGetLastError());
   } else {
     // adjacency rebuild into the spare arrays, then swap
-    launch_rebuild(n_new, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2,
-                   G->add, G->deg, G->scan_scratch, s);
+    launch_rebuild(n_new, n_old, brp, G->bslot, bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
+                   G->add0, G->deg, G->scan_scratch, s);
     HIP_OR_FAIL(G, hipGetLastError());
     std::swap(G->rp, G->rp2);
     std::swap(G->col, G->col2);
@@ -773,10 +813,10 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
     G->pbase.back() = n1;
   drop_loops(G);
   const int32_t insert_root = new_problem ? (int32_t)n_old : (n_old == 0 ? 0 : -1);
-  if ((rc = insert_levels(G, n_new, n_old, insert_root))) return rc;
+  if ((rc = insert_levels(G, n_new, n_old, insert_root, brp, bcol, bcost))) return rc;
   if (new_problem) {
     G->renumber_pending = true;
-  } else if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
+  } else if (G->reorder_growth > 0.0 && n1 >= G->reorder_min && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
     if ((rc = renumber(G))) return rc;
   }
   return PIRRT_OK;
@@ -889,7 +929,7 @@ int grow_problems(pirrt_graph* G, int32_t count, const int32_t* problems, const 
   launch_block_problems(n_old, tot, nblk, dblk, G->prob, s);
   launch_translate(nnz_b, G->bcol, G->slot_of, G->bslot, s);
   launch_rebuild(tot, n_old, G->brp, G->bslot, G->bcost, G->rp, G->col, G->cst, G->rp2, G->col2, G->cst2, G->add,
-                 G->deg, G->scan_scratch, s);
+                 G->add0, G->deg, G->scan_scratch, s);
   HIP_OR_FAIL(G, hipGetLastError());
   std::swap(G->rp, G->rp2);
   std::swap(G->col, G->col2);
@@ -898,7 +938,7 @@ int grow_problems(pirrt_graph* G, int32_t count, const int32_t* problems, const 
   G->n = n1;
   G->nnz += 2 * nnz_b;
   drop_loops(G);
-  if ((rc = insert_levels(G, tot, n_old, -1))) return rc;
+  if ((rc = insert_levels(G, tot, n_old, -1, G->brp, G->bcol, G->bcost))) return rc;
   // final caller ids, bases and host mirrors
   launch_reid(n1, n_old, nblk, dblk, G->dbase, dbase_new, G->prob, G->ext_of, G->slot_of, s);
   HIP_OR_FAIL(G, hipGetLastError());
@@ -1441,6 +1481,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   }
   const char* growth = getenv("PIRRT_REORDER_GROWTH");
   if (growth) G->reorder_growth = atof(growth);
+  const char* rmin = getenv("PIRRT_REORDER_MIN");
+  if (rmin) G->reorder_min = atoll(rmin);
   const char* ord = getenv("PIRRT_ORDER");
   if (ord) G->clustered_order = strcmp(ord, "bfs") != 0;
   const char* tr = getenv("PIRRT_TRACE");

@@ -12,8 +12,10 @@ void scan_i32_to_i32(const int32_t* in, int64_t n, int32_t* out, void* scratch, 
 
 // ---- store.hip ----
 // Neighbour ids of row i must lie in [lo_bound, n_old + i).
+// nnz_dev (nullable): read the entry count from the device (row_ptr[n_new]) instead of nnz.
 void launch_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound, const int64_t* rp, const int32_t* col,
-                          const float* cost, int64_t nnz, int* err, hipStream_t s);
+                          const float* cost, int64_t nnz, int* err, hipStream_t s,
+                          const int64_t* nnz_dev = nullptr);
 void launch_offset_ids(int64_t m, int32_t offset, int32_t* ids, hipStream_t s);
 // Growing problems of a batch: one block of appended rows per grown problem.
 struct BatchBlock {
@@ -29,9 +31,11 @@ void launch_block_problems(int64_t n_old, int32_t total, int32_t nblk, const Bat
                            hipStream_t s);
 void launch_reid(int64_t n1, int64_t n_old, int32_t nblk, const BatchBlock* blk, const int64_t* pbase_old,
                  const int64_t* pbase_new, const int32_t* prob, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
+// add0: int32 per slot, all zero on entry and on return (the per-row counts of new
+// entries are gathered there and cleared when read).
 void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
                     const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
-                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
+                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* add0, int32_t* deg, void* scan_scratch,
                     hipStream_t s);
 // Appends a block whose entries all lie inside it (a new problem of a batch): its
 // rows go after the nnz_old existing entries of rp / col / cst, which must have room
@@ -45,6 +49,13 @@ void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int3
 // insert_root: the new vertex that gets g = 0 (x_init), or -1.  The level's frontier
 // size is read on the device from *fsize (the grid covers max_size threads), and
 // *done accumulates the sizes, so several levels go out without a host round trip.
+// Every dependency level of a small batch in one single-workgroup launch (the first
+// frontier in f0, its size at fsize0; f1 the other frontier buffer).
+constexpr int32_t kInsertBlockMax = 2048;
+void launch_insert_block(const int32_t* fsize0, int32_t* done, int32_t* f0, int32_t* f1, int64_t n_old, int32_t n_new,
+                         int32_t insert_root, const int64_t* brp, const int32_t* bcol, const int32_t* bslot,
+                         const float* bcost, const int64_t* rp, const int32_t* col, float* g, int32_t* parent,
+                         float* pcost, int32_t* pending, hipStream_t s);
 void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, const int32_t* frontier,
                          int64_t n_old, int32_t insert_root, const int64_t* brp, const int32_t* bcol,
                          const int32_t* bslot, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
@@ -74,7 +85,9 @@ struct PermuteArgs {
   int32_t* slot_of;        // updated in place
   void* scan_scratch;
 };
-void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s);
+// Slots [lo, hi) take the same caller ids; with prob, they join problem `problem`.
+void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s,
+                         int32_t* prob = nullptr, int32_t problem = 0);
 void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s);
 void launch_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* a, hipStream_t s);
 // prob[s] for s < n from the problems' slot ranges (base: P + 1 device offsets).

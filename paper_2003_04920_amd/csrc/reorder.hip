@@ -30,11 +30,13 @@ inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
 }
 
 __global__ void __launch_bounds__(kThreads) k_identity_ids(int64_t lo, int64_t hi, int32_t* __restrict__ ext_of,
-                                                          int32_t* __restrict__ slot_of) {
+                                                          int32_t* __restrict__ slot_of, int32_t* __restrict__ prob,
+                                                          int32_t problem) {
   int64_t s = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= hi) return;
   ext_of[s] = (int32_t)s;
   slot_of[s] = (int32_t)s;
+  if (prob) prob[s] = problem;
 }
 
 __global__ void __launch_bounds__(kThreads) k_fill_i32(int64_t lo, int64_t hi, int32_t value, int32_t* __restrict__ a) {
@@ -399,9 +401,11 @@ __global__ void __launch_bounds__(kThreads) k_policy_from_ext(int32_t n, const i
 
 }  // namespace
 
-void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s) {
+void launch_identity_ids(int64_t lo, int64_t hi, int32_t* ext_of, int32_t* slot_of, hipStream_t s, int32_t* prob,
+                         int32_t problem) {
   if (hi > lo)
-    hipLaunchKernelGGL(k_identity_ids, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, ext_of, slot_of);
+    hipLaunchKernelGGL(k_identity_ids, dim3(blocks_for(hi - lo)), dim3(kThreads), 0, s, lo, hi, ext_of, slot_of, prob,
+                       problem);
 }
 
 void launch_translate(int64_t m, const int32_t* ids, const int32_t* slot_of, int32_t* out, hipStream_t s) {

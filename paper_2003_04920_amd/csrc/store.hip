@@ -27,13 +27,25 @@ inline unsigned blocks_for(int64_t n, int per_block = kThreads) {
 // Error bits raised by validation.
 enum { kErrRowPtr = 1, kErrCol = 2, kErrCost = 4 };
 
+// The per-row kernels of an insert give each row a group of kRowGW lanes, so a batch
+// of a thousand rows spreads over the chip instead of looping in a thousand threads.
+constexpr int kRowGW = 8;
+
 __global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound,
                                                            const int64_t* __restrict__ rp,
                                                            const int32_t* __restrict__ col,
-                                                           const float* __restrict__ cost, int64_t nnz,
+                                                           const float* __restrict__ cost, int64_t nnz_arg,
+                                                           const int64_t* __restrict__ nnz_dev,
                                                            int* __restrict__ err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kRowGW;
+  const int gl = (int)(t % kRowGW);
   if (i >= n_new) return;
+  const int64_t nnz = nnz_dev ? *nnz_dev : nnz_arg;
+  if (nnz < 0 || nnz > ((int64_t)1 << 40)) {
+    atomicOr(err, kErrRowPtr);
+    return;
+  }
   int64_t a = rp[i], b = rp[i + 1];
   int bad = 0;
   if (i == 0 && a != 0) bad |= kErrRowPtr;
@@ -42,7 +54,7 @@ __global__ void __launch_bounds__(kThreads) k_validate_rows(int32_t n_new, int64
     return;
   }
   const int64_t self = n_old + i;
-  for (int64_t j = a; j < b; ++j) {
+  for (int64_t j = a + gl; j < b; j += kRowGW) {
     int32_t c = col[j];
     uint32_t w = __float_as_uint(cost[j]);
     if ((int64_t)c < lo_bound || (int64_t)c >= self) bad |= kErrCol;
@@ -57,24 +69,29 @@ __global__ void __launch_bounds__(kThreads) k_count_new(int32_t n_new, int64_t n
                                                        const int64_t* __restrict__ brp,
                                                        const int32_t* __restrict__ bcol,
                                                        int32_t* __restrict__ add) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kRowGW;
+  const int gl = (int)(t % kRowGW);
   if (i >= n_new) return;
   int64_t a = brp[i], b = brp[i + 1];
-  if (b > a) atomicAdd(&add[n_old + i], (int)(b - a));
-  for (int64_t j = a; j < b; ++j) atomicAdd(&add[bcol[j]], 1);
+  if (gl == 0 && b > a) atomicAdd(&add[n_old + i], (int)(b - a));
+  for (int64_t j = a + gl; j < b; j += kRowGW) atomicAdd(&add[bcol[j]], 1);
 }
 
-// deg[v] = old degree + added entries; add[v] becomes the fill cursor of v's row
-// (old degree + forward length, mirrors go after it).
+// deg[v] = old degree + added entries (counted in cnt, which is cleared here); add[v]
+// becomes the fill cursor of v's row (old degree + forward length, mirrors go after
+// it).
 __global__ void __launch_bounds__(kThreads) k_degrees(int64_t n1, int64_t n_old,
                                                      const int64_t* __restrict__ rp_old,
-                                                     const int64_t* __restrict__ brp,
+                                                     const int64_t* __restrict__ brp, int32_t* __restrict__ cnt,
                                                      int32_t* __restrict__ add, int32_t* __restrict__ deg) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n1) return;
   int32_t old = v < n_old ? (int32_t)(rp_old[v + 1] - rp_old[v]) : 0;
   int32_t fwd = v >= n_old ? (int32_t)(brp[v - n_old + 1] - brp[v - n_old]) : 0;
-  deg[v] = old + add[v];
+  const int32_t c = cnt[v];
+  cnt[v] = 0;
+  deg[v] = old + c;
   add[v] = old + fwd;
 }
 
@@ -103,11 +120,13 @@ __global__ void __launch_bounds__(kThreads) k_scatter_new(int32_t n_new, int64_t
                                                          int32_t* __restrict__ cursor,
                                                          int32_t* __restrict__ col_new,
                                                          float* __restrict__ cst_new) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kRowGW;
+  const int gl = (int)(t % kRowGW);
   if (i >= n_new) return;
   const int32_t v = (int32_t)(n_old + i);
   int64_t a = brp[i], b = brp[i + 1], dst = rp_new[v];
-  for (int64_t j = a; j < b; ++j) {
+  for (int64_t j = a + gl; j < b; j += kRowGW) {
     int32_t u = bcol[j];
     float c = bcost[j];
     col_new[dst + (j - a)] = u;
@@ -119,28 +138,101 @@ __global__ void __launch_bounds__(kThreads) k_scatter_new(int32_t n_new, int64_t
 }
 
 // pending[i] = number of same-batch lower neighbours of new vertex n_old + i; the
-// ones with none start the first dependency level.
+// ones with none start the first dependency level.  Every lane of the grid reaches the
+// wave-wide reservation.
 __global__ void __launch_bounds__(kThreads) k_pending(int32_t n_new, int64_t n_old,
                                                      const int64_t* __restrict__ brp,
                                                      const int32_t* __restrict__ bcol,
                                                      int32_t* __restrict__ pending,
                                                      int32_t* __restrict__ frontier, int32_t* __restrict__ fcount) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int ready = 0;
-  if (i < n_new) {
-    int cnt = 0;
-    for (int64_t j = brp[i]; j < brp[i + 1]; ++j) cnt += (bcol[j] >= n_old);
-    pending[i] = cnt;
-    ready = cnt == 0;
-  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kRowGW;
+  const int gl = (int)(t % kRowGW);
+  int cnt = 0;
+  if (i < n_new)
+    for (int64_t j = brp[i] + gl; j < brp[i + 1]; j += kRowGW) cnt += (bcol[j] >= n_old);
+#pragma unroll
+  for (int off = kRowGW / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
+  const bool ready = i < n_new && gl == 0 && cnt == 0;
+  if (i < n_new && gl == 0) pending[i] = cnt;
   int slot = wave_reserve(fcount, ready);
   if (ready) frontier[slot] = (int32_t)(n_old + i);
 }
 
+// Extend's local relaxation of new vertices whose lower neighbours are all final, one
+// group of kInsGW lanes per vertex (every lane of the wave calls it; a group with
+// valid = false takes no part): the minimum over (g(u) + c, u, c) of the vertex's
+// forward row, u the caller's id (bcol) and g read at the storage slot (bslot), the
+// row's entries spread over the lanes and the lexicographic minimum taken with DPP.
+// kSameLaunch: g of same-batch neighbours was written earlier in this launch by
+// another wave of the workgroup, so it is read past the L1.  Then the vertex releases
+// its same-batch higher neighbours (the mirror part of its row, also spread over the
+// lanes); those whose last pending lower neighbour it was go through push().
+constexpr int kInsGW = 8;
+
+template <bool kSameLaunch, class Push>
+__device__ __forceinline__ void insert_group(bool valid, int32_t v, int64_t n_old, int32_t insert_root,
+                                             const int64_t* __restrict__ brp, const int32_t* __restrict__ bcol,
+                                             const int32_t* __restrict__ bslot, const float* __restrict__ bcost,
+                                             const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                             float* __restrict__ g, int32_t* __restrict__ parent,
+                                             float* __restrict__ pcost, int32_t* __restrict__ pending, Push push) {
+  const int gl = threadIdx.x % kInsGW;
+  const int64_t i = valid ? v - n_old : 0;
+  const int64_t a = valid ? brp[i] : 0, b = valid ? brp[i + 1] : 0;
+  const bool relax = valid && v != insert_root;
+  uint32_t bv = 0xffffffffu, bc = 0xffffffffu, be = 0xffffffffu;
+  int32_t bs = -1;
+  if (relax) {
+    for (int64_t j = a + gl; j < b; j += kInsGW) {
+      const uint32_t u = (uint32_t)bcol[j];
+      const float c = bcost[j];
+      const int32_t su = bslot[j];
+      const float gu = kSameLaunch && su >= n_old ? __hip_atomic_load(&g[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                  : g[su];
+      const uint32_t vb = __float_as_uint(add_rn(gu, c)), cb = __float_as_uint(c);
+      if (vb < bv || (vb == bv && (u < be || (u == be && cb < bc)))) {
+        bv = vb;
+        be = u;
+        bc = cb;
+        bs = su;
+      }
+    }
+  }
+  // (value, id) first, then the cost among the lanes that hold that pair
+  const unsigned long long k = ((unsigned long long)bv << 32) | be;
+  const unsigned long long km = dpp_group_min_u64<kInsGW>(k);
+  const uint32_t cm = dpp_group_min_u32<kInsGW>(k == km ? bc : 0xffffffffu);
+  const int grp = (threadIdx.x & (kWave - 1)) / kInsGW;
+  const unsigned long long wb = group_bits<kInsGW>(__ballot(k == km && bc == cm), grp);
+  const int32_t ws = __shfl(bs, grp * kInsGW + (wb ? __ffsll((long long)wb) - 1 : 0), kWave);
+  if (valid && gl == 0) {
+    if (!relax) {  // x_init of the graph (or of a new problem of a batch)
+      g[v] = 0.0f;
+      parent[v] = -1;
+      pcost[v] = 0.0f;
+    } else if (ws >= 0 && (uint32_t)(km >> 32) < 0x7f800000u) {
+      g[v] = __uint_as_float((uint32_t)(km >> 32));
+      parent[v] = ws;
+      pcost[v] = __uint_as_float(cm);
+    } else {
+      g[v] = pos_inf();
+      parent[v] = -1;
+      pcost[v] = 0.0f;
+    }
+  }
+  // release the same-batch higher neighbours (the mirror part of v's row)
+  if (valid) {
+    for (int64_t j = rp[v] + (b - a) + gl; j < rp[v + 1]; j += kInsGW) {
+      const int32_t w = col[j];
+      if (atomicSub(&pending[w - n_old], 1) == 1) push(w);
+    }
+  }
+}
+
 // One dependency level of the insertion-time policy: every vertex of the frontier
-// has all its lower neighbours final, so its local relaxation is final too.  The
-// minimum is over (g(u) + c, u, c) with u the caller's id (bcol); g is read at the
-// storage slot (bslot).  New vertices occupy slots equal to their ids.
+// has all its lower neighbours final, so its local relaxation is final too.  New
+// vertices occupy slots equal to their ids.
 __global__ void __launch_bounds__(kThreads) k_insert_level(const int32_t* __restrict__ fsize_dev,
                                                           int32_t* __restrict__ done,
                                                           const int32_t* __restrict__ frontier,
@@ -155,71 +247,93 @@ __global__ void __launch_bounds__(kThreads) k_insert_level(const int32_t* __rest
                                                           int32_t* __restrict__ pending,
                                                           int32_t* __restrict__ next, int32_t* __restrict__ ncount) {
   const int32_t fsize = *fsize_dev;  // this level's frontier (the grid covers the whole batch)
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0 && fsize > 0) atomicAdd(done, fsize);
-  if (t >= fsize) return;
-  const int32_t v = frontier[t];
-  const int64_t i = v - n_old;
-  const int64_t a = brp[i], b = brp[i + 1];
-  if (v == insert_root) {  // x_init of the graph (or of a new problem of a batch)
-    g[v] = 0.0f;
-    parent[v] = -1;
-    pcost[v] = 0.0f;
-  } else {
-    uint32_t bv = 0xffffffffu, bc = 0xffffffffu;
-    int32_t be = 0x7fffffff;
-    int64_t bj = -1;
-    for (int64_t j = a; j < b; ++j) {
-      const int32_t u = bcol[j];
-      const float c = bcost[j];
-      const uint32_t vb = __float_as_uint(add_rn(g[bslot[j]], c)), cb = __float_as_uint(c);
-      if (vb < bv || (vb == bv && (u < be || (u == be && cb < bc)))) {
-        bv = vb;
-        be = u;
-        bc = cb;
-        bj = j;
-      }
-    }
-    if (bj >= 0 && bv < 0x7f800000u) {
-      g[v] = __uint_as_float(bv);
-      parent[v] = bslot[bj];
-      pcost[v] = __uint_as_float(bc);
-    } else {
-      g[v] = pos_inf();
-      parent[v] = -1;
-      pcost[v] = 0.0f;
-    }
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kInsGW;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && fsize > 0) atomicAdd(done, fsize);
+  if ((int64_t)blockIdx.x * (blockDim.x / kInsGW) >= fsize) return;  // the whole workgroup
+  const bool valid = t < fsize;
+  insert_group<false>(valid, valid ? frontier[t] : 0, n_old, insert_root, brp, bcol, bslot, bcost, rp, col, g,
+                      parent, pcost, pending, [&](int32_t w) { next[atomicAdd(ncount, 1)] = w; });
+}
+
+// Every dependency level of a small batch in one workgroup, with a workgroup barrier
+// between levels (the frontiers alternate between f0 and f1, their sizes in LDS): a
+// batch of a few thousand vertices needs a dozen levels, each far too small for a
+// launch of its own.  fsize0 (device) is the first frontier, already in f0.  Writes the
+// number of vertices placed to *done.
+constexpr int kBlockThreads = 1024;
+
+__global__ void __launch_bounds__(kBlockThreads) k_insert_block(const int32_t* __restrict__ fsize0,
+                                                               int32_t* __restrict__ done,
+                                                               int32_t* __restrict__ f0, int32_t* __restrict__ f1,
+                                                               int64_t n_old, int32_t n_new, int32_t insert_root,
+                                                               const int64_t* __restrict__ brp,
+                                                               const int32_t* __restrict__ bcol,
+                                                               const int32_t* __restrict__ bslot,
+                                                               const float* __restrict__ bcost,
+                                                               const int64_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ col, float* __restrict__ g,
+                                                               int32_t* __restrict__ parent, float* __restrict__ pcost,
+                                                               int32_t* __restrict__ pending) {
+  constexpr int kGroups = kBlockThreads / kInsGW;
+  __shared__ int32_t size_cur, size_next;
+  if (threadIdx.x == 0) {
+    size_cur = *fsize0;
+    size_next = 0;
   }
-  // release the same-batch higher neighbours (the mirror part of v's row)
-  for (int64_t j = rp[v] + (b - a); j < rp[v + 1]; ++j) {
-    const int32_t w = col[j];
-    if (atomicSub(&pending[w - n_old], 1) == 1) next[atomicAdd(ncount, 1)] = w;
+  __syncthreads();
+  int32_t placed = 0;  // thread 0's running total
+  int32_t* cur = f0;
+  int32_t* nxt = f1;
+  for (int32_t level = 0; level <= n_new; ++level) {
+    const int32_t size = size_cur;  // the same for every thread of the workgroup
+    if (size == 0) break;
+    placed += size;
+    for (int32_t base = 0; base < size; base += kGroups) {
+      const int32_t t = base + (int32_t)(threadIdx.x / kInsGW);
+      const bool valid = t < size;
+      const int32_t v = valid ? __hip_atomic_load(&cur[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+      insert_group<true>(valid, v, n_old, insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending,
+                         [&](int32_t w) {
+                           __hip_atomic_store(&nxt[atomicAdd(&size_next, 1)], w, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                         });
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      size_cur = size_next;
+      size_next = 0;
+    }
+    __syncthreads();
+    int32_t* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
   }
+  if (threadIdx.x == 0) *done = placed;
 }
 
 }  // namespace
 
 void launch_validate_rows(int32_t n_new, int64_t n_old, int64_t lo_bound, const int64_t* rp, const int32_t* col,
-                          const float* cost, int64_t nnz, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate_rows, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, lo_bound, rp,
-                     col, cost, nnz, err);
+                          const float* cost, int64_t nnz, int* err, hipStream_t s, const int64_t* nnz_dev) {
+  hipLaunchKernelGGL(k_validate_rows, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, lo_bound, rp,
+                     col, cost, nnz, nnz_dev, err);
 }
 
 void launch_rebuild(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, const float* bcost,
                     const int64_t* rp_old, const int32_t* col_old, const float* cst_old, int64_t* rp_new,
-                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* deg, void* scan_scratch,
+                    int32_t* col_new, float* cst_new, int32_t* add, int32_t* add0, int32_t* deg, void* scan_scratch,
                     hipStream_t s) {
   const int64_t n1 = n_old + n_new;
-  hipMemsetAsync(add, 0, sizeof(int32_t) * (size_t)n1, s);
   if (n_new > 0)
-    hipLaunchKernelGGL(k_count_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add);
-  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n1)), dim3(kThreads), 0, s, n1, n_old, rp_old, brp, add, deg);
+    hipLaunchKernelGGL(k_count_new, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add0);
+  hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n1)), dim3(kThreads), 0, s, n1, n_old, rp_old, brp, add0, add, deg);
   scan_i32_to_i64(deg, n1, rp_new, scan_scratch, s);
   if (n_old > 0)
     hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(n_old * kWave)), dim3(kThreads), 0, s, n_old, rp_old,
                        col_old, cst_old, rp_new, col_new, cst_new);
   if (n_new > 0)
-    hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol,
+    hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol,
                        bcost, rp_new, add, col_new, cst_new);
 }
 
@@ -247,19 +361,27 @@ void launch_append(int32_t n_new, int64_t n_old, int64_t nnz_old, const int64_t*
                    const float* bcost, int64_t* rp, int32_t* col, float* cst, int32_t* add, int32_t* deg,
                    int64_t* tmp, void* scan_scratch, hipStream_t s) {
   hipMemsetAsync(add + n_old, 0, sizeof(int32_t) * (size_t)n_new, s);
-  hipLaunchKernelGGL(k_count_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add);
+  hipLaunchKernelGGL(k_count_new, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, add);
   hipLaunchKernelGGL(k_degrees_append, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, add, deg);
   scan_i32_to_i64(deg, n_new, tmp, scan_scratch, s);
   hipLaunchKernelGGL(k_offset_rows, dim3(blocks_for((int64_t)n_new + 1)), dim3(kThreads), 0, s, n_new, n_old, nnz_old,
                      tmp, rp);
-  hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, bcost,
+  hipLaunchKernelGGL(k_scatter_new, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, bcost,
                      rp, add, col, cst);
 }
 
 void launch_pending(int32_t n_new, int64_t n_old, const int64_t* brp, const int32_t* bcol, int32_t* pending,
                     int32_t* frontier, int32_t* fcount, hipStream_t s) {
-  hipLaunchKernelGGL(k_pending, dim3(blocks_for(n_new)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, pending,
+  hipLaunchKernelGGL(k_pending, dim3(blocks_for((int64_t)n_new * kRowGW)), dim3(kThreads), 0, s, n_new, n_old, brp, bcol, pending,
                      frontier, fcount);
+}
+
+void launch_insert_block(const int32_t* fsize0, int32_t* done, int32_t* f0, int32_t* f1, int64_t n_old, int32_t n_new,
+                         int32_t insert_root, const int64_t* brp, const int32_t* bcol, const int32_t* bslot,
+                         const float* bcost, const int64_t* rp, const int32_t* col, float* g, int32_t* parent,
+                         float* pcost, int32_t* pending, hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_block, dim3(1), dim3(kBlockThreads), 0, s, fsize0, done, f0, f1, n_old, n_new,
+                     insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending);
 }
 
 void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, const int32_t* frontier,
@@ -267,7 +389,8 @@ void launch_insert_level(int32_t max_size, const int32_t* fsize, int32_t* done, 
                          const int32_t* bslot, const float* bcost, const int64_t* rp, const int32_t* col, float* g,
                          int32_t* parent, float* pcost, int32_t* pending, int32_t* next, int32_t* ncount,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for(max_size)), dim3(kThreads), 0, s, fsize, done, frontier, n_old,
+  hipLaunchKernelGGL(k_insert_level, dim3(blocks_for((int64_t)max_size * kInsGW)), dim3(kThreads), 0, s, fsize, done,
+                     frontier, n_old,
                      insert_root, brp, bcol, bslot, bcost, rp, col, g, parent, pcost, pending, next, ncount);
 }
 

@@ -390,6 +390,7 @@ def test_lattice_ties(P, prune):
 def test_renumbering_is_invisible(P, monkeypatch):
     wl = W.batched_6d(batches=5, batch=800, seed=102)
     outs = []
+    monkeypatch.setenv("PIRRT_REORDER_MIN", "0")  # renumber small graphs too
     for growth in ("0", "1.0", "1.25"):
         monkeypatch.setenv("PIRRT_REORDER_GROWTH", growth)
         G = gpu_graph(P)
