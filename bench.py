@@ -696,32 +696,46 @@ def bench_breakeven(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream().cuda_stream
+    def timed(n_host_max, b, hd, prune=True, reps=7, skip=2):
+        """Median synchronous Replan time (ms) on a fresh handle created with
+        PIRRT_HOST_MAX = n_host_max (0: the device loop; huge: the host Replan)."""
+        if n_host_max is None:
+            os.environ.pop("PIRRT_HOST_MAX", None)
+        else:
+            os.environ["PIRRT_HOST_MAX"] = str(n_host_max)
+        G = P.Graph(stream=stream)
+        os.environ.pop("PIRRT_HOST_MAX", None)
+        G.insert_rows(b)
+        G.snapshot_save()
+        ts = []
+        for i in range(reps):
+            G.snapshot_restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = G.replan(0, 1, hd, prune)
+            ts.append(time.perf_counter() - t0)
+        return 1e3 * float(np.median(ts[skip:])), st
+
     rows = []
     for n in [int(x) for x in args.breakeven_n.split(",")]:
         wl = W.plain_2d(samples=n, seed=0)
         b = wl.batches[0]
         h = wl.heuristic(wl.n)
-        G = P.Graph(stream=stream)
-        G.insert_rows(b)
-        G.snapshot_save()
         hd = torch.from_numpy(h).to(dev)
-        ts = []
-        for i in range(7):
-            G.snapshot_restore()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, st = G.replan(0, 1, hd, True)
-            ts.append(time.perf_counter() - t0)
-        gpu_ms = 1e3 * float(np.median(ts[2:]))
+        gpu_ms, st = timed(0, b, hd)
+        host_ms, sh = timed(1 << 30, b, hd) if wl.n <= 100_000 else (None, None)
+        auto_ms, sa = timed(None, b, hd)
         O = oracle.Graph()
         assert O.insert_batch(b) == 0
         t0 = time.perf_counter()
         rc, so = O.replan(0, 1, h, True)
         cpu_ms = 1e3 * (time.perf_counter() - t0)
-        assert rc == 0 and so["edges_examined"] == st["edges_examined"]
+        assert rc == 0 and so["edges_examined"] == st["edges_examined"] == sa["edges_examined"]
         row = {"n": wl.n, "directed_edges": 2 * b.nnz, "iterations": st["iterations"],
-               "edges_examined": st["edges_examined"], "gpu_ms": round(gpu_ms, 3), "cpu_oracle_ms": round(cpu_ms, 3),
-               "speedup": round(cpu_ms / gpu_ms, 2)}
+               "edges_examined": st["edges_examined"], "gpu_ms": round(gpu_ms, 3),
+               "host_replan_ms": None if host_ms is None else round(host_ms, 3),
+               "adaptive_ms": round(auto_ms, 3), "adaptive_on_host": bool(sa["on_host"]),
+               "cpu_oracle_ms": round(cpu_ms, 3), "speedup": round(cpu_ms / gpu_ms, 2)}
         rows.append(row)
         log("breakeven: %s" % json.dumps(row))
     n0 = next((r["n"] for r in rows if r["speedup"] > 1.0), None)
@@ -754,7 +768,8 @@ def bench_breakeven(args):
         small.append(row)
         log("small configuration: %s" % json.dumps(row))
     out = {
-        "metric": "Replan time vs graph size, GPU library against the serial oracle (2D, 8 boxes)",
+        "metric": "Replan time vs graph size, GPU library against the serial oracle (2D, 8 boxes); the library's "
+                  "host Replan and its adaptive placement beside them",
         "value": n0, "unit": "vertices (break-even)", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "2D unit square, 8 boxes; n free samples in one batch, r = (ln n/n)^(1/2); one full "
@@ -871,7 +886,7 @@ def main():
     ap.add_argument("--async-n", type=int, default=100_000, help="async: free samples")
     ap.add_argument("--berrt-batches", type=int, default=100, help="berrt6d: batches")
     ap.add_argument("--berrt-batch", type=int, default=1000, help="berrt6d: free samples per batch")
-    ap.add_argument("--breakeven-n", default="100,300,1000,3000,10000,30000,100000,300000",
+    ap.add_argument("--breakeven-n", default="30,100,200,300,1000,3000,10000,30000,100000,300000",
                     help="breakeven: free samples per graph")
     ap.add_argument("--async-s", type=int, default=1000, help="async: batch size")
     ap.add_argument("--sweep-cpu-batches", type=int, default=3000,

@@ -110,7 +110,7 @@ typedef struct {
 
 typedef struct {
   int32_t iterations;     /* Improve passes, including the last one with no change */
-  int32_t reserved0;      /* 0 */
+  int32_t on_host;        /* 1 when the call replanned on the host (small graphs), else 0 */
   int64_t edges_examined; /* sum over iterations of the degrees of the Improve domain */
   int64_t sum_P;          /* sum over iterations of |promising set| */
   int64_t sum_D;          /* sum over iterations of |Improve domain| */
@@ -175,6 +175,12 @@ int pirrt_insert_batch(pirrt_graph* g, int32_t n_new, const int64_t* row_ptr, co
  *                { (parent(v), v) } (Alg. 1 output).
  *   mem_kind   : location of h, g_out and parent_out.
  *   stats      : optional.
+ * Adaptive placement (the CPU/GPU choice the paper's break-even size motivates,
+ * Sec. VI-VII): a graph of at most 512 vertices (environment PIRRT_HOST_MAX at create;
+ * 0 = always the device) replans on the calling host thread, with the same steps and
+ * the same binary32 arithmetic, so the results and counters are identical either way;
+ * stats->on_host says which ran, and its phase timings stay 0.  PIRRT_TRUNCATED always
+ * runs on the device.
  * Errors: EINVAL (root/goal out of range, bad h, PIRRT_TRUNCATED with
  * PIRRT_LOOKAHEAD), ENOTCONVERGED (cap reached; the state is a consistent policy with
  * its g -- with PIRRT_TRUNCATED, except for the stale g the mode leaves on vertices its

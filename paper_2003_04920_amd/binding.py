@@ -88,7 +88,7 @@ class pirrt_mlp_config(ctypes.Structure):
 
 
 class pirrt_stats(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("iterations", ctypes.c_int32), ("on_host", ctypes.c_int32),
                 ("edges_examined", ctypes.c_int64), ("sum_P", ctypes.c_int64), ("sum_D", ctypes.c_int64),
                 ("changed_total", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_evaluate", ctypes.c_double), ("ms_mark", ctypes.c_double), ("ms_improve", ctypes.c_double),

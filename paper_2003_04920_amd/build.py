@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpirrt.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["scan.hip", "store.hip", "reorder.hip", "evaluate.hip", "mark.hip", "improve.hip", "small.hip", "driver.hip", "capi.hip", "rrg.hip", "mlp.hip"]
+SOURCES = ["scan.hip", "store.hip", "reorder.hip", "evaluate.hip", "mark.hip", "improve.hip", "small.hip", "driver.hip", "capi.hip", "rrg.hip", "mlp.hip",
+           "host_replan.hip"]
 ARCH = os.environ.get("PIRRT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

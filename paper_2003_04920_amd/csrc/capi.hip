@@ -119,14 +119,24 @@ struct pirrt_graph {
   // further (every path gives the same bits), and L1-cached stamp reads beat device-scope
   // ones (6D 100k per-batch Replans: 23% faster); the autotuner tries both.
   bool walk_coherent = false;
+  // Single graphs up to this many vertices replan on the host (PIRRT_HOST_MAX; 0 = never)
+  int64_t host_max = 512;
+  uint64_t adj_version = 0;  // bumped whenever the adjacency or the slot order changes
+  // host copies of the slot-ordered adjacency and ids for the host Replan
+  uint64_t hm_version = ~0ull;
+  std::vector<int64_t> hm_rp;
+  std::vector<int32_t> hm_col, hm_ext;
+  std::vector<float> hm_cst;
   // storage order: ext_of[slot] = caller id, slot_of[id] = slot (host mirror hslot)
   int32_t* ext_of = nullptr;
   int32_t* slot_of = nullptr;
   std::vector<int32_t> hslot;
   int64_t reorder_n = 0;          // vertex count at the last renumbering
   double reorder_growth = 1.25;   // renumber when n grows by this factor (0 = never)
-  // ... and only from this many vertices on: below it a Replan is bound by launch
-  // latency, not by where its rows and g values lie (PIRRT_REORDER_MIN)
+  // ... and, below this many vertices, only when the batch itself brings that growth
+  // (a graph built in one or a few large inserts): a small graph growing in many small
+  // batches replans as fast in insertion order, and each renumbering costs more than it
+  // saves there (PIRRT_REORDER_MIN)
   int64_t reorder_min = 131072;
   bool clustered_order = true;    // seed clusters on top of the breadth-first order
   bool renumber_pending = false;  // batch problems added since the last renumbering
@@ -665,6 +675,7 @@ int renumber(pirrt_graph* G) {
   HIP_OR_FAIL(G, hipStreamSynchronize(s));
   G->reorder_n = n;
   G->renumber_pending = false;
+  G->adj_version++;
   G->snap_n = -1;  // a snapshot in the old order is no longer valid
   drop_loops(G);
   return PIRRT_OK;
@@ -805,6 +816,7 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
   }
   G->n = n1;
   G->nnz += 2 * nnz_b;
+  G->adj_version++;
   G->hslot.resize((size_t)n1);
   for (int64_t v = n_old; v < n1; ++v) G->hslot[(size_t)v] = (int32_t)v;
   if (new_problem)
@@ -816,7 +828,8 @@ int insert_rows(pirrt_graph* G, int32_t n_new, const int64_t* row_ptr, const int
   if ((rc = insert_levels(G, n_new, n_old, insert_root, brp, bcol, bcost))) return rc;
   if (new_problem) {
     G->renumber_pending = true;
-  } else if (G->reorder_growth > 0.0 && n1 >= G->reorder_min && (double)n1 >= G->reorder_growth * (double)G->reorder_n) {
+  } else if (G->reorder_growth > 0.0 && (double)n1 >= G->reorder_growth * (double)G->reorder_n &&
+             (n1 >= G->reorder_min || (double)n_new >= (1.0 - 1.0 / G->reorder_growth) * (double)n1)) {
     if ((rc = renumber(G))) return rc;
   }
   return PIRRT_OK;
@@ -937,6 +950,7 @@ int grow_problems(pirrt_graph* G, int32_t count, const int32_t* problems, const 
   std::swap(G->ecap, G->ecap2);
   G->n = n1;
   G->nnz += 2 * nnz_b;
+  G->adj_version++;
   drop_loops(G);
   if ((rc = insert_levels(G, tot, n_old, -1, G->brp, G->bcol, G->bcost))) return rc;
   // final caller ids, bases and host mirrors
@@ -1303,6 +1317,118 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   return PIRRT_OK;
 }
 
+// Replan of a small single graph on the host (host_replan.hip): the slot-ordered
+// adjacency is copied to the host when it changed since the last such call, the policy
+// and h are copied over, the roots re-marked as on the device, and the result goes
+// back to the device arrays (which stay the handle's state) and to the caller in
+// caller ids.
+int run_host_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, int mem_kind, bool prune,
+                    bool lookahead, float* g_out, int32_t* parent_out, pirrt_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = G->stream;
+  const int32_t n = (int32_t)G->n;
+  const size_t m = (size_t)G->nnz;
+  if (G->hm_version != G->adj_version) {
+    G->hm_rp.resize((size_t)n + 1);
+    G->hm_col.resize(m);
+    G->hm_cst.resize(m);
+    HIP_OR_FAIL(G, hipMemcpyAsync(G->hm_rp.data(), G->rp, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    if (m) {
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->hm_col.data(), G->col, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(G, hipMemcpyAsync(G->hm_cst.data(), G->cst, sizeof(float) * m, hipMemcpyDeviceToHost, s));
+    }
+    G->hm_ext.resize((size_t)n);
+    for (int32_t id = 0; id < n; ++id) G->hm_ext[(size_t)G->hslot[(size_t)id]] = id;
+  }
+  std::vector<float> g((size_t)n), pc((size_t)n), hs;
+  std::vector<int32_t> par((size_t)n);
+  HIP_OR_FAIL(G, hipMemcpyAsync(par.data(), G->parent, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(pc.data(), G->pcost, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
+  std::vector<float> hc;
+  if (h && mem_kind == PIRRT_MEM_DEVICE) {
+    hc.resize((size_t)n);
+    HIP_OR_FAIL(G, hipMemcpyAsync(hc.data(), h, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
+  }
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  G->hm_version = G->adj_version;
+  if (h) {
+    const float* hsrc = mem_kind == PIRRT_MEM_DEVICE ? hc.data() : h;
+    hs.resize((size_t)n);
+    for (int32_t id = 0; id < n; ++id) {
+      if (!(hsrc[id] >= 0.0f)) return fail(G, PIRRT_EINVAL, "h has a NaN or negative entry");
+      hs[(size_t)G->hslot[(size_t)id]] = hsrc[id];
+    }
+  }
+  // the previous roots lose their mark (in order, before the new one gets it)
+  for (const int32_t id : G->hroots) {
+    const size_t sl = (size_t)G->hslot[(size_t)id];
+    if (par[sl] == kRootMark) par[sl] = -1;
+  }
+  HostReplan p;
+  p.n = n;
+  p.rp = G->hm_rp.data();
+  p.col = G->hm_col.data();
+  p.cst = G->hm_cst.data();
+  p.ext = G->hm_ext.data();
+  p.h = h ? hs.data() : nullptr;
+  p.g = g.data();
+  p.parent = par.data();
+  p.pcost = pc.data();
+  p.root = G->hslot[(size_t)root];
+  p.goal = G->hslot[(size_t)goal];
+  p.prune = prune;
+  p.lookahead = lookahead;
+  p.cap = G->max_iters > 0 ? G->max_iters : 4 * (int64_t)n + 8;
+  HostReplanStats hst;
+  const int capped = host_replan(p, &hst);
+  // the device arrays stay the handle's state
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->g, g.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->parent, par.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->pcost, pc.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+  int rc;
+  if ((rc = ensure_pcap(G, 1))) return rc;
+  HIP_OR_FAIL(G, hipMemcpyAsync(G->droots, &root, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  G->nroots = 1;
+  G->hroots.assign(1, root);
+  // the caller's outputs in caller ids (a root reads -1)
+  std::vector<float> go;
+  std::vector<int32_t> po;
+  float* gw = g_out;
+  int32_t* pw = parent_out;
+  const bool dev = mem_kind == PIRRT_MEM_DEVICE;
+  if (dev && g_out) {
+    go.resize((size_t)n);
+    gw = go.data();
+  }
+  if (dev && parent_out) {
+    po.resize((size_t)n);
+    pw = po.data();
+  }
+  for (int32_t id = 0; id < n; ++id) {
+    const size_t sl = (size_t)G->hslot[(size_t)id];
+    if (gw) gw[id] = g[sl];
+    if (pw) pw[id] = par[sl] >= 0 ? G->hm_ext[(size_t)par[sl]] : -1;
+  }
+  if (dev && g_out) HIP_OR_FAIL(G, hipMemcpyAsync(g_out, go.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+  if (dev && parent_out)
+    HIP_OR_FAIL(G, hipMemcpyAsync(parent_out, po.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(G, hipStreamSynchronize(s));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->iterations = hst.iterations;
+    stats->edges_examined = hst.edges;
+    stats->sum_P = hst.sum_P;
+    stats->sum_D = hst.sum_D;
+    stats->changed_total = hst.changed;
+    stats->mark_edges = hst.mark_edges;
+    stats->evaluate_calls = hst.iterations;
+    stats->on_host = 1;
+    stats->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return capped ? PIRRT_ENOTCONVERGED : PIRRT_OK;
+}
+
 // Copies and validates a caller h (caller order) into slot order in hbuf.
 int stage_h(pirrt_graph* G, const float* h, int mem_kind, const float** out) {
   *out = nullptr;
@@ -1493,6 +1619,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
   if (wp && atoi(wp) >= 1) G->walk_parts = atoi(wp);
   const char* wc = getenv("PIRRT_WALK_COHERENT");
   if (wc) G->walk_coherent = atoi(wc) != 0;
+  const char* hm = getenv("PIRRT_HOST_MAX");
+  if (hm) G->host_max = atoll(hm);
   const char* gr = getenv("PIRRT_GRAPH");
   if (gr) G->use_graph = atoi(gr) != 0;
   const char* sm = getenv("PIRRT_SMALL");
@@ -1577,6 +1705,14 @@ int pirrt_replan(pirrt_graph* G, int32_t root, int32_t goal, const float* h, uin
     return fail(G, PIRRT_EINVAL, "PIRRT_TRUNCATED and PIRRT_LOOKAHEAD cannot be combined");
   if (G->n <= 0) return fail(G, PIRRT_EINVAL, "empty graph");
   if (root < 0 || root >= G->n || goal < 0 || goal >= G->n) return fail(G, PIRRT_EINVAL, "root or goal out of range");
+  if (G->n <= G->host_max && !(flags & PIRRT_TRUNCATED)) {  // small: the host finishes first
+    pirrt_stats hst;
+    rc = run_host_replan(G, root, goal, h, mem_kind, (flags & PIRRT_NO_PRUNE) == 0, (flags & PIRRT_LOOKAHEAD) != 0,
+                         g_out, parent_out, &hst);
+    if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
+    if (stats) *stats = hst;
+    return rc;
+  }
   const float* hdev = nullptr;
   if ((rc = stage_h(G, h, mem_kind, &hdev))) return rc;
   const int32_t rslot = G->hslot[(size_t)root], gslot = G->hslot[(size_t)goal];

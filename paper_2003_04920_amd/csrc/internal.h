@@ -167,6 +167,29 @@ struct WalkArgs {
 };
 void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 
+// ---- host_replan.hip ----
+// One Replan of a small graph on the host, on slot-ordered host copies (see the file).
+struct HostReplan {
+  int32_t n;
+  const int64_t* rp;   // adjacency: row offsets [n + 1], neighbour slots, costs
+  const int32_t* col;
+  const float* cst;
+  const int32_t* ext;  // caller id of each slot (tie-break key)
+  const float* h;      // slot order, or NULL (h = 0)
+  float* g;            // out
+  int32_t* parent;     // in / out (the root gets kRootMark)
+  float* pcost;        // in / out
+  int32_t root, goal;  // slots
+  bool prune, lookahead;
+  int64_t cap;         // iteration cap
+};
+struct HostReplanStats {
+  int32_t iterations;
+  int64_t edges, sum_P, sum_D, changed, mark_edges;
+};
+// 0 at the fixed point, 1 at the iteration cap (the state is consistent either way).
+int host_replan(const HostReplan& p, HostReplanStats* st);
+
 // ---- driver.hip ----
 // Also sets each problem's threshold to g(goal) as stored (+inf without pruning): the
 // threshold the truncated Evaluate reads in the first walk.

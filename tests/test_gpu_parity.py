@@ -26,6 +26,12 @@ def P():
     return P
 
 
+@pytest.fixture(autouse=True)
+def device_path(monkeypatch):
+    """These cases test the device loop: small graphs stay on the device too."""
+    monkeypatch.setenv("PIRRT_HOST_MAX", "0")
+
+
 def gpu_graph(P, **kw):
     import torch
     return P.Graph(stream=torch.cuda.current_stream().cuda_stream, **kw)
