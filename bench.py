@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 IMPROVE_SRC = os.path.join(ROOT, "paper_2003_04920_amd", "csrc", "improve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_6d_1m_traffic.txt")
 MULTI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_improve_multi512_traffic.txt")
+BATCH_BLOCKS = (2048, 1024, 4096, 8192)  # batch grid sizes, in the autotuner's order
 CALIB_BYTES = 1 << 30  # the calibration kernel reads 1 GiB and writes 1 GiB
 
 
@@ -133,7 +134,7 @@ def measured_traffic(path=TRAFFIC_FILE):
 
 
 def _short(name: str) -> str:
-    name = name.replace("pirrt::(anonymous namespace)::", "").replace("void ", "")
+    name = name.replace("pirrt::", "").replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0]
 
 
@@ -187,7 +188,56 @@ def profile_summary(paths):
             out.append("k_improve_write_bytes_per_launch: %d" % int(round(w_imp * 1024 * sw)))
             out.append("k_improve_traffic_bytes_per_launch: %d" % traffic)
             out.append("improve_src_sha256_16: %s" % source_digest())
+    for path in paths:
+        for f in sorted(glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True)):
+            out.extend(loop_windows(f))
     print("\n".join(out))
+
+
+LOOP_KERNELS = ("k_promising_list", "k_mark", "k_domain_list", "k_improve", "k_finish", "k_eval_walk",
+                "k_after_eval")
+
+
+def loop_windows(path, min_kernels=30):
+    """Replan loops in a kernel trace: maximal runs of loop kernels (any other
+    dispatch, such as a copy, ends a run).  For the last run: its span from the first
+    start to the last end, the time some kernel was running (the union of the
+    dispatch intervals) and the rest, the gaps a single persistent launch could
+    remove, with the time per kernel."""
+    with open(path) as fh:
+        ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"]))
+                    for r in csv.DictReader(fh))
+    runs, cur = [], []
+    for e in ev:
+        if e[2].split("<")[0] in LOOP_KERNELS or e[2].startswith("k_mark"):
+            cur.append(e)
+            continue
+        if len(cur) >= min_kernels:
+            runs.append(cur)
+        cur = []
+    if len(cur) >= min_kernels:
+        runs.append(cur)
+    if not runs:
+        return []
+    w = runs[-1]
+    span = w[-1][1] - w[0][0]
+    busy, last = 0, 0
+    for s0, e0, _ in w:
+        lo = max(s0, last)
+        if e0 > lo:
+            busy += e0 - lo
+        last = max(last, e0)
+    per = {}
+    for s0, e0, k in w:
+        t = per.setdefault(k, [0, 0])
+        t[0] += 1
+        t[1] += e0 - s0
+    out = ["Replan loop (%s, last of %d runs): %d dispatches, span %.3f ms, kernels running %.3f ms, "
+           "gaps %.3f ms (%.2f%%)" % (os.path.basename(path), len(runs), len(w), span / 1e6, busy / 1e6,
+                                      (span - busy) / 1e6, 100.0 * (span - busy) / max(1, span))]
+    for k, (c, t) in sorted(per.items(), key=lambda x: -x[1][1]):
+        out.append("  %-60s %6d dispatches %10.3f ms %9.2f us avg" % (k[:60], c, t / 1e6, t / 1e3 / c))
+    return out
 
 
 def bench_multi(args):
@@ -208,7 +258,8 @@ def bench_multi(args):
     specs = [W.multi_problem_spec(i) for i in range(args.problems)]
     if args.config >= 0:  # a fixed kernel configuration instead of the autotuner's choice
         os.environ["PIRRT_ROW_VARIANT"] = str(args.config % 4)
-        os.environ["PIRRT_WALK_COHERENT"] = "0" if args.config >= 4 else "1"
+        os.environ["PIRRT_WALK_COHERENT"] = "0" if (args.config // 4) % 2 else "1"
+        os.environ["PIRRT_BATCH_BLOCKS"] = str(BATCH_BLOCKS[args.config // 8])
     B = P.Batch(stream=stream)
     rrgs, hs = [], []
     torch.cuda.synchronize()
@@ -235,8 +286,9 @@ def bench_multi(args):
     goals = np.ones(len(specs), np.int32)
     t0 = time.perf_counter()
     tuned = B.tune(roots, goals, h, True) if args.config < 0 else args.config
-    log("autotuner: configuration %d (row split %d, %s-scope Evaluate stamps), %.2f s" %
-        (tuned, tuned % 4, "workgroup" if tuned >= 4 else "device", time.perf_counter() - t0))
+    log("autotuner: configuration %d (row split %d, %s-scope Evaluate stamps, %d workgroups per launch), %.2f s" %
+        (tuned, tuned % 4, "workgroup" if (tuned // 4) % 2 else "device", BATCH_BLOCKS[tuned // 8],
+         time.perf_counter() - t0))
 
     def batch_step():
         B.snapshot_restore()
@@ -892,8 +944,8 @@ def main():
     ap.add_argument("--sweep-cpu-batches", type=int, default=3000,
                     help="sweep: oracle exploitation only for cells with at most this many batches")
     ap.add_argument("--config", type=int, default=-1,
-                    help="plain6d: fixed kernel configuration 0-7 (row split + 4 x workgroup-scope stamps) instead "
-                         "of the autotuner")
+                    help="fixed kernel configuration instead of the autotuner: row split + 4 x workgroup-scope "
+                         "stamps (0-7); multi adds 8 x the index of the batch grid size in (2048, 1024, 4096, 8192)")
     ap.add_argument("--layouts", type=int, default=100, help="learned: training layouts")
     ap.add_argument("--per-layout", type=int, default=8192, help="learned: samples kept per layout")
     ap.add_argument("--epochs", type=int, default=4, help="learned: training epochs")

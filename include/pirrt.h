@@ -336,7 +336,10 @@ int64_t pirrt_batch_problem_offset(const pirrt_batch* b, int32_t problem);
 int pirrt_batch_replan(pirrt_batch* b, const int32_t* roots, const int32_t* goals, const float* h,
                        uint32_t flags, float* g_out, int32_t* parent_out, int mem_kind, pirrt_stats* stats);
 
-/* As pirrt_tune for the batch's Replan of every problem. */
+/* As pirrt_tune for the batch's Replan of every problem, with one more dimension: the
+   workgroups of the batch's grid-stride launches (2048, 1024, 4096, 8192), tried with
+   the best configuration of the others.  *config = row split + 4 x (workgroup-scope
+   stamps) + 8 x (index of the workgroup count in that list). */
 int pirrt_batch_tune(pirrt_batch* b, const int32_t* roots, const int32_t* goals, const float* h, uint32_t flags,
                      int mem_kind, int32_t* config);
 

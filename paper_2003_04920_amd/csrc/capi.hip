@@ -60,9 +60,9 @@ thread_local std::string g_create_error;
 
 // Identity of a captured loop body: every pointer and size baked into its nodes.
 struct LoopKey {
-  const void* ptrs[16];
+  const void* ptrs[17];
   int64_t n, nnz;
-  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead, truncated;
+  int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead, truncated, blocks;
   bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
 };
 
@@ -194,6 +194,7 @@ struct pirrt_graph {
   // tuning
   int32_t mid_hint = 64;
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
+  int batch_blocks = kBatchBlocks;  // batches: workgroups per grid-stride launch (autotuned)
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
   bool truncated = false;  // truncated Evaluate for the current call (PIRRT_TRUNCATED)
   LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
@@ -1010,14 +1011,16 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   if (timing) (void)hipEventRecord(G->ev[1], s);
   // a single graph's promising list (next iteration) takes the thresholds step
   if (!single)
-    launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), G->tiles, s);
+    launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), base_map(G),
+                      G->tiles, s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   LoopKey k;
   memset(&k, 0, sizeof(k));
-  const void* p[16] = {G->rp, G->col, G->cst, G->g, G->parent, G->pcost, G->stamp, G->word,
-                       G->ext_of, problem_map(G), G->ps, G->ctr, G->ctl, L.sa.h, G->child, G->lvl};
+  const void* p[17] = {G->rp,     G->col,         G->cst, G->g,   G->parent, G->pcost,  G->stamp,
+                       G->word,   G->ext_of,      problem_map(G), base_map(G), G->ps,    G->ctr,
+                       G->ctl,    L.sa.h,         G->child,       G->lvl};
   memcpy(k.ptrs, p, sizeof(p));
   k.n = G->n;
   k.nnz = G->nnz;
@@ -1032,6 +1035,7 @@ LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   k.mid = L.ea.mid_launches;
   k.lookahead = L.sa.lookahead;
   k.truncated = L.sa.truncated;
+  k.blocks = L.sa.blocks;
   return k;
 }
 
@@ -1137,6 +1141,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   sa.lookahead = G->lookahead;
   sa.truncated = G->truncated;
   sa.word = G->word;
+  sa.blocks = G->batch_blocks;
   WalkArgs& wa = L.wa;
   wa.n = n;
   wa.prob = problem_map(G);
@@ -1152,6 +1157,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.tiles = G->tiles;
   wa.truncated = G->truncated;
   wa.h = h;
+  wa.blocks = G->batch_blocks;
   EvalArgs& ea = L.ea;
   ea.n = n;
   ea.ps = G->ps;
@@ -1208,7 +1214,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   enqueue_evaluate(G, L, s);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
   if (problem_map(G))  // a single graph's first promising list takes the thresholds step
-    launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), G->tiles, s);
+    launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), base_map(G), G->tiles, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
@@ -1240,13 +1246,17 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
           agg.evaluate_calls += 1;
         }
       }
-      if (G->trace)
+      if (G->trace) {
+        int active = 0;
+        for (int32_t q = 0; q < P; ++q) active += G->hps[q].active != 0;
         fprintf(stderr,
                 "pirrt iter %d: problem 0 iterations %d edges %llu sum_P %llu sum_D %llu changed %llu; walk hops "
-                "%llu\n",
+                "%llu; problems active %d, tiles %d\n",
                 it + 1, G->hps[0].iterations, (unsigned long long)G->hps[0].edges,
                 (unsigned long long)G->hps[0].sum_P, (unsigned long long)G->hps[0].sum_D,
-                (unsigned long long)G->hps[0].changed_total, (unsigned long long)G->host->hops);
+                (unsigned long long)G->hps[0].changed_total, (unsigned long long)G->host->hops, active,
+                G->host->ctl.ntiles);
+      }
       if (!G->host->ctl.any_active) break;
       if (done_iters > cap_iters + 1) return fail_device(G, hipErrorUnknown, "Replan loop did not stop");
     }
@@ -1461,9 +1471,12 @@ int stage_h(pirrt_graph* G, const float* h, int mem_kind, const float** out) {
 // walk's Evaluate stamps (device or workgroup) -- each from the same policy, the
 // fastest kept.  Each configuration runs twice in a row: the first run loads its
 // kernels and launches them directly, the second repeats its arguments, so it runs
-// from captured graphs as repeated Replans do, and is the one timed.  The policy and
-// the root marks are restored at the end.
+// from captured graphs as repeated Replans do, and is the one timed.  A batch then
+// tries the workgroup count of its grid-stride launches (kTuneBlocks, the first one
+// being the default) with the best of those, one dimension after the other.  The
+// policy and the root marks are restored at the end.
 constexpr int kTuneConfigs = kRowVariants * 2;
+constexpr int kTuneBlocks[4] = {kBatchBlocks, 1024, 4096, 8192};
 
 int tune(pirrt_graph* G, int32_t P, const int32_t* rid, const int32_t* rs, const int32_t* gs, const float* hdev,
          bool prune, int32_t* config) {
@@ -1489,23 +1502,35 @@ int tune(pirrt_graph* G, int32_t P, const int32_t* rid, const int32_t* rs, const
   };
   double best = 1e300;
   int bestc = 0;
-  for (int c = 0; c < kTuneConfigs; ++c) {
+  auto apply = [&](int c) {
     G->row_variant = c % kRowVariants;
-    G->walk_coherent = c / kRowVariants == 0;
+    G->walk_coherent = (c / kRowVariants) % 2 == 0;
+    G->batch_blocks = kTuneBlocks[c / kTuneConfigs];
+  };
+  auto trial = [&](int c) -> int {
+    apply(c);
     for (int pass = 0; pass < 2; ++pass) {  // the second run repeats the first: graphs
-      if ((rc = restore())) return rc;
+      int r;
+      if ((r = restore())) return r;
       const auto t0 = std::chrono::steady_clock::now();
-      rc = run_replan(G, P, rid, rs, gs, hdev, prune, false, nullptr);
-      if (rc != PIRRT_OK && rc != PIRRT_ENOTCONVERGED) return rc;
+      r = run_replan(G, P, rid, rs, gs, hdev, prune, false, nullptr);
+      if (r != PIRRT_OK && r != PIRRT_ENOTCONVERGED) return r;
       const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       if (pass == 1 && ms < best) {
         best = ms;
         bestc = c;
       }
     }
+    return PIRRT_OK;
+  };
+  for (int c = 0; c < kTuneConfigs; ++c)
+    if ((rc = trial(c))) return rc;
+  if (G->batched) {  // single graphs size their grids to the work
+    const int row = bestc;
+    for (int b = 1; b < 4; ++b)
+      if ((rc = trial(row + kTuneConfigs * b))) return rc;
   }
-  G->row_variant = bestc % kRowVariants;
-  G->walk_coherent = bestc / kRowVariants == 0;
+  apply(bestc);
   if ((rc = restore())) return rc;
   if (config) *config = bestc;
   return PIRRT_OK;
@@ -1630,6 +1655,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     G->fault_launch = strcmp(fi, "launch") == 0;
     G->fault_alloc = strcmp(fi, "alloc") == 0;
   }
+  const char* bb = getenv("PIRRT_BATCH_BLOCKS");
+  if (bb && atoi(bb) > 0) G->batch_blocks = atoi(bb);
   const char* variant = getenv("PIRRT_ROW_VARIANT");
   if (variant) {
     int v = atoi(variant);

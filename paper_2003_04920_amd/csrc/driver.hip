@@ -150,22 +150,72 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
 // g(x_goal), +inf without pruning, -inf for a problem that has stopped).
 // In a batch it also lists the tiles that overlap a problem still iterating (a tile
 // spans at most a few problems: each holds thousands of slots).
-__global__ void k_after_eval(int32_t P, ProblemState* __restrict__ ps, const float* __restrict__ g, int prune,
-                             LoopCtl* __restrict__ ctl, int32_t n, const int32_t* __restrict__ prob,
-                             int32_t* __restrict__ tiles) {
+constexpr int kAfterEvalThreads = 1024;
+constexpr int kAfterEvalWords = 8192;  // tile bitmap in LDS: up to 262,144 tiles (2^30 slots)
+constexpr int kWordsPerThread = kAfterEvalWords / kAfterEvalThreads;
+
+__global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, ProblemState* __restrict__ ps,
+                                                                 const float* __restrict__ g, int prune,
+                                                                 LoopCtl* __restrict__ ctl, int32_t n,
+                                                                 const int32_t* __restrict__ prob,
+                                                                 const int64_t* __restrict__ base,
+                                                                 int32_t* __restrict__ tiles) {
   __shared__ int any, count;
+  __shared__ uint32_t bits[kAfterEvalWords];
+  __shared__ int wsum[kAfterEvalThreads / kWave + 1];
+  const int32_t T = prob ? (int32_t)(((int64_t)n + kTileSlots - 1) / kTileSlots) : 0;
+  // a problem's slots are the range [base[p], base[p + 1]), so its tiles are a range
+  // too: the active problems set their tiles' bits, and the list is read off the
+  // bitmap in tile order
+  const bool bitmap = T <= kAfterEvalWords * 32;
   if (threadIdx.x == 0) {
     any = 0;
     count = 0;
   }
+  for (int w = threadIdx.x; w < kAfterEvalWords; w += kAfterEvalThreads) bits[w] = 0u;
   __syncthreads();
   for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
     ProblemState& s = ps[i];
-    if (s.active) any = 1;
-    s.thr = s.active ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
+    const bool a = s.active != 0;
+    if (a) any = 1;
+    s.thr = a ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
+    if (prob && bitmap && a && base[i + 1] > base[i]) {
+      const int32_t t0 = (int32_t)(base[i] / kTileSlots), t1 = (int32_t)((base[i + 1] - 1) / kTileSlots);
+      for (int32_t t = t0; t <= t1; ++t) atomicOr(&bits[t >> 5], 1u << (t & 31));
+    }
   }
-  if (prob) {
-    const int32_t T = (n + kTileSlots - 1) / kTileSlots;
+  __syncthreads();
+  if (prob && bitmap) {
+    // each thread takes kWordsPerThread consecutive words; a block scan places them
+    const int w0 = threadIdx.x * kWordsPerThread;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k) c += __popc(bits[w0 + k]);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int w = 0; w < kAfterEvalThreads / kWave; ++w) {
+        const int x = wsum[w];
+        wsum[w] = t;
+        t += x;
+      }
+      count = t;
+    }
+    __syncthreads();
+    int pos = wsum[wid] + incl - c;
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k)
+      for (uint32_t m = bits[w0 + k]; m; m &= m - 1) tiles[pos++] = (w0 + k) * 32 + __ffs(m) - 1;
+  } else if (prob) {
+    // more tiles than the bitmap holds: test each tile's first and last problem
     for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
       const int64_t s0 = (int64_t)t * kTileSlots;
       const int64_t s1 = (s0 + kTileSlots < n ? s0 + kTileSlots : n) - 1;
@@ -206,8 +256,9 @@ void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl,
 }
 
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
-                       const int32_t* prob, int32_t* tiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(1024), 0, s, P, ps, g, prune, ctl, n, prob, tiles);
+                       const int32_t* prob, const int64_t* base, int32_t* tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(kAfterEvalThreads), 0, s, P, ps, g, prune, ctl, n, prob, base,
+                     tiles);
 }
 
 }  // namespace pirrt

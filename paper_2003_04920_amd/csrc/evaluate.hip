@@ -329,7 +329,7 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
     if (hi <= lo && k > 0) break;
     // batches launch whole tiles (the live ones are picked on the device)
     const int64_t units = (((int64_t)a.n + kTileSlots - 1) / kTileSlots) * (kTileSlots / kWalkThreads);
-    const dim3 grid(a.prob ? (unsigned)(units < kBatchBlocks ? (units > 0 ? units : 1) : kBatchBlocks)
+    const dim3 grid(a.prob ? (unsigned)(units < a.blocks ? (units > 0 ? units : 1) : a.blocks)
                            : blocks_for(hi - lo, kWalkThreads));
 #define PIRRT_WALK(H, C, B)                                                                                \
   hipLaunchKernelGGL((k_eval_walk<H, C, B, false>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \

@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
 
 template <int GW, int U, bool B, bool T>
 void launch_improve_t(const StepArgs& a, hipStream_t s) {
-  const dim3 grid = B ? batch_grid(a.n, kThreads / GW) : grid_for(a.n, GW);
+  const dim3 grid = B ? batch_grid(a.n, kThreads / GW, a.blocks) : grid_for(a.n, GW);
   if (a.nnz < ((int64_t)1 << 32) - 64 * GW)
     hipLaunchKernelGGL((k_improve<GW, U, uint32_t, B, T>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g,
                        a.rp, a.col, a.cst, a.dlist, a.ext_of, a.parent, a.pcost, a.ctr);

@@ -164,6 +164,7 @@ struct WalkArgs {
   // fl(g + h) < ps[0].thr are visited; unvisited vertices keep their g.
   bool truncated;
   const float* h;          // nullable (h = 0)
+  int blocks;              // batches: workgroups of the grid-stride launch
 };
 void launch_eval_walk(const WalkArgs& a, hipStream_t s);
 
@@ -203,11 +204,12 @@ void launch_replan_init_single(ProblemState* ps, int32_t root, int32_t goal, int
                                IterCounters* ctr, LoopCtl* ctl, const float* g, int prune, hipStream_t s);
 // single: one graph (P == 1, no problem map); see launch_after_eval.
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s);
-// prob / tiles: a batch's problem map and the active tile list it rebuilds (NULL
-// for a single graph).  Only batches launch it: a single graph's promising list does
-// the same work for its one problem at the start of the next iteration.
+// prob / base / tiles: a batch's problem map, its problems' slot ranges (P + 1
+// offsets) and the active tile list it rebuilds (NULL for a single graph).  Only
+// batches launch it: a single graph's promising list does the same work for its one
+// problem at the start of the next iteration.
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
-                       const int32_t* prob, int32_t* tiles, hipStream_t s);
+                       const int32_t* prob, const int64_t* base, int32_t* tiles, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
@@ -235,6 +237,7 @@ struct StepArgs {
   // the walk stamps), and Improve counts a switch only when it changes the policy.
   bool truncated;
   const unsigned long long* word;  // the walk stamps
+  int blocks;                // batches: workgroups of each grid-stride launch
 };
 constexpr int kRowVariants = 4;
 // One small graph (n <= kSmallMax vertices; the single workgroup is faster than the

@@ -138,15 +138,23 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
       if (wrap && sv != 0) stamp[v0 + i] = 0;
     }
   }
-  if (prob) {
-    for (uint32_t m = mask; m; m &= m - 1) {
-      const int i = __ffs(m) - 1;
-      if (!ps[prob[v0 + i]].active) mask &= ~(1u << i);
+  if (prob && mask) {
+    // the thread's slots nearly always belong to one problem: one flag to read
+    const int64_t last = v0 + kListPer <= n ? v0 + kListPer - 1 : n - 1;
+    const int32_t pa = prob[v0], pb = prob[last];
+    if (pa == pb) {
+      if (!ps[pa].active) mask = 0;
+    } else {
+      for (uint32_t m = mask; m; m &= m - 1) {
+        const int i = __ffs(m) - 1;
+        if (!ps[prob[v0 + i]].active) mask &= ~(1u << i);
+      }
     }
   }
   // workgroup exclusive scan of the per-thread counts
   __shared__ int wsum[kThreads / kWave];
-  __shared__ int base;
+  __shared__ int base, total;
+  __shared__ int32_t staged[kThreads * kListPer];  // the unit's list, written out coalesced
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   __syncthreads();  // the previous unit's readers of wsum / base are done
   const int c = __popc(mask);
@@ -166,14 +174,17 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
       t += x;
     }
     base = t ? atomicAdd(&ctl->ndomain, t) : 0;
+    total = t;
   }
   __syncthreads();
-  int pos = base + wsum[wid] + incl - c;
+  int pos = wsum[wid] + incl - c;
   while (mask) {
     const int i = __ffs(mask) - 1;
     mask &= mask - 1;
-    dlist[pos++] = (int32_t)(v0 + i);
+    staged[pos++] = (int32_t)(v0 + i);
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < total; j += kThreads) dlist[base + j] = staged[j];
   }
 }
 
@@ -232,15 +243,34 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
     for (int i = 0; i < kListPer && v0 + i < n; ++i)
       if (add_rn(g[v0 + i], h ? h[v0 + i] : 0.0f) < G) mask |= 1u << i;
   }
-  // the degrees of the listed rows (the rows the mark walks), for the counters
+  // the degrees of the listed rows (the rows the mark walks), for the counters: the
+  // thread's kListPer + 1 row offsets in one batch of 16-byte loads
   int pe = 0;
-  for (uint32_t m = mask; m; m &= m - 1) {
-    const int64_t v = v0 + __ffs(m) - 1;
-    pe += (int)(rp[v + 1] - rp[v]);
+  if (mask) {
+    if (v0 + kListPer <= n) {
+      const longlong2* r2 = reinterpret_cast<const longlong2*>(rp + v0);
+      int64_t r[kListPer + 1];
+#pragma unroll
+      for (int q = 0; q < kListPer / 2; ++q) {
+        const longlong2 t = r2[q];
+        r[2 * q] = t.x;
+        r[2 * q + 1] = t.y;
+      }
+      r[kListPer] = rp[v0 + kListPer];
+#pragma unroll
+      for (int i = 0; i < kListPer; ++i)
+        if (mask & (1u << i)) pe += (int)(r[i + 1] - r[i]);
+    } else {
+      for (uint32_t m = mask; m; m &= m - 1) {
+        const int64_t v = v0 + __ffs(m) - 1;
+        pe += (int)(rp[v + 1] - rp[v]);
+      }
+    }
   }
   __shared__ int wsum[kThreads / kWave];
   __shared__ int wpe[kThreads / kWave];
-  __shared__ int base;
+  __shared__ int base, total;
+  __shared__ int32_t staged[kThreads * kListPer];  // the workgroup's list, written out coalesced
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int c = __popc(mask);
   int incl = c;
@@ -263,17 +293,20 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
       e += wpe[w];
     }
     base = t ? atomicAdd(&ctl->npromising, t) : 0;
+    total = t;
     if (t) atomicAdd(&ctr[blockIdx.x % kCounterSlots].nP, t);
     if (e) atomicAdd(&ctr[blockIdx.x % kCounterSlots].pedges, e);
   }
   __syncthreads();
-  int pos = base + wsum[wid] + incl - c;
+  int pos = wsum[wid] + incl - c;
   while (mask) {
     const int i = __ffs(mask) - 1;
     mask &= mask - 1;
     stamp[v0 + i] = ep;
-    plist[pos++] = (int32_t)(v0 + i);
+    staged[pos++] = (int32_t)(v0 + i);
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < total; j += kThreads) plist[base + j] = staged[j];
 }
 
 
@@ -408,7 +441,7 @@ void launch_mark_t(const StepArgs& a, hipStream_t s) {
 #undef PIRRT_MARK_ROWS
     return;
   }
-  const dim3 grid = batch_grid(a.n, kThreads / GW);
+  const dim3 grid = batch_grid(a.n, kThreads / GW, a.blocks);
 #define PIRRT_MARK(I, L)                                                                                         \
   hipLaunchKernelGGL((k_mark<GW, U, I, B, L>), grid, dim3(kThreads), 0, s, a.n, a.prob, a.ps, a.ctl, a.g, a.h, a.rp, \
                      a.col, a.cst, a.stamp, a.ctr, a.tiles)
@@ -452,7 +485,7 @@ void launch_count_promising(int64_t first, int64_t count, int32_t goal_slot, con
 void launch_domain_list(const StepArgs& a, hipStream_t s) {
   const int64_t per_block = (int64_t)kThreads * kListPer;
   static_assert(kThreads * kListPer == kTileSlots, "one domain-list workgroup per tile");
-  const dim3 grid = a.prob ? batch_grid(a.n, (int)per_block) : dim3((unsigned)((a.n + per_block - 1) / per_block));
+  const dim3 grid = a.prob ? batch_grid(a.n, (int)per_block, a.blocks) : dim3((unsigned)((a.n + per_block - 1) / per_block));
   hipLaunchKernelGGL(k_domain_list, grid, dim3(kThreads), 0, s, a.n, a.ctl, a.stamp, a.dlist, a.prob, a.ps,
                      a.tiles);
 }

@@ -72,11 +72,12 @@ inline dim3 grid_for(int64_t n, int gw) {
   return dim3((unsigned)(b > 0 ? b : 1));
 }
 
-// Batches use a fixed grid that strides over the live work.
-inline dim3 batch_grid(int64_t n, int per_block) {
+// Batches use a fixed grid of `blocks` workgroups (at most one per work unit) that
+// strides over the live work.
+inline dim3 batch_grid(int64_t n, int per_block, int blocks) {
   const int64_t T = (n + kTileSlots - 1) / kTileSlots;
   const int64_t units = T * (kTileSlots / per_block);
-  return dim3((unsigned)(units < kBatchBlocks ? (units > 0 ? units : 1) : kBatchBlocks));
+  return dim3((unsigned)(units < blocks ? (units > 0 ? units : 1) : blocks));
 }
 
 }  // namespace rows

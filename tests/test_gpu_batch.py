@@ -251,7 +251,7 @@ def test_batch_tune(P):
     probs = problem_set()[:6]
     B = build(P, probs)
     cfg = B.tune([p.root for p in probs], [p.goal for p in probs], full_h(probs))
-    assert 0 <= cfg < 8
+    assert 0 <= cfg < 32  # row split + 4 x stamp scope + 8 x grid-size index
     g, parent, stats = B.replan([p.root for p in probs], [p.goal for p in probs], full_h(probs))
     off = B.offsets
     for i, pr in enumerate(probs):
@@ -259,6 +259,22 @@ def test_batch_tune(P):
         check_problem("tuned", g, parent, off[i], pr, fin.g, fin.parent)
         for k in STAT_KEYS:
             assert stats[i][k] == st[k], (pr.name, k)
+
+
+@pytest.mark.parametrize("blocks", [1, 7, 1024, 8192])
+def test_batch_grid_sizes(P, monkeypatch, blocks):
+    """The batch kernels stride over the live work with any number of workgroups,
+    down to one: the results and counters stay the oracle's."""
+    monkeypatch.setenv("PIRRT_BATCH_BLOCKS", str(blocks))
+    probs = problem_set()
+    B = build(P, probs)
+    g, parent, stats = B.replan([p.root for p in probs], [p.goal for p in probs], full_h(probs))
+    off = B.offsets
+    for i, pr in enumerate(probs):
+        _, rc, st, fin = oracle_run(pr)
+        check_problem("blocks %d" % blocks, g, parent, off[i], pr, fin.g, fin.parent)
+        for k in STAT_KEYS:
+            assert stats[i][k] == st[k], (pr.name, k, blocks)
 
 
 def test_batch_phase_timing(P):
