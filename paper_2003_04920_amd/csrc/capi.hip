@@ -63,6 +63,7 @@ struct LoopKey {
   const void* ptrs[17];
   int64_t n, nnz;
   int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead, truncated, blocks;
+  int32_t bitmap_tiles;
   bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
 };
 
@@ -195,6 +196,7 @@ struct pirrt_graph {
   int32_t mid_hint = 64;
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
   int batch_blocks = kBatchBlocks;  // batches: workgroups per grid-stride launch (autotuned)
+  int32_t bitmap_tiles = INT32_MAX;  // batches: tile lists from the bitmap up to this many tiles
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
   bool truncated = false;  // truncated Evaluate for the current call (PIRRT_TRUNCATED)
   LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
@@ -1012,7 +1014,7 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   // a single graph's promising list (next iteration) takes the thresholds step
   if (!single)
     launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), base_map(G),
-                      G->tiles, s);
+                      G->tiles, G->bitmap_tiles, s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
@@ -1036,6 +1038,7 @@ LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   k.lookahead = L.sa.lookahead;
   k.truncated = L.sa.truncated;
   k.blocks = L.sa.blocks;
+  k.bitmap_tiles = G->bitmap_tiles;
   return k;
 }
 
@@ -1214,7 +1217,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   enqueue_evaluate(G, L, s);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
   if (problem_map(G))  // a single graph's first promising list takes the thresholds step
-    launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), base_map(G), G->tiles, s);
+    launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), base_map(G), G->tiles,
+                      G->bitmap_tiles, s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
@@ -1655,6 +1659,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     G->fault_launch = strcmp(fi, "launch") == 0;
     G->fault_alloc = strcmp(fi, "alloc") == 0;
   }
+  const char* tb = getenv("PIRRT_TILE_BITMAP");
+  if (tb) G->bitmap_tiles = atoi(tb) < 0 ? 0 : atoi(tb);
   const char* bb = getenv("PIRRT_BATCH_BLOCKS");
   if (bb && atoi(bb) > 0) G->batch_blocks = atoi(bb);
   const char* variant = getenv("PIRRT_ROW_VARIANT");

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
                                                                  LoopCtl* __restrict__ ctl, int32_t n,
                                                                  const int32_t* __restrict__ prob,
                                                                  const int64_t* __restrict__ base,
-                                                                 int32_t* __restrict__ tiles) {
+                                                                 int32_t* __restrict__ tiles, int32_t bitmap_tiles) {
   __shared__ int any, count;
   __shared__ uint32_t bits[kAfterEvalWords];
   __shared__ int wsum[kAfterEvalThreads / kWave + 1];
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
   // a problem's slots are the range [base[p], base[p + 1]), so its tiles are a range
   // too: the active problems set their tiles' bits, and the list is read off the
   // bitmap in tile order
-  const bool bitmap = T <= kAfterEvalWords * 32;
+  const bool bitmap = T <= bitmap_tiles && T <= kAfterEvalWords * 32;
   if (threadIdx.x == 0) {
     any = 0;
     count = 0;
@@ -256,9 +256,10 @@ void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl,
 }
 
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
-                       const int32_t* prob, const int64_t* base, int32_t* tiles, hipStream_t s) {
+                       const int32_t* prob, const int64_t* base, int32_t* tiles, int32_t bitmap_tiles,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(kAfterEvalThreads), 0, s, P, ps, g, prune, ctl, n, prob, base,
-                     tiles);
+                     tiles, bitmap_tiles);
 }
 
 }  // namespace pirrt

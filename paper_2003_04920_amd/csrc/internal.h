@@ -205,11 +205,14 @@ void launch_replan_init_single(ProblemState* ps, int32_t root, int32_t goal, int
 // single: one graph (P == 1, no problem map); see launch_after_eval.
 void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl, bool single, hipStream_t s);
 // prob / base / tiles: a batch's problem map, its problems' slot ranges (P + 1
-// offsets) and the active tile list it rebuilds (NULL for a single graph).  Only
-// batches launch it: a single graph's promising list does the same work for its one
-// problem at the start of the next iteration.
+// offsets) and the active tile list it rebuilds (NULL for a single graph).  Up to
+// bitmap_tiles tiles (and the LDS bitmap's capacity) the list is read off a tile
+// bitmap; beyond, each tile's first and last problem are looked up.  Only batches
+// launch it: a single graph's promising list does the same work for its one problem at
+// the start of the next iteration.
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
-                       const int32_t* prob, const int64_t* base, int32_t* tiles, hipStream_t s);
+                       const int32_t* prob, const int64_t* base, int32_t* tiles, int32_t bitmap_tiles,
+                       hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {

@@ -277,6 +277,22 @@ def test_batch_grid_sizes(P, monkeypatch, blocks):
             assert stats[i][k] == st[k], (pr.name, k, blocks)
 
 
+@pytest.mark.parametrize("bitmap_tiles", [0])
+def test_batch_tile_list_without_bitmap(P, monkeypatch, bitmap_tiles):
+    """The active tile list taken tile by tile (the path for batches with more tiles
+    than the LDS bitmap holds) gives the oracle's results and counters too."""
+    monkeypatch.setenv("PIRRT_TILE_BITMAP", str(bitmap_tiles))
+    probs = problem_set()
+    B = build(P, probs)
+    g, parent, stats = B.replan([p.root for p in probs], [p.goal for p in probs], full_h(probs))
+    off = B.offsets
+    for i, pr in enumerate(probs):
+        _, rc, st, fin = oracle_run(pr)
+        check_problem("tile list %d" % bitmap_tiles, g, parent, off[i], pr, fin.g, fin.parent)
+        for k in STAT_KEYS:
+            assert stats[i][k] == st[k], (pr.name, k, bitmap_tiles)
+
+
 def test_batch_phase_timing(P):
     """With timing on, every problem's entry holds the batch's phase times; the
     results stay those of the oracle."""
