@@ -63,7 +63,7 @@ struct LoopKey {
   const void* ptrs[17];
   int64_t n, nnz;
   int32_t P, prune, variant, walk_parts, walk_coherent, eval_levels, has_h, iters, mid, lookahead, truncated, blocks;
-  int32_t bitmap_tiles;
+  int32_t bitmap_tiles, walk_rank;
   bool operator==(const LoopKey& o) const { return memcmp(this, &o, sizeof(LoopKey)) == 0; }
 };
 
@@ -197,6 +197,7 @@ struct pirrt_graph {
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
   int batch_blocks = kBatchBlocks;  // batches: workgroups per grid-stride launch (autotuned)
   int32_t bitmap_tiles = INT32_MAX;  // batches: tile lists from the bitmap up to this many tiles
+  bool walk_rank = true;  // batches: the walk takes the active tiles by their rank inside their problem
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
   bool truncated = false;  // truncated Evaluate for the current call (PIRRT_TRUNCATED)
   LoopKey prev_key;          // loop arguments of the previous Replan (graphs when they repeat)
@@ -337,7 +338,7 @@ int ensure_vcap(pirrt_graph* G, int64_t need) {
             dalloc(G->A, &T.deg, cap) && dalloc(G->A, &T.pending, cap) && dalloc(G->A, &T.hbuf, cap) && dalloc(G->A, &T.ext_of, cap) &&
             dalloc(G->A, &T.slot_of, cap) && dalloc(G->A, &T.g2, cap) && dalloc(G->A, &T.parent2, cap) && dalloc(G->A, &T.pcost2, cap) &&
             dalloc(G->A, &T.ext2, cap) && dalloc(G->A, &T.word, cap) && dalloc(G->A, &T.prob, cap) && dalloc(G->A, &T.dlist, cap) &&
-            dalloc(G->A, &T.tiles, cap / kTileSlots + 2) && dalloc(G->A, &T.add0, cap);
+            dalloc(G->A, &T.tiles, 2 * (cap / kTileSlots + 2)) && dalloc(G->A, &T.add0, cap);
   if (!ok) {
     free_vertex_arrays(&T);
     return fail(G, PIRRT_ENOMEM, "device allocation for vertex storage failed");
@@ -542,6 +543,10 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 
 int32_t* problem_map(pirrt_graph* G) { return G->batched ? G->prob : nullptr; }
 const int64_t* base_map(pirrt_graph* G) { return G->batched ? G->dbase : nullptr; }
+// The second half of the tile array: the walk's order of the active tiles.
+int32_t* walk_tiles(pirrt_graph* G) {
+  return G->batched && G->walk_rank ? G->tiles + (G->vcap / kTileSlots + 2) : nullptr;
+}
 
 // Copies the policy out in caller order (device outputs are written directly;
 // host outputs go through device staging).  In a batch, parents are local ids.
@@ -1014,7 +1019,7 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   // a single graph's promising list (next iteration) takes the thresholds step
   if (!single)
     launch_after_eval(L.P, G->ps, G->g, L.prune ? 1 : 0, G->ctl, (int32_t)G->n, problem_map(G), base_map(G),
-                      G->tiles, G->bitmap_tiles, s);
+                      G->tiles, G->bitmap_tiles, walk_tiles(G), s);
 }
 
 LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
@@ -1039,6 +1044,7 @@ LoopKey loop_key(pirrt_graph* G, const LoopArgs& L, int iters) {
   k.truncated = L.sa.truncated;
   k.blocks = L.sa.blocks;
   k.bitmap_tiles = G->bitmap_tiles;
+  k.walk_rank = G->walk_rank;
   return k;
 }
 
@@ -1157,7 +1163,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.hops = G->trace ? G->dhops : nullptr;
   wa.parts = G->walk_parts;
   wa.coherent = G->walk_coherent;
-  wa.tiles = G->tiles;
+  wa.tiles = walk_tiles(G) ? walk_tiles(G) : G->tiles;
   wa.truncated = G->truncated;
   wa.h = h;
   wa.blocks = G->batch_blocks;
@@ -1218,7 +1224,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
   if (problem_map(G))  // a single graph's first promising list takes the thresholds step
     launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), base_map(G), G->tiles,
-                      G->bitmap_tiles, s);
+                      G->bitmap_tiles, walk_tiles(G), s);
   HIP_OR_FAIL(G, hipGetLastError());
   if (timing) {
     HIP_OR_FAIL(G, hipStreamSynchronize(s));
@@ -1659,6 +1665,8 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     G->fault_launch = strcmp(fi, "launch") == 0;
     G->fault_alloc = strcmp(fi, "alloc") == 0;
   }
+  const char* wr = getenv("PIRRT_WALK_ORDER");
+  if (wr) G->walk_rank = strcmp(wr, "tiles") != 0;
   const char* tb = getenv("PIRRT_TILE_BITMAP");
   if (tb) G->bitmap_tiles = atoi(tb) < 0 ? 0 : atoi(tb);
   const char* bb = getenv("PIRRT_BATCH_BLOCKS");

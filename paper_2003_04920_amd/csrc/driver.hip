@@ -153,14 +153,26 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
 constexpr int kAfterEvalThreads = 1024;
 constexpr int kAfterEvalWords = 8192;  // tile bitmap in LDS: up to 262,144 tiles (2^30 slots)
 constexpr int kWordsPerThread = kAfterEvalWords / kAfterEvalThreads;
+constexpr int kRanks = kAfterEvalThreads;  // tile ranks inside a problem kept apart (the rest share the last)
+
+// Whether tile t0, the first tile of problem i, is also a tile of an earlier problem
+// that still iterates (that problem lists it).
+__device__ __forceinline__ bool listed_before(int32_t i, int64_t t0_slot, const int64_t* __restrict__ base,
+                                              const ProblemState* __restrict__ ps) {
+  for (int32_t q = i - 1; q >= 0 && base[q + 1] > t0_slot; --q)
+    if (ps[q].active && base[q + 1] > base[q]) return true;
+  return false;
+}
 
 __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, ProblemState* __restrict__ ps,
                                                                  const float* __restrict__ g, int prune,
                                                                  LoopCtl* __restrict__ ctl, int32_t n,
                                                                  const int32_t* __restrict__ prob,
                                                                  const int64_t* __restrict__ base,
-                                                                 int32_t* __restrict__ tiles, int32_t bitmap_tiles) {
+                                                                 int32_t* __restrict__ tiles, int32_t bitmap_tiles,
+                                                                 int32_t* __restrict__ tiles_walk) {
   __shared__ int any, count;
+  __shared__ int rank_at[kRanks];
   __shared__ uint32_t bits[kAfterEvalWords];
   __shared__ int wsum[kAfterEvalThreads / kWave + 1];
   const int32_t T = prob ? (int32_t)(((int64_t)n + kTileSlots - 1) / kTileSlots) : 0;
@@ -224,6 +236,53 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
       if (act) tiles[atomicAdd(&count, 1)] = t;
     }
   }
+  if (prob && tiles_walk) {
+    // The same tiles for the Evaluate walk, ordered by their rank inside their problem:
+    // every problem's first tiles, then every problem's second tiles, ...  Slots are
+    // numbered breadth-first inside a problem, so the walk then reaches the shallow
+    // parts of every tree before the deep ones, and climbs meet stamped ancestors
+    // sooner.  A tile shared by two problems is listed by the first one that iterates.
+    rank_at[threadIdx.x] = 0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        if (!ps[i].active || base[i + 1] <= base[i]) continue;
+        const int32_t t0 = (int32_t)(base[i] / kTileSlots), t1 = (int32_t)((base[i + 1] - 1) / kTileSlots);
+        const int32_t skip = base[i] % kTileSlots != 0 && listed_before(i, (int64_t)t0 * kTileSlots, base, ps);
+        for (int32_t t = t0 + skip; t <= t1; ++t) {
+          const int r = t - t0 < kRanks ? t - t0 : kRanks - 1;
+          if (pass == 0)
+            atomicAdd(&rank_at[r], 1);
+          else
+            tiles_walk[atomicAdd(&rank_at[r], 1)] = t;
+        }
+      }
+      __syncthreads();
+      if (pass == 0) {  // counts -> first position of each rank
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+        const int c = rank_at[threadIdx.x];
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int y = __shfl_up(incl, off, kWave);
+          if (lane >= off) incl += y;
+        }
+        if (lane == kWave - 1) wsum[wid] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          int t = 0;
+          for (int w = 0; w < kAfterEvalThreads / kWave; ++w) {
+            const int x = wsum[w];
+            wsum[w] = t;
+            t += x;
+          }
+        }
+        __syncthreads();
+        rank_at[threadIdx.x] = wsum[wid] + incl - c;
+        __syncthreads();
+      }
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     ctl->any_active = any;
@@ -257,9 +316,9 @@ void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl,
 
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
                        const int32_t* prob, const int64_t* base, int32_t* tiles, int32_t bitmap_tiles,
-                       hipStream_t s) {
+                       int32_t* tiles_walk, hipStream_t s) {
   hipLaunchKernelGGL(k_after_eval, dim3(1), dim3(kAfterEvalThreads), 0, s, P, ps, g, prune, ctl, n, prob, base,
-                     tiles, bitmap_tiles);
+                     tiles, bitmap_tiles, tiles_walk);
 }
 
 }  // namespace pirrt

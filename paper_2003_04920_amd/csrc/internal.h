@@ -210,9 +210,11 @@ void launch_finish(int32_t P, ProblemState* ps, IterCounters* ctr, LoopCtl* ctl,
 // bitmap; beyond, each tile's first and last problem are looked up.  Only batches
 // launch it: a single graph's promising list does the same work for its one problem at
 // the start of the next iteration.
+// tiles_walk (nullable): the same tiles ordered by their rank inside their problem,
+// for the Evaluate walk.
 void launch_after_eval(int32_t P, ProblemState* ps, const float* g, int prune, LoopCtl* ctl, int32_t n,
                        const int32_t* prob, const int64_t* base, int32_t* tiles, int32_t bitmap_tiles,
-                       hipStream_t s);
+                       int32_t* tiles_walk, hipStream_t s);
 
 // ---- improve.hip ----
 struct StepArgs {
