@@ -198,6 +198,29 @@ LOOP_KERNELS = ("k_promising_list", "k_mark", "k_domain_list", "k_improve", "k_f
                 "k_after_eval")
 
 
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Measured copy bandwidth of the GPU: a device-to-device copy of 1 GiB (1 GiB read
+    and 1 GiB written per copy), timed with events after two warm-ups; the practical
+    HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(2):
+        y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "note": "device-to-device copy of 1 GiB (read + write), mean of %d after 2 warm-ups" % reps}
+
+
 def loop_windows(path, min_kernels=30):
     """Replan loops in a kernel trace: maximal runs of loop kernels (any other
     dispatch, such as a copy, ends a run).  For the last run: its span from the first
@@ -1035,10 +1058,14 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [step() for _ in range(args.steps)]
+    stats, marks = [], [t0]
+    for _ in range(args.steps):  # each call returns once its outputs are valid
+        stats.append(step())
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / max(1, args.steps)
+    step_ms = [1e3 * (b - a) for a, b in zip(marks, marks[1:])]
     edges = sum(s["edges_examined"] for s in stats)
     gteps = edges / elapsed / 1e9
     st = stats[-1]
@@ -1235,6 +1262,9 @@ def main():
                    "vertices": n, "directed_edges": 2 * b0.nnz, "iterations": st["iterations"],
                    "edges_examined_per_replan": st["edges_examined"], "sum_D": st["sum_D"],
                    "autotuned_config": tuned, "parallelism": "single GPU"},
+        "step_ms": {"mean": round(ms_per_step, 4), "median": round(float(np.median(step_ms)), 4),
+                    "min": round(min(step_ms), 4)},
+        "copy_ceiling": copy_ceiling(),
         "phases_ms": {k: round(tst[k], 4) for k in ("ms_evaluate", "ms_mark", "ms_improve")},
         "roofline": roofline,
         "replan_hbm": replan_hbm,
