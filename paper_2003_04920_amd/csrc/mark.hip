@@ -419,11 +419,14 @@ __global__ void __launch_bounds__(kThreads) k_mark_rows(const ProblemState* __re
   }
 }
 
-// The listed rows' grid covers half the vertices: a workgroup takes a second chunk
-// of rows only while more than half the vertices are promising (the first iterations),
-// and the launch carries half as many workgroups that find nothing to do.  Measured on
-// the 1M graph: 1% per Replan against a grid for all n (a quarter or an eighth: no better).
+// On large graphs the listed rows' grid covers half the vertices: a workgroup takes a
+// second chunk of rows only while more than half the vertices are promising (the first
+// iterations), and the launch carries half as many workgroups that find nothing to do.
+// Measured on the 1M graph: 1% per Replan against a grid for all n (a quarter or an
+// eighth: no better).  Graphs below kMarkRowsHalfGridMin vertices, where that was not
+// measured, keep one chunk of rows per workgroup.
 constexpr int kMarkRowsGridDiv = 2;
+constexpr int32_t kMarkRowsHalfGridMin = 1 << 18;
 
 template <int GW, int U, bool B>
 void launch_mark_t(const StepArgs& a, hipStream_t s) {
@@ -437,7 +440,8 @@ void launch_mark_t(const StepArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_promising_list<false>, pgrid, dim3(kThreads), 0, s, a.n, a.ps, a.ctl, a.g, a.h, a.stamp,
                          a.plist, a.ctr, a.word, a.prune, a.rp);
     const bool narrow = a.nnz < ((int64_t)1 << 32) - 64 * GW;
-    const dim3 rgrid = grid_for((a.n + kMarkRowsGridDiv - 1) / kMarkRowsGridDiv, GW);
+    const int div = a.n >= kMarkRowsHalfGridMin ? kMarkRowsGridDiv : 1;
+    const dim3 rgrid = grid_for((a.n + div - 1) / div, GW);
 #define PIRRT_MARK_ROWS(I, L)                                                                                   \
   hipLaunchKernelGGL((k_mark_rows<GW, U, I, L>), rgrid, dim3(kThreads), 0, s, a.ps, a.ctl, a.plist, a.rp, a.col, \
                      a.cst, a.g, a.h, a.stamp)
