@@ -1092,6 +1092,7 @@ def main():
                                "bytes_per_launch": int(gbytes / max(1, tst["improve_launches"]))}
 
     goal_exact = float(g_out[1].item())
+    g_ref = g_out.clone()  # the timed calls' g (the extras below write g_out)
     # the narrowed Improve domain (PIRRT_LOOKAHEAD) on the same graph and policy
     look = None
     if not args.no_extra:
@@ -1111,6 +1112,29 @@ def main():
                 "goal_cost": goal_look, "goal_cost_full_domain": goal_exact,
                 "goal_cost_rel_diff": abs(goal_look - goal_exact) / goal_exact}
         log("narrowed domain: %s" % json.dumps(look))
+
+    # the same Replan with h read from and g / parent written to pinned host memory:
+    # the rate a caller sees when its buffers are on the host (PCIe included)
+    host_io = None
+    if not args.no_extra:
+        h_host = h.cpu().pin_memory()
+        g_host = torch.empty(n, dtype=torch.float32).pin_memory()
+        p_host = torch.empty(n, dtype=torch.int32).pin_memory()
+        G.snapshot_restore()
+        G.replan(0, 1, h_host, True, g_out=g_host, parent_out=p_host)
+        reps = 5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G.snapshot_restore()
+            _, _, s6 = G.replan(0, 1, h_host, True, g_out=g_host, parent_out=p_host)
+        torch.cuda.synchronize()
+        t_io = (time.perf_counter() - t0) / reps
+        assert np.array_equal(g_host.numpy().view(np.uint32), g_ref.cpu().numpy().view(np.uint32))
+        host_io = {"replan_ms": round(1e3 * t_io, 3), "gteps": round(s6["edges_examined"] / t_io / 1e9, 2),
+                   "bytes_over_pcie": int(12 * n),
+                   "note": "h from and g, parent to pinned host memory; same bits as the device-buffer call"}
+        log("host buffers: %s" % json.dumps(host_io))
 
     # the truncated Evaluate (PIRRT_TRUNCATED) on the same graph and policy
     trunc = None
@@ -1272,6 +1296,7 @@ def main():
         "cpu_baseline": cpu,
         "extra_batch": extra,
         "pruning_off": noprune,
+        "host_buffers": host_io,
         "lookahead_domain": look,
         "truncated_evaluate": trunc,
     }
