@@ -161,10 +161,13 @@ def profile_summary(paths):
                     key = (_short(row["Kernel_Name"]), row["Counter_Name"])
                     per.setdefault(key, []).append(float(row["Counter_Value"]))
     if per:
-        out.append("counters, mean KiB per dispatch:")
+        # the Replan loop's kernels and the calibration kernel (the other kernels of the
+        # run, graph building and exploration, are left out)
+        shown = lambda k: k.split("<")[0] in LOOP_KERNELS or k.startswith("k_mark") or "native::neg" in k
+        out.append("counters, mean KiB per dispatch (Replan loop kernels and the calibration kernel):")
         for (k, c), v in sorted(per.items()):
-            out.append("  %-60s %-11s dispatches %5d mean %14.1f" % (k[:60] or "(unnamed)", c, len(v),
-                                                                      sum(v) / len(v)))
+            if shown(k):
+                out.append("  %-60s %-11s dispatches %5d mean %14.1f" % (k[:60], c, len(v), sum(v) / len(v)))
         def mean(pred, counter):
             v = [x for (k, c), xs in per.items() if c == counter and pred(k) for x in xs]
             return sum(v) / len(v) if v else None
