@@ -98,8 +98,9 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
 // Compacted Improve domain: the slots stamped with this iteration's epoch.  Each
 // thread tests kListPer consecutive stamps (one 16-byte load), a workgroup scan
 // places them, and one atomic per workgroup reserves the workgroup's chunk
-// (ascending inside the chunk).  When the next mark epoch wraps its low byte, every
-// stamp is cleared here after being read.
+// (ascending inside the chunk), which is staged in LDS and written out coalesced.
+// When the next mark epoch wraps its low byte, every stamp is cleared here after being
+// read.
 constexpr int kListPer = 16;
 
 // In a batch only the active tiles are scanned, and a slot of a problem that has
@@ -190,7 +191,8 @@ __global__ void __launch_bounds__(kThreads) k_domain_list(int32_t n, LoopCtl* __
 
 // Single graphs mark in two steps.  k_promising_list tests kListPer consecutive
 // vertices per thread (16-byte loads of g and h), stamps the promising ones and lists
-// them (one atomic per workgroup); k_mark_rows then stamps the neighbours of the
+// them (one atomic per workgroup, the chunk staged in LDS and written out coalesced);
+// k_mark_rows then stamps the neighbours of the
 // listed vertices only, so the row work follows |P| rather than n.
 // kTrunc: P is the set the last (truncated) walk queued: the vertices other than the
 // root whose walk stamp lacks kWalkNoChildren (every vertex is stamped by each walk).
