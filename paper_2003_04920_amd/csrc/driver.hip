@@ -149,7 +149,9 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
 // problem's promising threshold G for the next iteration (Alg. 2's test against
 // g(x_goal), +inf without pruning, -inf for a problem that has stopped).
 // In a batch it also lists the tiles that overlap a problem still iterating (a tile
-// spans at most a few problems: each holds thousands of slots).
+// spans at most a few problems: each holds thousands of slots), in tile order for the
+// mark and the domain list and, for the Evaluate walk, by their rank inside their
+// problem.
 constexpr int kAfterEvalThreads = 1024;
 constexpr int kAfterEvalWords = 8192;  // tile bitmap in LDS: up to 262,144 tiles (2^30 slots)
 constexpr int kWordsPerThread = kAfterEvalWords / kAfterEvalThreads;
