@@ -993,13 +993,22 @@ struct LoopArgs {
   EvalArgs ea;
 };
 
+// A single graph's walk after an Improve takes the finish step itself (one launch
+// less per iteration); batches and the level-synchronous Evaluate keep k_finish.
+bool walk_finishes(pirrt_graph* G, const LoopArgs& L) {
+  return L.sa.prob == nullptr && !(G->eval_levels && !L.wa.truncated);
+}
+
 // Enqueues Evaluate for every problem that needs it (walk, or level-synchronous
-// for a single problem).
-void enqueue_evaluate(pirrt_graph* G, LoopArgs& L, hipStream_t s) {
-  if (G->eval_levels && !L.wa.truncated)  // the truncated Evaluate is a walk
+// for a single problem).  after_improve: the Evaluate of an iteration (not the first
+// one of a Replan).
+void enqueue_evaluate(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool after_improve) {
+  if (G->eval_levels && !L.wa.truncated) {  // the truncated Evaluate is a walk
     launch_evaluate(L.ea, s);
-  else
+  } else {
+    L.wa.finish = after_improve && walk_finishes(G, L);
     launch_eval_walk(L.wa, s);
+  }
 }
 
 // One iteration of Alg. 2 for every active problem.
@@ -1012,9 +1021,9 @@ void enqueue_iteration(pirrt_graph* G, LoopArgs& L, hipStream_t s, bool timing) 
   launch_improve(L.sa, G->row_variant, s);
   if (timing) (void)hipEventRecord(G->ev[4], s);
   const bool single = L.sa.prob == nullptr;
-  launch_finish(L.P, G->ps, G->ctr, G->ctl, single, s);
+  if (!walk_finishes(G, L)) launch_finish(L.P, G->ps, G->ctr, G->ctl, single, s);
   if (timing) (void)hipEventRecord(G->ev[0], s);
-  enqueue_evaluate(G, L, s);
+  enqueue_evaluate(G, L, s, true);
   if (timing) (void)hipEventRecord(G->ev[1], s);
   // a single graph's promising list (next iteration) takes the thresholds step
   if (!single)
@@ -1167,6 +1176,8 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.truncated = G->truncated;
   wa.h = h;
   wa.blocks = G->batch_blocks;
+  wa.ctr = G->ctr;
+  wa.finish = false;
   EvalArgs& ea = L.ea;
   ea.n = n;
   ea.ps = G->ps;
@@ -1220,7 +1231,7 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   // first Evaluate of every problem
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[0], s));
   if (G->trace) HIP_OR_FAIL(G, hipMemsetAsync(G->dhops, 0, sizeof(unsigned long long), s));
-  enqueue_evaluate(G, L, s);
+  enqueue_evaluate(G, L, s, false);
   if (timing) HIP_OR_FAIL(G, hipEventRecord(G->ev[1], s));
   if (problem_map(G))  // a single graph's first promising list takes the thresholds step
     launch_after_eval(P, G->ps, G->g, prune ? 1 : 0, G->ctl, n, problem_map(G), base_map(G), G->tiles,

@@ -36,6 +36,9 @@ struct ProblemState {
   int32_t cap;         // iteration cap
   unsigned long long edges, sum_P, sum_D, changed_total;
   unsigned long long mark_edges;  // sum over iterations of the promising rows' degrees
+  // Single graphs with the walk Evaluate: changed_total when the current iteration began
+  // (the walk that follows Improve compares the counters against it).
+  unsigned long long changed_seen;
 };
 
 // Device-side loop control shared by the kernels of one Replan.
@@ -88,6 +91,10 @@ struct EvalInfo {
 };
 
 __device__ __forceinline__ float pos_inf() { return __int_as_float(0x7f800000); }
+
+// Next mark epoch: its low byte (the stamp value) is never 0, so a cleared stamp never
+// matches.
+__device__ __forceinline__ uint32_t next_mark_epoch(uint32_t e) { return ((e + 1) & 0xffu) == 0 ? e + 2 : e + 1; }
 
 // Next Evaluate epoch (0 is never used, so a cleared stamp word never matches).
 __device__ __forceinline__ uint32_t next_epoch(uint32_t e) { return e + 1 == 0 ? 1u : e + 1; }

@@ -12,7 +12,6 @@ namespace {
 
 // Mark epochs are stored as their low byte: skip the values whose low byte is 0
 // (the cleared stamp).
-__device__ __forceinline__ uint32_t next_mark_epoch(uint32_t e) { return ((e + 1) & 0xffu) == 0 ? e + 2 : e + 1; }
 
 // Marks the roots, clears the counters and takes fresh epochs.  The threshold is set
 // to g(goal) as stored before any Evaluate of this Replan (the truncated Evaluate's

@@ -235,21 +235,81 @@ __device__ __forceinline__ void store_word(unsigned long long* p, unsigned long 
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool kCountHops, bool kCoherent, bool kBatched, bool kTrunc>
+// kFinish (single graphs, the walk after an Improve): the walk takes the finish step.
+// The counter copies accumulate over the Replan; every workgroup sums the parents
+// switched so far and runs only if that moved past ps->changed_seen (set by the
+// promising list at the start of the iteration, unchanged during this launch);
+// workgroup 0 of the first part writes the totals, the convergence test and the cap to
+// the problem state and the loop flags, which only later launches read.
+template <bool kFinish>
+__device__ __forceinline__ bool walk_finish(ProblemState* __restrict__ ps, LoopCtl* __restrict__ ctl,
+                                            const IterCounters* __restrict__ ctr, int book) {
+  if (!kFinish) return ctl->any_eval != 0;
+  __shared__ int run_flag;
+  if (threadIdx.x < kCounterSlots) {  // one wave
+    const IterCounters& c = ctr[threadIdx.x];
+    unsigned long long ch = (unsigned)c.changed, np = (unsigned)c.nP, nd = (unsigned)c.nD, ed = c.edges,
+                       pe = (unsigned)c.pedges;
+#pragma unroll
+    for (int off = kCounterSlots / 2; off > 0; off >>= 1) {
+      ch += __shfl_xor(ch, off, kCounterSlots);
+      np += __shfl_xor(np, off, kCounterSlots);
+      nd += __shfl_xor(nd, off, kCounterSlots);
+      ed += __shfl_xor(ed, off, kCounterSlots);
+      pe += __shfl_xor(pe, off, kCounterSlots);
+    }
+    if (threadIdx.x == 0) {
+      run_flag = ch != ps->changed_seen;
+      if (book && blockIdx.x == 0) {
+        ProblemState& q = *ps;
+        if (q.active) {
+          q.iterations += 1;
+          q.edges = ed;
+          q.sum_P = np;
+          q.sum_D = nd;
+          q.mark_edges = pe;
+          const bool switched = ch != q.changed_total;
+          q.changed_total = ch;
+          if (!switched) {  // no parent switched: fixed point (dJ = 0)
+            q.active = 0;
+            q.needs_eval = 0;
+          } else {
+            q.needs_eval = 1;
+            if (q.iterations >= q.cap) {
+              q.active = 0;
+              q.status = 1;
+            }
+          }
+        } else {
+          q.needs_eval = 0;
+        }
+        ctl->any_active = q.active;
+        ctl->npromising = 0;
+        ctl->epoch = next_mark_epoch(ctl->epoch);
+      }
+    }
+  }
+  __syncthreads();
+  return run_flag != 0;
+}
+
+template <bool kCountHops, bool kCoherent, bool kBatched, bool kTrunc, bool kFinish = false>
 __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t hi, int32_t n,
                                                            const int32_t* __restrict__ prob,
-                                                           const ProblemState* __restrict__ ps,
-                                                           const LoopCtl* __restrict__ ctl,
+                                                           ProblemState* __restrict__ ps,
+                                                           LoopCtl* __restrict__ ctl,
                                                            const int32_t* __restrict__ parent,
                                                            const float* __restrict__ pcost, float* __restrict__ g,
                                                            unsigned long long* __restrict__ word,
                                                            unsigned long long* __restrict__ hops,
                                                            const int32_t* __restrict__ tiles,
-                                                           const float* __restrict__ h) {
+                                                           const float* __restrict__ h,
+                                                           const IterCounters* __restrict__ ctr, int book) {
   static_assert(!(kTrunc && kBatched), "the truncated Evaluate takes a single graph");
   __shared__ int32_t ring_v[kRing][kWalkThreads];
   __shared__ float ring_c[kRing][kWalkThreads];
-  if (ctl->any_eval == 0) return;  // no problem changed in this iteration
+  static_assert(!(kFinish && kBatched), "batches keep their finish step");
+  if (!walk_finish<kFinish>(ps, ctl, ctr, book)) return;  // no parent switched in this iteration
   const unsigned long long tag = (unsigned long long)ctl->eval_epoch << 32;
   const float G0 = kTrunc ? ps[0].thr : 0.0f;
   unsigned long long walked = 0;
@@ -259,7 +319,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
   const int64_t v = (kBatched ? tile_unit_slot(ctl, tiles, kWalkThreads, wu) : lo + (int64_t)blockIdx.x * blockDim.x) +
                     threadIdx.x;
   if (v >= hi) continue;
-  if (!ps[kBatched ? prob[v] : 0].needs_eval) continue;
+  if (!kFinish && !ps[kBatched ? prob[v] : 0].needs_eval) continue;
   for (;;) {
     int32_t u = (int32_t)v;
     int64_t k = 0;
@@ -331,12 +391,19 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
     const int64_t units = (((int64_t)a.n + kTileSlots - 1) / kTileSlots) * (kTileSlots / kWalkThreads);
     const dim3 grid(a.prob ? (unsigned)(units < a.blocks ? (units > 0 ? units : 1) : a.blocks)
                            : blocks_for(hi - lo, kWalkThreads));
-#define PIRRT_WALK(H, C, B)                                                                                \
-  hipLaunchKernelGGL((k_eval_walk<H, C, B, false>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \
-                     a.ctl, a.parent, a.pcost, a.g, a.word, a.hops, a.tiles, a.h)
-#define PIRRT_WALK_TRUNC(H, C)                                                                                \
-  hipLaunchKernelGGL((k_eval_walk<H, C, false, true>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \
-                     a.ctl, a.parent, a.pcost, a.g, a.word, a.hops, a.tiles, a.h)
+#define PIRRT_WALK1(H, C, B, T, F)                                                                          \
+  hipLaunchKernelGGL((k_eval_walk<H, C, B, T, F>), grid, dim3(kWalkThreads), 0, s, lo, hi, a.n, a.prob, a.ps, \
+                     a.ctl, a.parent, a.pcost, a.g, a.word, a.hops, a.tiles, a.h, a.ctr, k == 0 ? 1 : 0)
+#define PIRRT_WALK(H, C, B)                                              \
+  do {                                                                   \
+    if (!B && a.finish) PIRRT_WALK1(H, C, false, false, true);           \
+    else PIRRT_WALK1(H, C, B, false, false);                             \
+  } while (0)
+#define PIRRT_WALK_TRUNC(H, C)                                           \
+  do {                                                                   \
+    if (a.finish) PIRRT_WALK1(H, C, false, true, true);                  \
+    else PIRRT_WALK1(H, C, false, true, false);                          \
+  } while (0)
     const bool b = a.prob != nullptr;
     if (a.truncated && !b) {  // the host rejects the truncated Evaluate for batches
       if (a.hops) {
@@ -355,6 +422,7 @@ void launch_eval_walk(const WalkArgs& a, hipStream_t s) {
     }
 #undef PIRRT_WALK
 #undef PIRRT_WALK_TRUNC
+#undef PIRRT_WALK1
   }
 }
 

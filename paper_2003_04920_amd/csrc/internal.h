@@ -150,8 +150,13 @@ void launch_evaluate(const EvalArgs& a, hipStream_t s);
 struct WalkArgs {
   int32_t n;
   const int32_t* prob;     // problem of each slot, or NULL for a single problem
-  const ProblemState* ps;
-  const LoopCtl* ctl;      // eval_epoch, any_eval
+  ProblemState* ps;
+  LoopCtl* ctl;            // eval_epoch, any_eval
+  // Single graphs, the walk after an Improve: the walk also takes the finish step (sums
+  // the iteration's counters, which accumulate over the Replan, applies the convergence
+  // test and the cap) and runs only if a parent switched.
+  bool finish;
+  IterCounters* ctr;
   const int32_t* parent;   // roots carry kRootMark
   const float* pcost;
   float* g;

@@ -218,6 +218,7 @@ __global__ void __launch_bounds__(kThreads) k_promising_list(int32_t n, ProblemS
     ctl->ndomain = 0;
     ctl->ntiles = -1;
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
+    ps[0].changed_seen = ps[0].changed_total;  // the walk after this Improve compares against it
   }
   if (!active) return;  // the problem has converged
   const uint8_t ep = (uint8_t)ctl->epoch;
