@@ -459,6 +459,15 @@ def test_every_kernel_configuration(P, monkeypatch, variant, coherent):
     run_both(P, wl.batches, {0: (0, 1), 2: (0, 1)}, wl.heuristic, True, check_insert=False)
 
 
+@pytest.mark.parametrize("parts", [2, 3])
+def test_walk_in_parts(P, monkeypatch, parts):
+    """The walk split over consecutive slot ranges (one launch each; the first also takes
+    the finish step after an Improve) gives the oracle's results and counters."""
+    monkeypatch.setenv("PIRRT_WALK_PARTS", str(parts))
+    wl = W.batched_6d(batches=3, batch=800, seed=103)
+    run_both(P, wl.batches, {0: (0, 1), 1: (5, 1), 2: (0, 1)}, wl.heuristic, True, check_insert=False)
+
+
 def test_tune_restores_policy_and_keeps_results(P):
     wl = W.plain_2d()
     G = gpu_graph(P)
