@@ -879,14 +879,19 @@ def bench_berrt6d(args):
     wl = W.batched_6d(batches=args.berrt_batches, batch=args.berrt_batch, seed=100)
     log("workload %s: n=%d, %d batches (%.1fs)" % (wl.name, wl.n, len(wl.batches), time.time() - t0))
 
-    def run(timed_graph):
-        G = P.Graph(stream=stream)
+    host_rows = [(b.row_ptr, b.col, b.cost) for b in wl.batches]
+    dev_rows = [tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in r) for r in host_rows]
+
+    def run(rows, capacity=False):
+        # capacity: the graph is created with the workload's final vertex and edge counts
+        G = (P.Graph(stream=stream, vertex_capacity=wl.n, edge_capacity=2 * sum(b.nnz for b in wl.batches))
+             if capacity else P.Graph(stream=stream))
         per, ins = [], []
         edges = iters = 0
-        for b in wl.batches:
+        for r in rows:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            G.insert_rows(b)  # host rows: includes their copy and, now and then, the renumbering
+            G.insert_batch(*r)  # now and then also the renumbering; host rows include their copy
             torch.cuda.synchronize()
             ins.append(time.perf_counter() - t1)
             h = torch.from_numpy(wl.heuristic(G.n)).to(dev)
@@ -898,8 +903,14 @@ def bench_berrt6d(args):
             iters += st["iterations"]
         return per, ins, edges, iters, float(g[1].item())
 
-    run(False)  # warm-up: kernel loading and allocations
-    per, ins, edges, iters, cost = run(True)
+    run(host_rows)  # warm-up: kernel loading and allocations
+    per, ins, edges, iters, cost = run(host_rows)
+    per_d, ins_d, edges_d, _, cost_d = run(dev_rows, capacity=True)
+    assert edges_d == edges and cost_d == cost, "device rows gave another Replan sequence"
+    log("inserts: host rows %.2f ms (median %.3f, max %.3f); device rows into a graph created with its capacity "
+        "%.2f ms (median %.3f, max %.3f); Replans %.2f ms and %.2f ms"
+        % (1e3 * sum(ins), 1e3 * float(np.median(ins)), 1e3 * max(ins), 1e3 * sum(ins_d),
+           1e3 * float(np.median(ins_d)), 1e3 * max(ins_d), 1e3 * sum(per), 1e3 * sum(per_d)))
     tot = sum(per)
     cpu = None
     if not args.no_cpu_baseline:
@@ -932,6 +943,8 @@ def bench_berrt6d(args):
                                "to goal" % (len(wl.batches), args.berrt_batch), "vertices": wl.n},
         "replans": len(per), "replan_total_ms": round(1e3 * tot, 2), "replan_mean_ms": round(1e3 * tot / len(per), 3),
         "replan_last_ms": round(1e3 * per[-1], 3), "insert_total_ms": round(1e3 * sum(ins), 2),
+        "insert_total_ms_device_rows_with_capacity": round(1e3 * sum(ins_d), 2),
+        "replan_total_ms_device_rows_run": round(1e3 * sum(per_d), 2),
         "iterations_total": iters, "edges_examined": edges,
         "final_cost": cost, "cpu_baseline": cpu,
     }

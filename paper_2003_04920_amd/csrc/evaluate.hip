@@ -204,7 +204,11 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
 //
 // The path is kept in a ring of kRing slots per thread in LDS; a longer path folds
 // its top kRing vertices, stamps them and walks again from v (which now stops
-// there).  A walk longer than n hops can only be a parent cycle away from the
+// there).  Single graphs keep each path vertex's edge cost beside it (32 KB per
+// workgroup, 4 waves per SIMD; more waves in flight meet more ancestors not yet
+// stamped, and the 1M-vertex walk gets slower with 6 or 8); batches keep the vertex
+// only and read its cost again in the fold (16 KB, 8 waves per SIMD: their deep 2D
+// and 3D trees are bound by the latency of long climbs).  A walk longer than n hops can only be a parent cycle away from the
 // root; its vertices are unreachable and get +inf.
 //
 // kTrunc (single graphs): the truncated Evaluate.  A vertex is visited only when its
@@ -307,7 +311,8 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
                                                            const IterCounters* __restrict__ ctr, int book) {
   static_assert(!(kTrunc && kBatched), "the truncated Evaluate takes a single graph");
   __shared__ int32_t ring_v[kRing][kWalkThreads];
-  __shared__ float ring_c[kRing][kWalkThreads];
+  constexpr bool kRingCost = !kBatched;  // the ring holds the edge costs too
+  __shared__ float ring_c[kRingCost ? kRing : 1][kWalkThreads];
   static_assert(!(kFinish && kBatched), "batches keep their finish step");
   if (!walk_finish<kFinish>(ps, ctl, ctr, book)) return;  // no parent switched in this iteration
   const unsigned long long tag = (unsigned long long)ctl->eval_epoch << 32;
@@ -340,7 +345,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
         break;
       }
       ring_v[k % kRing][threadIdx.x] = u;
-      ring_c[k % kRing][threadIdx.x] = c;
+      if (kRingCost) ring_c[k % kRing][threadIdx.x] = c;
       ++k;
       if (p < 0 || k > n) {  // detached chain (or a cycle): unreachable
         top = kTrunc ? kWalkNoChildren : 0x7f800000u;
@@ -356,7 +361,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
       for (int64_t i = k - 1; i >= stop; --i) {
         const int32_t x = ring_v[i % kRing][threadIdx.x];
         if (!(st & kWalkNoChildren)) {  // x is visited: fresh g, then its own test
-          const float acc = add_rn(__uint_as_float(st), ring_c[i % kRing][threadIdx.x]);
+          const float acc = add_rn(__uint_as_float(st), kRingCost ? ring_c[i % kRing][threadIdx.x] : pcost[x]);
           g[x] = acc;
           st = __float_as_uint(acc) | (add_rn(acc, h ? h[x] : 0.0f) < G0 ? 0u : kWalkNoChildren);
         }
@@ -368,7 +373,7 @@ __global__ void __launch_bounds__(kWalkThreads) k_eval_walk(int32_t lo, int32_t 
     float acc = __uint_as_float(top);
     for (int64_t i = k - 1; i >= stop; --i) {
       const int32_t x = ring_v[i % kRing][threadIdx.x];
-      acc = add_rn(acc, ring_c[i % kRing][threadIdx.x]);
+      acc = add_rn(acc, kRingCost ? ring_c[i % kRing][threadIdx.x] : pcost[x]);
       store_word<kCoherent>(&word[x], tag | __float_as_uint(acc));
       g[x] = acc;
     }
