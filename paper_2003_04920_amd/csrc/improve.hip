@@ -135,7 +135,11 @@ __global__ void __launch_bounds__(kThreads) k_improve(int32_t n, const int32_t* 
     pcost[x] = __uint_as_float(wc);
     changed = 1;
   }
-  flush_counters(ctr, p, valid && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
+  if (kBatched)
+    rows::flush_counters_wave<false, true, true, true, false>(ctr, p, valid && gl == 0, 0, in ? 1 : 0,
+                                                              in ? (unsigned long long)(b - a) : 0ull, changed);
+  else
+    flush_counters(ctr, p, valid && gl == 0, 0, in ? 1 : 0, in ? (unsigned long long)(b - a) : 0ull, changed);
   }
 }
 

@@ -91,7 +91,11 @@ __global__ void __launch_bounds__(kThreads) k_mark(int32_t n, const int32_t* __r
       }
     }
   }
-  flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0, in ? (int)(rb - ra) : 0);
+  if (kBatched)
+    rows::flush_counters_wave<true, false, false, false, true>(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0,
+                                                               in ? (int)(rb - ra) : 0);
+  else
+    flush_counters(ctr, p, v < n && gl == 0, in ? 1 : 0, 0, 0ull, 0, in ? (int)(rb - ra) : 0);
   }
 }
 

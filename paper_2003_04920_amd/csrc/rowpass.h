@@ -67,6 +67,50 @@ __device__ __forceinline__ void flush_counters(IterCounters* ctr, int p, bool le
   }
 }
 
+// The same sums per wave, without the workgroup's barriers (the grid-stride loops of
+// a batch call it once per work unit): when every leader lane of the wave lies in one
+// problem, lane 0 adds the wave's sums, one atomic per counter; otherwise each leader
+// adds its own.  Counters that a caller never sets are left out at compile time.
+template <bool kP, bool kD, bool kE, bool kC, bool kPE>
+__device__ __forceinline__ void flush_counters_wave(IterCounters* ctr, int p, bool leader, int nP, int nD,
+                                                    unsigned long long edges, int changed, int pedges = 0) {
+  const unsigned long long lm = __ballot(leader);
+  if (lm == 0ull) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int p0 = __shfl(p, __ffsll((long long)lm) - 1, kWave);
+  const int slot = (int)((blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave) % kCounterSlots);
+  if (__ballot(leader && p != p0) != 0ull) {  // the wave straddles problems
+    if (leader) {
+      IterCounters& C = ctr[(int64_t)p * kCounterSlots + slot];
+      if (kP && nP) atomicAdd(&C.nP, nP);
+      if (kD && nD) atomicAdd(&C.nD, nD);
+      if (kE && edges) atomicAdd(&C.edges, edges);
+      if (kC && changed) atomicAdd(&C.changed, changed);
+      if (kPE && pedges) atomicAdd(&C.pedges, pedges);
+    }
+    return;
+  }
+  int a = kP && leader ? nP : 0, b = kD && leader ? nD : 0, d = kC && leader ? changed : 0,
+      e = kPE && leader ? pedges : 0;
+  unsigned long long c = kE && leader ? edges : 0ull;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    if (kP) a += __shfl_xor(a, off, kWave);
+    if (kD) b += __shfl_xor(b, off, kWave);
+    if (kE) c += __shfl_xor(c, off, kWave);
+    if (kC) d += __shfl_xor(d, off, kWave);
+    if (kPE) e += __shfl_xor(e, off, kWave);
+  }
+  if (lane == 0) {
+    IterCounters& C = ctr[(int64_t)p0 * kCounterSlots + slot];
+    if (kP && a) atomicAdd(&C.nP, a);
+    if (kD && b) atomicAdd(&C.nD, b);
+    if (kE && c) atomicAdd(&C.edges, c);
+    if (kC && d) atomicAdd(&C.changed, d);
+    if (kPE && e) atomicAdd(&C.pedges, e);
+  }
+}
+
 inline dim3 grid_for(int64_t n, int gw) {
   const int64_t b = ((int64_t)n * gw + kThreads - 1) / kThreads;
   return dim3((unsigned)(b > 0 ? b : 1));
