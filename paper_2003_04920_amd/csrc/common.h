@@ -50,7 +50,7 @@ struct LoopCtl {
   int32_t ndomain;      // entries of the compacted Improve domain of this iteration
   int32_t ntiles;       // batches: entries of the active tile list; -1 = every tile
   int32_t npromising;   // single graphs: entries of the compacted promising set
-  int32_t pad;
+  int32_t tiles_stale;  // batches: a problem stopped since the tile lists were built
 };
 
 // Truncated Evaluate: the low word of a vertex's walk stamp carries this bit when the

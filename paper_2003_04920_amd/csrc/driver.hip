@@ -42,6 +42,7 @@ __global__ void k_replan_init(int32_t P, ProblemState* __restrict__ ps, int32_t*
     ctl->ntiles = -1;
     ctl->ndomain = 0;
     ctl->npromising = 0;
+    ctl->tiles_stale = 1;
   }
 }
 
@@ -132,6 +133,7 @@ __global__ void __launch_bounds__(kCounterSlots) k_finish(int32_t P, ProblemStat
         }
         atomicOr(&ctl->any_eval, 1);
       }
+      if (!s.active) atomicOr(&ctl->tiles_stale, 1);
     } else {
       s.needs_eval = 0;
     }
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
                                                                  const int64_t* __restrict__ base,
                                                                  int32_t* __restrict__ tiles, int32_t bitmap_tiles,
                                                                  int32_t* __restrict__ tiles_walk) {
-  __shared__ int any, count;
+  __shared__ int any, count, rebuild;
   __shared__ int rank_at[kRanks];
   __shared__ uint32_t bits[kAfterEvalWords];
   __shared__ int wsum[kAfterEvalThreads / kWave + 1];
@@ -181,24 +183,28 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
   // too: the active problems set their tiles' bits, and the list is read off the
   // bitmap in tile order
   const bool bitmap = T <= bitmap_tiles && T <= kAfterEvalWords * 32;
+  // The lists stay as they are while no problem has stopped since they were built
+  // (problems only ever stop, and listed tiles of a stopped problem cost work but
+  // change no result).
   if (threadIdx.x == 0) {
     any = 0;
-    count = 0;
+    rebuild = prob && (ctl->tiles_stale != 0 || ctl->ntiles < 0);
+    count = rebuild ? 0 : ctl->ntiles;
   }
   for (int w = threadIdx.x; w < kAfterEvalWords; w += kAfterEvalThreads) bits[w] = 0u;
-  __syncthreads();
+  __syncthreads();  // also: rebuild is set
   for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
     ProblemState& s = ps[i];
     const bool a = s.active != 0;
     if (a) any = 1;
     s.thr = a ? (prune ? g[s.goal] : pos_inf()) : -pos_inf();
-    if (prob && bitmap && a && base[i + 1] > base[i]) {
+    if (rebuild && bitmap && a && base[i + 1] > base[i]) {
       const int32_t t0 = (int32_t)(base[i] / kTileSlots), t1 = (int32_t)((base[i + 1] - 1) / kTileSlots);
       for (int32_t t = t0; t <= t1; ++t) atomicOr(&bits[t >> 5], 1u << (t & 31));
     }
   }
   __syncthreads();
-  if (prob && bitmap) {
+  if (rebuild && bitmap) {
     // each thread takes kWordsPerThread consecutive words; a block scan places them
     const int w0 = threadIdx.x * kWordsPerThread;
     int c = 0;
@@ -227,7 +233,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
 #pragma unroll
     for (int k = 0; k < kWordsPerThread; ++k)
       for (uint32_t m = bits[w0 + k]; m; m &= m - 1) tiles[pos++] = (w0 + k) * 32 + __ffs(m) - 1;
-  } else if (prob) {
+  } else if (rebuild) {
     // more tiles than the bitmap holds: test each tile's first and last problem
     for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
       const int64_t s0 = (int64_t)t * kTileSlots;
@@ -237,7 +243,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
       if (act) tiles[atomicAdd(&count, 1)] = t;
     }
   }
-  if (prob && tiles_walk) {
+  if (rebuild && tiles_walk) {
     // The same tiles for the Evaluate walk, ordered by their rank inside their problem:
     // every problem's first tiles, then every problem's second tiles, ...  Slots are
     // numbered breadth-first inside a problem, so the walk then reaches the shallow
@@ -291,6 +297,7 @@ __global__ void __launch_bounds__(kAfterEvalThreads) k_after_eval(int32_t P, Pro
     ctl->ndomain = 0;
     ctl->npromising = 0;
     ctl->ntiles = prob ? count : -1;
+    ctl->tiles_stale = 0;
     ctl->eval_epoch = next_epoch(ctl->eval_epoch);
   }
 }
