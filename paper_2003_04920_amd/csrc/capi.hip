@@ -196,6 +196,7 @@ struct pirrt_graph {
   int32_t mid_hint = 64;
   int row_variant = 1;  // 8 lanes x 2 quads per row; the autotuner tries the others
   int batch_blocks = kBatchBlocks;  // batches: workgroups per grid-stride launch (autotuned)
+  int cus = 256;                     // compute units of the device
   int32_t bitmap_tiles = INT32_MAX;  // batches: tile lists from the bitmap up to this many tiles
   bool walk_rank = true;  // batches: the walk takes the active tiles by their rank inside their problem
   bool lookahead = false;  // narrowed Improve domain for the current call (PIRRT_LOOKAHEAD)
@@ -1175,7 +1176,9 @@ int run_replan(pirrt_graph* G, int32_t P, const int32_t* root_ids, const int32_t
   wa.tiles = walk_tiles(G) ? walk_tiles(G) : G->tiles;
   wa.truncated = G->truncated;
   wa.h = h;
-  wa.blocks = G->batch_blocks;
+  // the batched walk runs no more workgroups than stay resident at once, so it takes
+  // the tiles in their rank order with few climbs through unstamped ancestors
+  wa.blocks = std::min(G->batch_blocks, G->cus * kWalkResidentPerCu);
   wa.ctr = G->ctr;
   wa.finish = false;
   EvalArgs& ea = L.ea;
@@ -1608,6 +1611,10 @@ pirrt_graph* new_graph(const pirrt_config* cfg, int* rc_out) {
     g_create_error = "hipSetDevice failed";
     *rc_out = PIRRT_EDEVICE;
     return nullptr;
+  }
+  if (hipDeviceGetAttribute(&G->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || G->cus < 1) {
+    (void)hipGetLastError();
+    G->cus = 256;
   }
   bool ok = dalloc(G->A, &G->info, 1) && dalloc(G->A, &G->dflag, 1) && dalloc(G->A, &G->dcount, 3) && dalloc(G->A, &G->dhops, 1) &&
             dalloc(G->A, &G->ctl, 1);

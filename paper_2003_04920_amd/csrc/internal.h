@@ -172,6 +172,9 @@ struct WalkArgs {
   int blocks;              // batches: workgroups of the grid-stride launch
 };
 void launch_eval_walk(const WalkArgs& a, hipStream_t s);
+// Workgroups of the batched walk resident on one compute unit (256 threads and 16 KB
+// of LDS each: 8 waves per SIMD).
+constexpr int kWalkResidentPerCu = 8;
 
 // ---- host_replan.hip ----
 // One Replan of a small graph on the host, on slot-ordered host copies (see the file).
