@@ -208,8 +208,9 @@ __global__ void __launch_bounds__(kWgThreads) k_bfs_tail(int32_t j0, int32_t tai
 // workgroup, 4 waves per SIMD; more waves in flight meet more ancestors not yet
 // stamped, and the 1M-vertex walk gets slower with 6 or 8); batches keep the vertex
 // only and read its cost again in the fold (16 KB, 8 waves per SIMD: their deep 2D
-// and 3D trees are bound by the latency of long climbs).  A walk longer than n hops can only be a parent cycle away from the
-// root; its vertices are unreachable and get +inf.
+// and 3D trees are bound by the latency of long climbs).  A walk longer than n hops
+// can only be a parent cycle away from the root; its vertices are unreachable and get
+// +inf.
 //
 // kTrunc (single graphs): the truncated Evaluate.  A vertex is visited only when its
 // parent is the root or a visited vertex with fl(g + h) < G0, G0 being the problem's
